@@ -1,0 +1,155 @@
+/*
+ * nsim_ev.h -- C ABI of the MI355X DVS event generator (libnsim_ev.so).
+ *
+ * Operation (paper Sec. 2, event-camera simulation paragraph; Fig. 3
+ * caption): "process a new intensity frame, trigger events based on the
+ * contrast threshold model, update the internal pixel states, and output the
+ * event stream".  Each pixel keeps the level of its last triggered event;
+ * events are tuples (t, x, y, p) with t an integer number of microseconds and
+ * p = +1 / -1 (Sec. 1, event tuple); every frame yields a variable number of
+ * events (Sec. 2, kernel paragraph).
+ *
+ * The model computed, per pixel and frame interval (t_prev, t]:
+ *   L   = ln(I + log_eps)                 (or L = I with NSIM_INPUT_LOG)
+ *   R   = L_init + (n_up*C_pos - n_down*C_neg)   (lattice reference level)
+ *   up crossings while L >= R + C_pos, down crossings while L <= R - C_neg;
+ *   crossing time tau = t_prev + (level - L_prev)/(L - L_prev) * (t - t_prev),
+ *   timestamp ceil(tau) microseconds; a crossing is emitted iff the pixel has
+ *   no earlier emitted event or t - t_last >= refractory_us; suppressed
+ *   crossings still move R.  The first frame of a stream only initialises.
+ *   Output order: (t, y, x), ties in generation order.
+ * All decisions and timestamps equal those of an FP64 evaluation of this
+ * model: the kernels take FP32 shortcuts only where an error bound proves
+ * the FP64 result, and re-evaluate in FP64 otherwise.
+ *
+ * Memory: every pointer marked "device" is HIP device memory; "host" is
+ * ordinary host memory.  The library owns its state, scratch and event
+ * queue; callers own frames and drain destinations.  All work is enqueued on
+ * the stream given at creation (a hipStream_t passed as void*; NULL is the
+ * null stream).  A handle is not thread-safe and belongs to one stream.
+ *
+ * Errors: every call returns NSIM_OK (0) or a negative code;
+ * nsim_ev_last_error() gives the message of the handle's last failure.
+ */
+#ifndef NSIM_EV_H
+#define NSIM_EV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NSIM_OK 0
+#define NSIM_EINVAL (-1)    /* bad argument; nothing was enqueued */
+#define NSIM_ENOMEM (-2)    /* device or host allocation failed */
+#define NSIM_EOVERFLOW (-3) /* a step's events did not fit; see nsim_ev_step */
+#define NSIM_EHIP (-4)      /* a HIP runtime call failed */
+#define NSIM_ESTATE (-5)    /* handle unusable (internal error) */
+
+/* config.flags */
+#define NSIM_INPUT_LOG 0x1u  /* frames hold log intensity L, not I */
+#define NSIM_FORCE_FP64 0x2u /* verification mode: evaluate every candidate
+                                crossing in FP64 (same results, slower) */
+
+typedef struct nsim_ev_config {
+    int32_t width;   /* 1 .. 65535 */
+    int32_t height;  /* 1 .. 65535, width*height < 2^31 */
+    float c_pos;     /* scalar thresholds, used when the maps are NULL; > 0 */
+    float c_neg;
+    const float* c_pos_map; /* device [height*width] row-major, or NULL;
+                               copied at creation; every entry > 0 */
+    const float* c_neg_map;
+    double log_eps;          /* eps in ln(I + eps); ignored for log input */
+    int64_t refractory_us;   /* 0 disables; at most 2^30 */
+    int64_t capacity_events; /* events the queue holds until drained; also
+                                the most one internal launch may produce */
+    uint32_t flags;          /* NSIM_INPUT_LOG | NSIM_FORCE_FP64 */
+    int32_t max_frames_per_launch; /* 0 = automatic; else 1 .. 256 */
+} nsim_ev_config;
+
+typedef struct nsim_ev nsim_ev_t;
+
+/* Create a stream.  Allocates state (about 28 B per pixel), scratch and the
+ * event queue (13 B per event of capacity plus 16 B of sort scratch).
+ * Returns NSIM_EINVAL for a bad config (out is set to NULL). */
+int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out);
+
+/* Enqueue K frames (device, [K][height][width] float32, caller-owned, valid
+ * until the stream has executed the step) with their timestamps (host,
+ * int64 microseconds [K], strictly increasing across all calls, gaps < 2^30).
+ * The very first frame of the stream (or after nsim_ev_reset) only
+ * initialises the pixel state.  Asynchronous: no host synchronisation.
+ * Intensities must be finite with I + log_eps > 0.
+ * All-or-nothing: if a step's events would overflow the queue, its state is
+ * not committed, this and every later step become no-ops, and the next
+ * nsim_ev_sync / nsim_ev_drain reports NSIM_EOVERFLOW once; the caller then
+ * drains and re-issues frames after nsim_ev_committed_time(). */
+int nsim_ev_step(nsim_ev_t* h, const float* frames, const int64_t* t_us,
+                 int32_t K);
+
+/* Same as nsim_ev_step for a handle created with NSIM_INPUT_LOG: frames hold
+ * log intensity.  Returns NSIM_EINVAL on a handle without that flag. */
+int nsim_ev_step_log(nsim_ev_t* h, const float* log_frames,
+                     const int64_t* t_us, int32_t K);
+
+/* Synchronise the stream and copy up to `cap` queued events, in output
+ * order, to caller-owned device arrays (t: int64 microseconds, x, y: uint16,
+ * p: int8 +1/-1).  *n_out (host) receives the number copied; the rest stay
+ * queued.  Returns the sticky error of a failed step, if any (events that
+ * were committed before it are still copied). */
+int nsim_ev_drain(nsim_ev_t* h, int64_t* t, uint16_t* x, uint16_t* y,
+                  int8_t* p, int64_t cap, int64_t* n_out);
+
+/* Synchronise the stream; returns the sticky error, if any. */
+int nsim_ev_sync(nsim_ev_t* h);
+
+/* Synchronise and report the number of queued events (host *n). */
+int nsim_ev_pending(nsim_ev_t* h, int64_t* n);
+
+/* Synchronise and report the timestamp of the last committed frame (host). */
+int nsim_ev_committed_time(nsim_ev_t* h, int64_t* t_us);
+
+/* Drop queued events and pixel state; the next step starts a new stream. */
+int nsim_ev_reset(nsim_ev_t* h);
+
+/* Synchronise, free everything.  Accepts NULL. */
+int nsim_ev_destroy(nsim_ev_t* h);
+
+/* Message of the last failure on this handle ("" if none). */
+const char* nsim_ev_last_error(const nsim_ev_t* h);
+
+/* Checkpoint: size of the serialised pixel state, and copies of it to/from
+ * a caller-owned device buffer.  The state covers the committed frame time,
+ * per-pixel levels, counters, previous sample and refractory time; it does
+ * not cover queued events.  set_state requires a handle with the same
+ * width, height and flags. */
+int64_t nsim_ev_state_bytes(const nsim_ev_t* h);
+int nsim_ev_get_state(nsim_ev_t* h, void* dev_buf, int64_t bytes);
+int nsim_ev_set_state(nsim_ev_t* h, const void* dev_buf, int64_t bytes);
+
+/* Kernel timing and counters.  Profiling records HIP events around the
+ * fused step kernel on the handle's stream. */
+typedef struct nsim_ev_stats {
+    int64_t step_launches;     /* fused step-kernel launches */
+    double step_kernel_ms;     /* their total duration (profiling on) */
+    int64_t step_timed;        /* launches included in step_kernel_ms */
+    int64_t pixel_updates;     /* pixel x frame intervals processed */
+    int64_t events;            /* events committed to the queue */
+    int64_t fp64_evaluations;  /* candidate crossings re-evaluated in FP64 */
+    int64_t sort_passes;       /* radix passes launched */
+    int64_t packed_event_bytes;/* bytes of packed events written by the step kernel */
+} nsim_ev_stats;
+
+int nsim_ev_set_profiling(nsim_ev_t* h, int on);
+int nsim_ev_get_stats(nsim_ev_t* h, nsim_ev_stats* out);
+
+/* Diagnostic: out[i] = the step kernel's FP32 base-2 logarithm of x[i]
+ * (device arrays of n floats), so its error bound can be checked. */
+int nsim_diag_fast_log2(const float* x, float* out, int64_t n, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NSIM_EV_H */

@@ -1,0 +1,155 @@
+// Internal layout shared by the runtime (ev_runtime.cpp) and the kernels
+// (ev_kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nsim {
+
+constexpr int kWave = 64;
+constexpr int kStepThreads = 256;            // 4 waves, one pixel per lane
+constexpr int kStepWaves = kStepThreads / kWave;
+constexpr int kStepLdsEntries = 1200;        // staged events per wave (8 B each)
+constexpr int kMaxFramesPerLaunch = 256;
+constexpr int kSortThreads = 256;
+constexpr int kSortItems = 16;               // items per thread per tile
+constexpr int kSortTile = kSortThreads * kSortItems;
+constexpr int kDigitBits = 8;
+constexpr int kDigits = 1 << kDigitBits;
+constexpr int kMaxPasses = 4;
+constexpr uint32_t kKeyHole = 0xFFFFFFFFu;   // a suppressed crossing in LDS
+constexpr int32_t kTlastNone = -(1 << 30);   // no emitted event that matters
+
+// Device-resident stream header.  Written by kernels, read by the host only
+// after a stream synchronisation.
+struct alignas(64) Header {
+    int32_t cur;          // which ping-pong state buffer holds committed state
+    int32_t status;       // 0, or a sticky NSIM_E* code
+    int64_t n_step;       // events produced by the last step launch
+    int64_t head;         // queue read position (monotonic)
+    int64_t tail;         // queue write position (monotonic)
+    int64_t t_prev;       // timestamp of the last committed frame
+    int64_t dropped_t;    // first frame time of the first dropped step
+    int64_t events_total; // committed events
+    int64_t fp64_evals;   // candidate crossings evaluated in FP64
+    int32_t internal_err; // 1: a bounded wait gave up
+    int32_t pad;
+};
+
+// Arguments of the fused step kernel.  Frame times travel by value.
+struct StepArgs {
+    const float* frames;   // [K][P]
+    int32_t K;
+    int32_t P;
+    int32_t width;
+    int32_t ntiles;
+    const double* L_init;  // [P]
+    int2* nud[2];          // (n_up, n_down) [P], ping-pong
+    float* prev[2];        // previous sample (I or L) [P], ping-pong
+    int32_t* tlast[2];     // last emitted time relative to the last frame
+    const float* c_pos_map;
+    const float* c_neg_map;
+    float c_pos;
+    float c_neg;
+    double log_eps;
+    float log_eps_f;
+    int32_t tref;
+    int64_t T0;            // absolute time of the frame before frames[0]
+    float eT;              // absolute-time rounding allowance of FP64 tau
+    float pad0;
+    uint32_t* out_key;     // packed events: key = t - T0
+    uint32_t* out_val;     //                val = pixel << 1 | (p > 0)
+    int64_t out_cap;
+    Header* hdr;
+    uint64_t* tile_status; // [ntiles]
+    uint32_t* tile_ctr;
+    uint32_t epoch;
+    uint32_t flags;
+    int32_t toff[kMaxFramesPerLaunch];  // frame k time minus T0
+};
+
+struct InitArgs {
+    const float* frame;
+    int32_t P;
+    uint32_t flags;
+    double log_eps;
+    double* L_init;
+    int2* nud[2];
+    float* prev[2];
+    int32_t* tlast[2];
+    Header* hdr;
+    int64_t t0;
+};
+
+struct HistArgs {
+    const uint32_t* keys;
+    Header* hdr;
+    int64_t scratch_cap;
+    int64_t qcap;
+    int32_t npass;
+    uint32_t* hist;          // [kMaxPasses][kDigits]
+    uint32_t* status;        // [kMaxPasses][max_tiles][kDigits]
+    int64_t max_tiles;
+    uint32_t* pass_ctr;      // [kMaxPasses]
+};
+
+struct PassArgs {
+    const uint32_t* kin;
+    const uint32_t* vin;
+    uint32_t* kout;
+    uint32_t* vout;
+    int64_t* t_out;          // final pass: queue ring
+    uint16_t* x_out;
+    uint16_t* y_out;
+    int8_t* p_out;
+    int64_t qcap;
+    int32_t final_pass;
+    int32_t shift;
+    int32_t bits;
+    int32_t width;
+    int64_t T0;
+    const uint32_t* hist;    // this pass's digit counts
+    uint32_t* status;        // this pass's [max_tiles][kDigits]
+    uint32_t* tile_ctr;
+    Header* hdr;
+    int64_t scratch_cap;
+};
+
+struct CommitArgs {
+    Header* hdr;
+    int64_t scratch_cap;
+    int64_t qcap;
+    int64_t t_last;          // absolute time of the step's last frame
+    int64_t t_first;         // absolute time of the step's first frame
+    int64_t pixel_updates;
+    uint32_t* hist;
+    uint32_t* step_tile_ctr;
+};
+
+struct StateCopyArgs {
+    Header* hdr;
+    int32_t P;
+    int32_t to_buffer;       // 1: state -> buffer, 0: buffer -> state
+    double* L_init;
+    int2* nud[2];
+    float* prev[2];
+    int32_t* tlast[2];
+    uint8_t* buf;
+};
+
+// Launchers (ev_kernels.hip).  Each returns the hipError_t of the launch.
+hipError_t launch_init(const InitArgs& a, hipStream_t s);
+hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
+                       hipStream_t s);
+hipError_t launch_hist(const HistArgs& a, hipStream_t s);
+hipError_t launch_pass(const PassArgs& a, hipStream_t s);
+hipError_t launch_commit(const CommitArgs& a, hipStream_t s);
+hipError_t launch_reset_header(Header* hdr, uint32_t* hist,
+                               uint32_t* step_tile_ctr, hipStream_t s);
+hipError_t launch_clear_status(Header* hdr, hipStream_t s);
+hipError_t launch_state_copy(const StateCopyArgs& a, hipStream_t s);
+hipError_t launch_fast_log2(const float* x, float* out, int64_t n,
+                            hipStream_t s);
+
+}  // namespace nsim

@@ -1,0 +1,329 @@
+"""GPU parity of the HIP event path against the FP64 oracle (MI355X).
+
+Every test drives the library through its C ABI (via the thin binding) on
+seeded synthetic inputs and compares with the oracle run on the very same
+frames: exact equality is expected; the comparison protocol's tolerance is
+the pass bar.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+import oracle  # noqa: E402
+from paper_2602_15018_amd import scene  # noqa: E402
+from tests.parity import as_numpy, compare, exact_equal, is_sorted_tyx  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda", 0)
+
+
+def _sim(W, H, **kw):
+    from paper_2602_15018_amd.ev import EventSim
+    return EventSim(W, H, **kw)
+
+
+def gpu_run(frames, t, c_pos=0.2, c_neg=0.2, log_eps=1e-3, refractory_us=0,
+            input_is_log=False, chunks=None, capacity=1 << 22, force_fp64=False,
+            max_frames=0):
+    dev = _dev()
+    fr = torch.as_tensor(frames).to(dev) if not torch.is_tensor(frames) else frames.to(dev)
+    F, H, W = fr.shape
+    kw = dict(log_eps=log_eps, refractory_us=refractory_us,
+              input_is_log=input_is_log, capacity_events=capacity,
+              force_fp64=force_fp64, max_frames_per_launch=max_frames)
+    if np.ndim(c_pos) == 0:
+        sim = _sim(W, H, c_pos=float(c_pos), c_neg=float(c_neg), **kw)
+    else:
+        sim = _sim(W, H, c_pos_map=c_pos, c_neg_map=c_neg, **kw)
+    t = np.asarray(t, np.int64)
+    bounds = [0, F] if not chunks else list(chunks)
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        if b > a:
+            sim.step(fr[a:b], t[a:b])
+    out = as_numpy(sim.drain())
+    st = sim.stats()
+    sim.close()
+    return out, st
+
+
+def check_parity(frames_np, t, W, **kw):
+    okw = {k: v for k, v in kw.items() if k in (
+        "c_pos", "c_neg", "log_eps", "refractory_us", "input_is_log")}
+    ref = oracle.run(frames_np, t, want_fragile=True, **okw)
+    got, st = gpu_run(frames_np, t, **kw)
+    rep = compare(got, ref["events"], W, frame_times=np.asarray(t),
+                  fragile=ref["fragile"])
+    return rep, got, ref, st
+
+
+# ---------------------------------------------------------------- primitives
+
+def test_fast_log2_error_bound():
+    """The fast path's FP32 log2 stays within the error the guard band
+    assumes: |log2f(x) - log2(x)| <= 2^-22 (1 + |log2 x|)."""
+    from paper_2602_15018_amd.ev import fast_log2
+    dev = _dev()
+    rng = np.random.default_rng(0)
+    xs = np.concatenate([
+        rng.uniform(1e-3, 1.001, 2_000_000),
+        np.exp(rng.uniform(-40, 40, 1_000_000)),
+        1.0 + rng.uniform(-1e-3, 1e-3, 500_000),
+    ]).astype(np.float32)
+    got = fast_log2(torch.from_numpy(xs).to(dev)).cpu().numpy().astype(np.float64)
+    want = np.log2(xs.astype(np.float64))
+    err = np.abs(got - want)
+    bound = 2.0 ** -22 * (1.0 + np.abs(want))
+    assert np.all(err <= bound), float(np.max(err / bound))
+
+
+# ----------------------------------------------------------- closed forms
+
+def test_handworked_golden_gpu():
+    g = json.load(open(os.path.join(GOLDEN, "handworked_single_pixel.json")))
+    fr = np.asarray(g["log_frames"], np.float32).reshape(-1, 1, 1)
+    for key, tref in (("no_refractory", 0), ("refractory_600", 600)):
+        (t, x, y, p), _ = gpu_run(fr, g["t_us"], c_pos=g["c_pos"],
+                                  c_neg=g["c_neg"], input_is_log=True,
+                                  refractory_us=tref)
+        assert t.tolist() == g[key]["t"]
+        assert p.tolist() == g[key]["p"]
+
+
+RAMP_SLOPES = [2.0561e-3, -1.1014e-3, 0.5065e-3, -2.7732e-3, 1.8134e-3]
+RAMP_START = [-4.5, 20.0, -4.5, 20.0, -4.5]
+
+
+@pytest.mark.parametrize("as_log", [False, True])
+@pytest.mark.parametrize("dt,F", [(500, 13), (1000, 8), (8000, 2)])
+def test_exp_ramp_gpu(as_log, dt, F):
+    C = float(np.float32(0.2))
+    t0 = 1_000_000
+    t = t0 + dt * np.arange(F, dtype=np.int64)
+    fr = scene.exp_ramp_frames(RAMP_SLOPES, t, t0, RAMP_START, as_log=as_log)
+    (tt, x, y, p), _ = gpu_run(fr, t, input_is_log=as_log)
+    for i, a in enumerate(RAMP_SLOPES):
+        n = math.floor(abs(a) * dt * (F - 1) / C)
+        want = np.ceil(t0 + np.arange(1, n + 1) * (C / abs(a))).astype(np.int64)
+        np.testing.assert_array_equal(tt[x == i], want)
+        assert np.all(p[x == i] == (1 if a > 0 else -1))
+
+
+# ------------------------------------------------------------------ parity
+
+@pytest.mark.parametrize("seed,F,dt,tref,mismatch", [
+    (11, 6, 1000, 0, False), (12, 6, 1000, 100, True), (13, 8, 500, 250, True),
+    (14, 3, 8000, 100, True), (15, 10, 333, 0, True)])
+def test_parity_random_8x8(seed, F, dt, tref, mismatch):
+    rng = np.random.default_rng(seed)
+    fr = scene.random_frames(seed, F, 8, 8)
+    if mismatch:
+        cp = rng.uniform(0.05, 0.5, size=(8, 8)).astype(np.float32)
+        cn = rng.uniform(0.05, 0.5, size=(8, 8)).astype(np.float32)
+    else:
+        cp = cn = np.float32(0.2)
+    t = 17 + dt * np.arange(F)
+    rep, *_ = check_parity(fr, t, 8, c_pos=cp, c_neg=cn, refractory_us=tref)
+    assert rep["exact"], rep
+
+
+def test_parity_log_input_large_jumps():
+    """Log input with jumps of tens of thresholds per frame: exercises the
+    FP64 count path, multi-crossing frames and the staging overflow rerun."""
+    rng = np.random.default_rng(21)
+    H, W, F = 9, 70, 12
+    L = np.cumsum(rng.normal(0, 6.0, size=(F, H, W)), axis=0).astype(np.float32)
+    cp = rng.uniform(0.05, 0.5, size=(H, W)).astype(np.float32)
+    cn = rng.uniform(0.05, 0.5, size=(H, W)).astype(np.float32)
+    t = 1000 * np.arange(F)
+    rep, got, ref, st = check_parity(L, t, W, c_pos=cp, c_neg=cn,
+                                     input_is_log=True, refractory_us=30)
+    assert rep["n_oracle"] > 20000
+    assert rep["exact"], rep
+
+
+def test_parity_dvs_workload_full():
+    """The 240x180, 200-frame workload in full (uniform thresholds)."""
+    w = scene.WORKLOADS["dvs240x180_200f_1000fps"]
+    fr = scene.render_workload(w, device=_dev())
+    t = scene.frame_times(w)
+    rep, got, ref, st = check_parity(fr.cpu().numpy(), t, w.width, c_pos=0.2,
+                                     c_neg=0.2)
+    print("dvs full:", {k: rep[k] for k in ("n_gpu", "n_oracle", "exact")},
+          "fp64 evals", st["fp64_evaluations"], flush=True)
+    assert rep["ok"], rep
+
+
+def test_parity_vga_crop_mismatch_refractory():
+    w = scene.WORKLOADS["vga640x480_1000f_1000fps"]
+    H, W, F = 120, 200, 90
+    fr = scene.render_workload(w, 0, F, device=_dev(), height=H, width=W)
+    t = scene.frame_times(w, 0, F)
+    cp, cn = scene.threshold_maps(w, H, W)
+    rep, got, ref, st = check_parity(fr.cpu().numpy(), t, W, c_pos=cp,
+                                     c_neg=cn, refractory_us=100)
+    print("vga crop:", {k: rep[k] for k in ("n_gpu", "n_oracle", "exact")},
+          "fp64 evals", st["fp64_evaluations"], flush=True)
+    assert rep["ok"], rep
+
+
+def test_force_fp64_identical():
+    """Re-evaluating every candidate in FP64 changes nothing: the FP32 fast
+    path only decides what its error bound proves."""
+    w = scene.WORKLOADS["hd1280x720_2000f_2000fps_agile"]
+    H, W, F = 96, 256, 60
+    fr = scene.render_workload(w, 0, F, device=_dev(), height=H, width=W)
+    t = scene.frame_times(w, 0, F)
+    cp, cn = scene.threshold_maps(w, H, W)
+    a, sa = gpu_run(fr, t, c_pos=cp, c_neg=cn, refractory_us=100)
+    b, sb = gpu_run(fr, t, c_pos=cp, c_neg=cn, refractory_us=100,
+                    force_fp64=True)
+    assert len(a[0]) > 1000
+    assert sb["fp64_evaluations"] > sa["fp64_evaluations"]
+    assert exact_equal(a, b)
+
+
+@pytest.mark.parametrize("chunks", [[0, 1, 2, 3, 50], [0, 7, 14, 21, 28, 35, 42, 49, 50],
+                                    [0, 50]])
+def test_chunking_invariance_gpu(chunks):
+    w = scene.WORKLOADS["vga640x480_1000f_1000fps"]
+    H, W, F = 50, 77, 50
+    fr = scene.render_workload(w, 0, F, device=_dev(), height=H, width=W)
+    t = scene.frame_times(w, 0, F)
+    cp, cn = scene.threshold_maps(w, H, W)
+    ref, _ = gpu_run(fr, t, c_pos=cp, c_neg=cn, refractory_us=100)
+    got, _ = gpu_run(fr, t, c_pos=cp, c_neg=cn, refractory_us=100, chunks=chunks)
+    assert exact_equal(ref, got)
+    one, _ = gpu_run(fr, t, c_pos=cp, c_neg=cn, refractory_us=100, max_frames=1)
+    assert exact_equal(ref, one)
+
+
+def test_determinism_and_sortedness():
+    w = scene.WORKLOADS["dvs240x180_200f_1000fps"]
+    fr = scene.render_workload(w, 0, 80, device=_dev())
+    t = scene.frame_times(w, 0, 80)
+    a, _ = gpu_run(fr, t)
+    b, _ = gpu_run(fr, t)
+    assert len(a[0]) > 10000
+    assert exact_equal(a, b)
+    assert is_sorted_tyx(a[0], a[1], a[2])
+
+
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 300), (37, 29), (3, 257)])
+def test_ragged_sizes(H, W):
+    fr = scene.random_frames(3, 9, H, W)
+    t = 5 + 1000 * np.arange(9)
+    rng = np.random.default_rng(3)
+    cp = rng.uniform(0.05, 0.5, size=(H, W)).astype(np.float32)
+    cn = rng.uniform(0.05, 0.5, size=(H, W)).astype(np.float32)
+    rep, *_ = check_parity(fr, t, W, c_pos=cp, c_neg=cn, refractory_us=40)
+    assert rep["exact"], rep
+
+
+def test_static_scene_gpu():
+    f0 = np.random.default_rng(1).uniform(0.01, 1, size=(31, 45)).astype(np.float32)
+    fr = np.repeat(f0[None], 12, axis=0)
+    (t, x, y, p), _ = gpu_run(fr, 1000 * np.arange(12))
+    assert len(t) == 0
+
+
+def test_inversion_gpu():
+    rng = np.random.default_rng(7)
+    H, W, F = 16, 40, 25
+    L = np.cumsum(rng.normal(0, 0.3, size=(F, H, W)), axis=0).astype(np.float32)
+    cp = rng.uniform(0.1, 0.4, size=(H, W)).astype(np.float32)
+    cn = rng.uniform(0.1, 0.4, size=(H, W)).astype(np.float32)
+    t = 3 + 800 * np.arange(F)
+    a, _ = gpu_run(L, t, c_pos=cp, c_neg=cn, input_is_log=True, refractory_us=150)
+    b, _ = gpu_run(-L, t, c_pos=cn, c_neg=cp, input_is_log=True, refractory_us=150)
+    assert len(a[0]) > 500
+    for i in range(3):
+        np.testing.assert_array_equal(a[i], b[i])
+    np.testing.assert_array_equal(a[3], -b[3])
+
+
+# ------------------------------------------------------------- ABI behaviour
+
+def test_overflow_all_or_nothing_and_reissue():
+    from paper_2602_15018_amd.ev import EventSim, NsimError
+    dev = _dev()
+    w = scene.WORKLOADS["dvs240x180_200f_1000fps"]
+    H, W, F = 60, 80, 40
+    fr = scene.render_workload(w, 0, F, device=dev, height=H, width=W)
+    t = scene.frame_times(w, 0, F)
+    ref, _ = gpu_run(fr, t)
+    n_total = len(ref[0])
+    assert n_total > 2000
+    cap = n_total // 3
+    sim = EventSim(W, H, capacity_events=cap, max_frames_per_launch=4)
+    got = [[], [], [], []]
+    k = 0
+    while k < F:
+        sim.step(fr[k:k + 4], t[k:k + 4])
+        k += 4
+        try:
+            sim.sync()
+        except NsimError as e:
+            assert e.code == -3
+            k = int(np.searchsorted(t, sim.committed_time(), "right"))
+            part = as_numpy(sim.drain())
+            for i in range(4):
+                got[i].append(part[i])
+            continue
+    part = as_numpy(sim.drain())
+    for i in range(4):
+        got[i].append(part[i])
+    sim.close()
+    got = tuple(np.concatenate(g) for g in got)
+    assert exact_equal(ref, got)
+
+
+def test_checkpoint_resume():
+    from paper_2602_15018_amd.ev import EventSim
+    dev = _dev()
+    w = scene.WORKLOADS["vga640x480_1000f_1000fps"]
+    H, W, F = 40, 64, 30
+    fr = scene.render_workload(w, 0, F, device=dev, height=H, width=W)
+    t = scene.frame_times(w, 0, F)
+    cp, cn = scene.threshold_maps(w, H, W)
+    ref, _ = gpu_run(fr, t, c_pos=cp, c_neg=cn, refractory_us=100)
+    a = EventSim(W, H, c_pos_map=cp, c_neg_map=cn, refractory_us=100)
+    a.step(fr[:13], t[:13])
+    first = as_numpy(a.drain())
+    st = a.get_state()
+    a.close()
+    b = EventSim(W, H, c_pos_map=cp, c_neg_map=cn, refractory_us=100)
+    b.set_state(st)
+    b.step(fr[13:], t[13:])
+    second = as_numpy(b.drain())
+    b.close()
+    got = tuple(np.concatenate([u, v]) for u, v in zip(first, second))
+    assert exact_equal(ref, got)
+
+
+def test_invalid_arguments():
+    from paper_2602_15018_amd.ev import EventSim, NsimError
+    dev = _dev()
+    with pytest.raises(NsimError):
+        EventSim(0, 4)
+    with pytest.raises(NsimError):
+        EventSim(4, 4, capacity_events=0)
+    sim = EventSim(4, 4)
+    fr = torch.full((3, 4, 4), 0.5, device=dev)
+    with pytest.raises(NsimError):
+        sim.step(fr, [0, 10, 10])
+    sim.step(fr[:2], [0, 10])
+    with pytest.raises(NsimError):
+        sim.step(fr[:1], [10])
+    sim.close()
