@@ -43,6 +43,10 @@ FRAME_B = 4
 PACKED_EVENT_B = 8
 
 
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -107,8 +111,10 @@ def main():
     t = scene.frame_times(w, 0, F)
     cp, cn = scene.threshold_maps(w)
     frames = torch.empty((F, w.height, w.width), dtype=torch.float32, device=dev)
+    log("rendering %d frames %dx%d" % (F, w.width, w.height))
     scene.render_workload(w, 0, F, device=dev, out=frames)
     torch.cuda.synchronize()
+    log("frames resident (%.2f GB)" % (frames.numel() * 4 / 1e9))
 
     est_events = int(0.09 * w.pixels * (F - 1)) + (1 << 20)
     cap = min(est_events, (1 << 30) - 1)
@@ -130,6 +136,7 @@ def main():
     n_ev = 0
     for _ in range(args.warmup):
         n_ev = one_step()
+        log("warmup step: %d events" % n_ev)
     base = sim.stats()
     sim.set_profiling(True)
     torch.cuda.synchronize()
@@ -141,6 +148,7 @@ def main():
     elapsed = time.perf_counter() - t0
     st = sim.stats()
     sim.close()
+    log("timed %d steps in %.3f s" % (args.steps, elapsed))
 
     ms_per_step = elapsed * 1e3 / args.steps
     pu_step = w.pixels * (F - 1)
@@ -192,6 +200,7 @@ def main():
         },
     }
     if not args.no_cpu:
+        log("CPU oracle sample (%d frame intervals)" % args.cpu_sample_frames)
         result["cpu_baseline"] = cpu_baseline(frames, t, cp, cn, w,
                                               args.cpu_sample_frames)
     print(json.dumps(result), flush=True)

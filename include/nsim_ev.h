@@ -78,7 +78,7 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out);
 
 /* Enqueue K frames (device, [K][height][width] float32, caller-owned, valid
  * until the stream has executed the step) with their timestamps (host,
- * int64 microseconds [K], strictly increasing across all calls, gaps < 2^30).
+ * int64 microseconds [K], strictly increasing across all calls, gaps < 2^25).
  * The very first frame of the stream (or after nsim_ev_reset) only
  * initialises the pixel state.  Asynchronous: no host synchronisation.
  * Intensities must be finite with I + log_eps > 0.
@@ -140,6 +140,14 @@ typedef struct nsim_ev_stats {
     int64_t fp64_evaluations;  /* candidate crossings re-evaluated in FP64 */
     int64_t sort_passes;       /* radix passes launched */
     int64_t packed_event_bytes;/* bytes of packed events written by the step kernel */
+    int64_t diag[8];           /* diagnostic counters of the step kernel:
+                                  0 FP64 count evaluations, 1 FP64 timestamp
+                                  evaluations, 2 waves regenerated after a
+                                  staging overflow, 3 wave-frames with a
+                                  candidate, 4 wave-frames with an FP64
+                                  count, 5 wave-level event-loop iterations,
+                                  6 wave-level FP64 timestamp branches,
+                                  7 wave-frames with a crossing */
 } nsim_ev_stats;
 
 int nsim_ev_set_profiling(nsim_ev_t* h, int on);

@@ -10,16 +10,18 @@ namespace nsim {
 constexpr int kWave = 64;
 constexpr int kStepThreads = 256;            // 4 waves, one pixel per lane
 constexpr int kStepWaves = kStepThreads / kWave;
-constexpr int kStepLdsEntries = 1200;        // staged events per wave (8 B each)
+constexpr int kStepLdsEntries = 2000;        // staged events per wave (4 B each)
+constexpr int kChunk = 8;                     // frames prefetched per chunk
 constexpr int kMaxFramesPerLaunch = 256;
+constexpr int kAutoFramesPerLaunch = 64;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;               // items per thread per tile
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kDigitBits = 8;
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kMaxPasses = 4;
-constexpr uint32_t kKeyHole = 0xFFFFFFFFu;   // a suppressed crossing in LDS
 constexpr int32_t kTlastNone = -(1 << 30);   // no emitted event that matters
+constexpr int64_t kMaxLaunchSpan = (int64_t(1) << 25) - 2;  // us per launch
 
 // Device-resident stream header.  Written by kernels, read by the host only
 // after a stream synchronisation.
@@ -35,15 +37,27 @@ struct alignas(64) Header {
     int64_t fp64_evals;   // candidate crossings evaluated in FP64
     int32_t internal_err; // 1: a bounded wait gave up
     int32_t pad;
+    int64_t alloc;        // packed-event slots handed out in this launch
+    // diagnostic counters (summed over launches):
+    // 0 FP64 count evaluations (lanes), 1 FP64 timestamp evaluations
+    // (events), 2 waves regenerated after staging overflow, 3 wave-frames
+    // with a candidate crossing, 4 wave-frames running the FP64 count,
+    // 5 event-loop iterations (wave level), 6 wave-level FP64 timestamp
+    // branches, 7 wave-frames with at least one crossing
+    int64_t diag[8];
 };
 
-// Arguments of the fused step kernel.  Frame times travel by value.
+// Arguments of the fused step kernel.  Frame times travel by value.  Each
+// wave of 64 pixels is independent: it owns the staging segment
+// [wave * kStepLdsEntries, +kStepLdsEntries); a wave whose events outgrow its
+// LDS staging takes a segment from the overflow pool behind the fixed
+// segments with one atomic.  (base, count) go to seg_base / seg_count.
 struct StepArgs {
     const float* frames;   // [K][P]
     int32_t K;
     int32_t P;
     int32_t width;
-    int32_t ntiles;
+    int32_t nwaves;        // ceil(P / 64)
     const double* L_init;  // [P]
     int2* nud[2];          // (n_up, n_down) [P], ping-pong
     float* prev[2];        // previous sample (I or L) [P], ping-pong
@@ -58,15 +72,44 @@ struct StepArgs {
     int64_t T0;            // absolute time of the frame before frames[0]
     float eT;              // absolute-time rounding allowance of FP64 tau
     float pad0;
-    uint32_t* out_key;     // packed events: key = t - T0
-    uint32_t* out_val;     //                val = pixel << 1 | (p > 0)
-    int64_t out_cap;
+    uint32_t* out_key;     // staging: key = t - T0
+    uint32_t* out_val;     //          val = pixel << 1 | (p > 0)
+    int64_t out_cap;       // staging entries: fixed segments + overflow pool
+    int64_t* seg_base;     // [nwaves] first staging entry of the wave
+    uint32_t* seg_count;   // [nwaves] events of the wave
     Header* hdr;
-    uint64_t* tile_status; // [ntiles]
-    uint32_t* tile_ctr;
-    uint32_t epoch;
     uint32_t flags;
+    uint32_t pad1;
     int32_t toff[kMaxFramesPerLaunch];  // frame k time minus T0
+};
+
+// Exclusive scan of the per-wave event counts (wave order = pixel order).
+struct ScanArgs {
+    const uint32_t* seg_count;
+    uint32_t* pref;
+    int32_t nwaves;
+    Header* hdr;
+};
+
+// Gather the per-wave segments into pixel order, build the digit
+// histograms of every radix pass and clear the passes' look-back words.
+struct GatherArgs {
+    const int64_t* seg_base;
+    const uint32_t* seg_count;
+    const uint32_t* pref;
+    int32_t nwaves;
+    int32_t npass;
+    const uint32_t* skey;    // staging
+    const uint32_t* sval;
+    uint32_t* dkey;          // dense, pixel order
+    uint32_t* dval;
+    Header* hdr;
+    int64_t scratch_cap;
+    int64_t qcap;
+    uint32_t* hist;          // [kMaxPasses][kDigits]
+    uint32_t* status;        // [kMaxPasses][max_tiles][kDigits]
+    int64_t max_tiles;
+    uint32_t* pass_ctr;      // [kMaxPasses]
 };
 
 struct InitArgs {
@@ -80,18 +123,6 @@ struct InitArgs {
     int32_t* tlast[2];
     Header* hdr;
     int64_t t0;
-};
-
-struct HistArgs {
-    const uint32_t* keys;
-    Header* hdr;
-    int64_t scratch_cap;
-    int64_t qcap;
-    int32_t npass;
-    uint32_t* hist;          // [kMaxPasses][kDigits]
-    uint32_t* status;        // [kMaxPasses][max_tiles][kDigits]
-    int64_t max_tiles;
-    uint32_t* pass_ctr;      // [kMaxPasses]
 };
 
 struct PassArgs {
@@ -124,7 +155,6 @@ struct CommitArgs {
     int64_t t_first;         // absolute time of the step's first frame
     int64_t pixel_updates;
     uint32_t* hist;
-    uint32_t* step_tile_ctr;
 };
 
 struct StateCopyArgs {
@@ -142,11 +172,11 @@ struct StateCopyArgs {
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
                        hipStream_t s);
-hipError_t launch_hist(const HistArgs& a, hipStream_t s);
+hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
+hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, hipStream_t s);
 hipError_t launch_commit(const CommitArgs& a, hipStream_t s);
-hipError_t launch_reset_header(Header* hdr, uint32_t* hist,
-                               uint32_t* step_tile_ctr, hipStream_t s);
+hipError_t launch_reset_header(Header* hdr, uint32_t* hist, hipStream_t s);
 hipError_t launch_clear_status(Header* hdr, hipStream_t s);
 hipError_t launch_state_copy(const StateCopyArgs& a, hipStream_t s);
 hipError_t launch_fast_log2(const float* x, float* out, int64_t n,

@@ -10,11 +10,13 @@
 //
 // Pipeline per launch of up to 256 frames:
 //   step_kernel  one lane per pixel walks the frames with its state in
-//                registers; candidate crossings are staged per wave in LDS
-//                in (frame, pixel, k) order; a decoupled look-back over
-//                pixel tiles gives every tile its output offset, so packed
-//                events land in (pixel block, frame, pixel, k) order;
-//   hist_kernel  digit histograms of the packed keys (time offsets);
+//                registers; crossings are staged per wave in LDS in
+//                (frame, pixel, k) order; each wave (64 pixels) is
+//                independent and writes its events to a segment it reserves
+//                with one atomic;
+//   scan_kernel  exclusive scan of the per-wave counts (pixel order);
+//   gather       segments copied into (pixel block, frame, pixel, k) order,
+//                digit histograms of the time-offset keys built on the way;
 //   pass_kernel  stable LSD radix passes on the time offset (onesweep:
 //                single pass per digit with per-digit look-back); the last
 //                pass expands to SoA (t, x, y, p) in the queue ring.  Equal
@@ -37,13 +39,15 @@ namespace nsim {
 
 namespace {
 
-constexpr float kDelta0 = 0x1p-17f;      // absolute part of the guard band
-constexpr float kDeltaRel = 0x1p-19f;    // relative part (times |level|)
-constexpr int kFastMaxCross = 64;        // more crossings: FP64 path
+constexpr int kFastMaxCross = 32;        // longer runs per frame: FP64 replica
 constexpr int kMaxCross = 1 << 20;       // termination bound (finite input)
 constexpr uint32_t kSpinLimit = 1u << 24;
-constexpr double kInvLn2 = 1.4426950408889634073599246810019;
 constexpr uint32_t kAgg = 1u, kInc = 2u;
+constexpr double kG32 = 0x1p-22;         // guard of the FP32 sample tests
+constexpr double kG64 = 0x1p-36;         // guard of the FP64 level tests
+constexpr float kLn2f = 0.693147180559945309f;
+constexpr float kSeriesRel = 0x1p-20f;   // bound of two_atanh on |z| <= 1/4
+constexpr uint32_t kEntryHole = 0xFFFFFFFFu;
 
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
@@ -51,14 +55,20 @@ __device__ __forceinline__ uint64_t lanemask_lt() {
     return (1ull << lane_id()) - 1ull;
 }
 
+// Inclusive scan over the 64 lanes with DPP: shifts within rows of 16, then
+// row broadcasts of lanes 15 and 31 (gfx9 row_bcast controls).
 __device__ __forceinline__ int wave_incl_scan(int v) {
-    const int lane = lane_id();
-#pragma unroll
-    for (int d = 1; d < kWave; d <<= 1) {
-        int t = __shfl_up(v, d, kWave);
-        if (lane >= d) v += t;
-    }
+    v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, true);  // row_shr:1
+    v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, true);  // row_shr:2
+    v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, true);  // row_shr:4
+    v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, true);  // row_shr:8
+    v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false); // row_bcast:15
+    v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false); // row_bcast:31
     return v;
+}
+
+__device__ __forceinline__ int wave_last(int v) {
+    return __builtin_amdgcn_readlane(v, kWave - 1);
 }
 
 __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
@@ -86,9 +96,14 @@ __device__ __forceinline__ void atomic_store_u32(uint32_t* p, uint32_t v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// FP32 base-2 logarithm of the fast path (v_log_f32).
+// FP32 base-2 logarithm (v_log_f32).
 __device__ __forceinline__ float fast_log2(float x) {
     return __builtin_amdgcn_logf(x);
+}
+
+// FP32 reciprocal (v_rcp_f32).
+__device__ __forceinline__ float fast_rcp(float x) {
+    return __builtin_amdgcn_rcpf(x);
 }
 
 // Log intensity in FP64, as the definition computes it.
@@ -98,33 +113,107 @@ __device__ __forceinline__ double log_intensity64(float v, double eps) {
     return log((double)v + eps);
 }
 
-// Per-lane pixel state while a launch walks its frames.
+// 2 atanh(z) = ln((1+z)/(1-z)) for |z| <= 1/4: odd series through z^13,
+// truncation below 3e-10 relative.
+__device__ __forceinline__ float two_atanh_series(float z) {
+    const float u = z * z;
+    float p = 0.076923076923f;           // 1/13
+    p = fmaf(p, u, 0.090909090909f);     // 1/11
+    p = fmaf(p, u, 0.111111111111f);     // 1/9
+    p = fmaf(p, u, 0.142857142857f);     // 1/7
+    p = fmaf(p, u, 0.2f);
+    p = fmaf(p, u, 0.333333333333f);
+    p = fmaf(p, u, 1.0f);
+    return 2.0f * z * p;
+}
+
+// ln(xa / xb) for xa, xb > 0 given diff = xa - xb and sum = xa + xb, with a
+// bound on its relative error (rel) and its absolute error (abs_err).
+struct LnRatio {
+    float v;
+    float rel;
+};
+
+__device__ __forceinline__ LnRatio ln_ratio(float diff, float sum, float xa,
+                                           float xb) {
+    const float z = diff * fast_rcp(sum);
+    LnRatio r;
+    if (fabsf(z) <= 0.25f) {
+        r.v = two_atanh_series(z);
+        r.rel = kSeriesRel;
+    } else {
+        // |ln| >= 2 atanh(1/4) > 0.51: the difference of two logs is well
+        // conditioned; each log2 carries at most 2^-21 (1 + |log2 x|).
+        const float la = fast_log2(xa), lb = fast_log2(xb);
+        r.v = (la - lb) * kLn2f;
+        r.rel = 0x1p-21f * (2.0f + fabsf(la) + fabsf(lb)) * kLn2f /
+                    fabsf(r.v) +
+                0x1p-22f;
+    }
+    return r;
+}
+
+// Per-lane pixel state while a launch walks its frames.  The lattice levels
+// are kept in FP64 in the domain of the samples: for intensity input the
+// levels are X = exp(level) (so a sample crosses when I + eps >= X), for log
+// input the levels themselves.  Moving the reference by one threshold
+// multiplies (adds) the level by a per-pixel step.
 struct Px {
     double L_init;
+    double Xh, Xl;   // first up / down level
+    double Ep, En;   // up / down step of a level
     int nup, ndn;
     int tlast;       // relative to T0 of the launch
     float prev;      // previous sample (I, or L for log input)
-    float Lprev;     // FP32 log of prev in scaled units
     float cp, cn;    // thresholds (FP32 values of the definition)
-    float cps, cns;  // thresholds in scaled units
-    float icps, icns;
-    float hi, lo;    // first up / down level in scaled units (FP32)
-    float dp;        // guard band for this pixel
-    float him, lop;  // candidate tests: L > hi - dp or L < lo + dp
+    double Ep2, En2; // level-2 factors with the guard folded in (intensity)
+    float Ahi, Bhi, Chi;  // I > Ahi: maybe up; I >= Bhi: surely >= 1 up;
+                          // I <= Chi: surely < 2 up
+    float Alo, Blo, Clo;  // mirrored for down crossings
 };
 
-// Rebuild the FP32 levels from the exact lattice, R computed as defined.
 template <bool LOGIN>
-__device__ __forceinline__ void refresh_levels(Px& q) {
-    const double S = LOGIN ? 1.0 : kInvLn2;
-    const double cp = (double)q.cp, cn = (double)q.cn;
-    const double R = q.L_init + ((double)q.nup * cp - (double)q.ndn * cn);
-    q.hi = (float)((R + cp) * S);
-    q.lo = (float)((R - cn) * S);
-    q.dp = kDelta0 + fmaxf(fabsf(q.hi), fabsf(q.lo)) * kDeltaRel;
-    q.him = q.hi - q.dp;
-    q.lop = q.lo + q.dp;
+__device__ __forceinline__ double lvl_step(double X, double E) {
+    return LOGIN ? X + E : X * E;
 }
+// Sample value just below / above level X (guard g relative to the level).
+// (For intensity input the guard is relative to X + eps, which also bounds
+// the FP32 rounding of X - eps; with eps = 0 these compare I + eps with X.)
+template <bool LOGIN>
+__device__ __forceinline__ double lvl_below(double X, double g, double eps) {
+    return LOGIN ? X - g * (1.0 + fabs(X)) : (X - eps) - g * (X + eps);
+}
+template <bool LOGIN>
+__device__ __forceinline__ double lvl_above(double X, double g, double eps) {
+    return LOGIN ? X + g * (1.0 + fabs(X)) : (X - eps) + g * (X + eps);
+}
+
+// The six FP32 sample thresholds of the current levels.  For intensity
+// input each is one FMA: X (1 -/+ g) - eps (1 +/- g), with the level-2
+// factors Ep (1 - g), En (1 + g) precomputed per pixel.
+template <bool LOGIN>
+__device__ __forceinline__ void refresh_thresholds(Px& q, double eps) {
+    if (LOGIN) {
+        q.Ahi = (float)lvl_below<LOGIN>(q.Xh, kG32, eps);
+        q.Bhi = (float)lvl_above<LOGIN>(q.Xh, kG32, eps);
+        q.Chi = (float)lvl_below<LOGIN>(lvl_step<LOGIN>(q.Xh, q.Ep), kG32, eps);
+        q.Alo = (float)lvl_above<LOGIN>(q.Xl, kG32, eps);
+        q.Blo = (float)lvl_below<LOGIN>(q.Xl, kG32, eps);
+        q.Clo = (float)lvl_above<LOGIN>(lvl_step<LOGIN>(q.Xl, q.En), kG32, eps);
+    } else {
+        const double eb = -eps * (1.0 + kG32), ea = -eps * (1.0 - kG32);
+        q.Ahi = (float)fma(q.Xh, 1.0 - kG32, eb);
+        q.Bhi = (float)fma(q.Xh, 1.0 + kG32, ea);
+        q.Chi = (float)fma(q.Xh, q.Ep2, eb);
+        q.Alo = (float)fma(q.Xl, 1.0 + kG32, ea);
+        q.Blo = (float)fma(q.Xl, 1.0 - kG32, eb);
+        q.Clo = (float)fma(q.Xl, q.En2, ea);
+    }
+}
+
+// Levels from the exact lattice: R computed as the definition does.
+template <bool LOGIN>
+__device__ __forceinline__ void exact_levels(Px& q, double eps);
 
 template <bool LOGIN>
 __device__ __forceinline__ void load_pixel(Px& q, const double* L_init,
@@ -132,7 +221,7 @@ __device__ __forceinline__ void load_pixel(Px& q, const double* L_init,
                                            const int32_t* tlast,
                                            const float* cpm, const float* cnm,
                                            float cp, float cn, int pix,
-                                           bool valid, float eps_f) {
+                                           bool valid, double eps) {
     if (valid) {
         q.L_init = L_init[pix];
         int2 c = nud[pix];
@@ -149,31 +238,119 @@ __device__ __forceinline__ void load_pixel(Px& q, const double* L_init,
         q.tlast = kTlastNone;
         q.cp = q.cn = 1.0f;
     }
-    const float S = LOGIN ? 1.0f : (float)kInvLn2;
-    q.cps = q.cp * S;
-    q.cns = q.cn * S;
-    q.icps = 1.0f / q.cps;
-    q.icns = 1.0f / q.cns;
-    q.Lprev = LOGIN ? q.prev : fast_log2(q.prev + eps_f);
-    refresh_levels<LOGIN>(q);
+    if (LOGIN) {
+        q.Ep = (double)q.cp;
+        q.En = -(double)q.cn;
+    } else {
+        q.Ep = exp((double)q.cp);
+        q.En = exp(-(double)q.cn);
+    }
+    q.Ep2 = q.Ep * (1.0 - kG32);
+    q.En2 = q.En * (1.0 + kG32);
+    exact_levels<LOGIN>(q, eps);
+}
+
+// ---- rare paths, kept out of line so the frame loop stays small.  They
+// take and return plain values so the caller's state stays in registers.
+
+struct LogPair {
+    double L0, L1;
+};
+
+template <bool LOGIN>
+__device__ __attribute__((noinline)) LogPair log_pair64(float prev, float I,
+                                                        double eps) {
+    return {log_intensity64<LOGIN>(prev, eps), log_intensity64<LOGIN>(I, eps)};
+}
+
+struct Count64 {
+    int n;
+    int up;
+};
+
+// Crossings of one frame interval counted exactly as the definition does.
+__device__ __attribute__((noinline)) Count64 count64(double L_init, int nup,
+                                                     int ndn, float cpf,
+                                                     float cnf, double L1) {
+    const double cp = (double)cpf, cn = (double)cnf;
+    double R = L_init + ((double)nup * cp - (double)ndn * cn);
+    int c = 0, up = 0;
+    if (L1 >= R + cp) {
+        up = 1;
+        do {
+            ++c;
+            R = L_init + ((double)(nup + c) * cp - (double)ndn * cn);
+        } while (L1 >= R + cp && c < kMaxCross);
+    } else if (L1 <= R - cn) {
+        do {
+            ++c;
+            R = L_init + ((double)nup * cp - (double)(ndn + c) * cn);
+        } while (L1 <= R - cn && c < kMaxCross);
+    }
+    return {c, up};
+}
+
+// Timestamp of crossing j (0-based) of a frame, as the definition computes
+// it; returned relative to T0.
+__device__ __attribute__((noinline)) int time64(double L_init, int nup,
+                                                int ndn, float cpf, float cnf,
+                                                int up, int j, double L0,
+                                                double L1, int64_t T0, int tp,
+                                                int dt) {
+    const double cp = (double)cpf, cn = (double)cnf;
+    double lvl;
+    if (up) {
+        const double R = L_init + ((double)(nup + j) * cp - (double)ndn * cn);
+        lvl = R + cp;
+    } else {
+        const double R = L_init + ((double)nup * cp - (double)(ndn + j) * cn);
+        lvl = R - cn;
+    }
+    const double tau =
+        (double)(T0 + (int64_t)tp) + (lvl - L0) / (L1 - L0) * (double)dt;
+    return (int)((int64_t)ceil(tau) - T0);
+}
+
+struct Levels {
+    double Xh, Xl;
+};
+
+template <bool LOGIN>
+__device__ __attribute__((noinline)) Levels levels64(double L_init, int nup,
+                                                     int ndn, float cpf,
+                                                     float cnf) {
+    const double cp = (double)cpf, cn = (double)cnf;
+    const double R = L_init + ((double)nup * cp - (double)ndn * cn);
+    if (LOGIN) return {R + cp, R - cn};
+    return {exp(R + cp), exp(R - cn)};
+}
+
+template <bool LOGIN>
+__device__ __forceinline__ void exact_levels(Px& q, double eps) {
+    const Levels l = levels64<LOGIN>(q.L_init, q.nup, q.ndn, q.cp, q.cn);
+    q.Xh = l.Xh;
+    q.Xl = l.Xl;
+    refresh_thresholds<LOGIN>(q, eps);
 }
 
 // Copy a wave's staged entries to the packed output, dropping suppressed
-// crossings; returns the next output position.
-__device__ __forceinline__ int64_t flush_wave(const uint2* buf, int count,
-                                              uint32_t* okey, uint32_t* oval,
-                                              int64_t g, int64_t cap) {
+// crossings; returns the next output position.  Entry layout:
+// (time offset << 7) | (lane << 1) | (p > 0).
+__device__ __forceinline__ int64_t flush_wave(const uint32_t* buf, int count,
+                                              uint32_t pix0, uint32_t* okey,
+                                              uint32_t* oval, int64_t g,
+                                              int64_t cap) {
     const uint64_t lt = lanemask_lt();
     for (int j0 = 0; j0 < count; j0 += kWave) {
         const int j = j0 + lane_id();
-        uint2 e = make_uint2(kKeyHole, 0u);
+        uint32_t e = kEntryHole;
         if (j < count) e = buf[j];
-        const bool v = e.x != kKeyHole;
+        const bool v = e != kEntryHole;
         const uint64_t m = __ballot(v);
         const int64_t pos = g + __popcll(m & lt);
         if (v && pos < cap) {
-            okey[pos] = e.x;
-            oval[pos] = e.y;
+            okey[pos] = e >> 7;
+            oval[pos] = ((pix0 + ((e >> 1) & 63u)) << 1) | (e & 1u);
         }
         g += __popcll(m);
     }
@@ -186,113 +363,152 @@ __device__ __forceinline__ int64_t flush_wave(const uint2* buf, int count,
 // buffer to global memory whenever it fills.
 template <bool LOGIN, bool RERUN>
 __device__ __forceinline__ void walk_frames(
-    const StepArgs& a, Px& q, bool valid, int pix, uint2* buf, int& cursor,
-    bool& over, int& emitted, int& f64count, int64_t& gpos) {
+    const StepArgs& a, Px& q, bool valid, int pix, uint32_t pix0,
+    uint32_t* buf, float* fslab, int& cursor, bool& over, int& emitted,
+    int& f64count, int64_t& gpos, int* dg) {
     const float eps_f = a.log_eps_f;
     const double eps = a.log_eps;
     const int tref = a.tref;
     const bool force64 = (a.flags & 0x2u) != 0;
-    const uint32_t val_base = ((uint32_t)pix << 1);
+    const uint32_t lane_bits = ((uint32_t)lane_id()) << 1;
     const float* fr = a.frames + pix;
     const int64_t P = a.P;
     const int K = a.K;
 
-    constexpr int U = 8;
-    float nxt[U];
+    // Frames are prefetched a chunk of kChunk frames ahead into registers;
+    // at the start of each chunk the registers (loaded one chunk earlier)
+    // are parked in the wave's LDS slab and the next chunk's loads are
+    // issued, so the frame walk reads LDS and never waits on a fresh load.
+    constexpr int U = kChunk;
+    float r[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        nxt[u] = (valid && u < K) ? __builtin_nontemporal_load(fr + (int64_t)u * P)
-                                  : 1.0f;
+        r[u] = (valid && u < K) ? __builtin_nontemporal_load(fr + (int64_t)u * P)
+                                : 1.0f;
+    const int lane = lane_id();
 
-    for (int k0 = 0; k0 < K; k0 += U) {
-        float cur[U];
+    for (int kc = 0; kc < K; kc += U) {
 #pragma unroll
-        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+        for (int u = 0; u < U; ++u) fslab[u * kWave + lane] = r[u];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int kk = k0 + U + u;
-            nxt[u] = (valid && kk < K)
-                         ? __builtin_nontemporal_load(fr + (int64_t)kk * P)
-                         : 1.0f;
+            const int kk = kc + U + u;
+            r[u] = (valid && kk < K)
+                       ? __builtin_nontemporal_load(fr + (int64_t)kk * P)
+                       : 1.0f;
         }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int k = k0 + u;
-            if (k >= K) break;
-            const float I = cur[u];
-            const float L = LOGIN ? I : fast_log2(I + eps_f);
-            const bool cand = valid && ((L > q.him) || (L < q.lop));
+        const int cnt = (K - kc) < U ? (K - kc) : U;
+#pragma clang loop unroll(disable)
+        for (int u = 0; u < cnt; ++u) {
+            const int k = kc + u;
+            const float I = fslab[u * kWave + lane];
+            const bool cand = valid && ((I > q.Ahi) || (I < q.Alo));
             if (__ballot(cand)) {
+                ++dg[3];
                 const int tp = k > 0 ? a.toff[k - 1] : 0;
-                const int tc = a.toff[k];
-                const int dt = tc - tp;
-                // ---- crossing count, FP32 where the bound decides it
+                const int dt = a.toff[k] - tp;
+                // ---- crossing count: FP32 certainty for one crossing,
+                // FP64 level walk otherwise, FP64 replica if undecided
                 int n = 0;
                 bool up = false;
                 bool f64 = false;
+                bool slow = false;
                 if (cand) {
-                    up = L > q.him;
-                    const float base = up ? q.hi : q.lo;
-                    const float u1 = up ? (L - base) : (base - L);
-                    if (force64 || u1 < q.dp) {
+                    up = I > q.Ahi;
+                    const bool one = up ? (I >= q.Bhi && I <= q.Chi)
+                                        : (I <= q.Blo && I >= q.Clo);
+                    if (force64)
                         f64 = true;
-                    } else {
-                        const int m = (int)(u1 * (up ? q.icps : q.icns));
-                        const float stp = up ? q.cps : -q.cns;
-                        const float lv_last = fmaf((float)m, stp, base);
-                        const float lv_next = fmaf((float)(m + 1), stp, base);
-                        const float a1 = up ? (L - lv_last) : (lv_last - L);
-                        const float a2 = up ? (lv_next - L) : (L - lv_next);
-                        if (a1 >= q.dp && a2 >= q.dp && m < kFastMaxCross)
-                            n = m + 1;
-                        else
-                            f64 = true;
+                    else if (one)
+                        n = 1;
+                    else
+                        slow = true;
+                }
+                if (__ballot(slow)) {
+                    if (slow) {
+                        // walk the levels in FP64 with a tiny guard
+                        const double s = LOGIN ? (double)I : (double)I + eps;
+                        double X = up ? q.Xh : q.Xl;
+                        const double E = up ? q.Ep : q.En;
+                        for (;;) {
+                            const double lo = lvl_below<LOGIN>(X, kG64, 0.0);
+                            const double hi = lvl_above<LOGIN>(X, kG64, 0.0);
+                            const bool crossed = up ? (s >= hi) : (s <= lo);
+                            const bool short_ = up ? (s < lo) : (s > hi);
+                            if (crossed) {
+                                ++n;
+                                if (n >= kFastMaxCross) {
+                                    f64 = true;
+                                    break;
+                                }
+                                X = lvl_step<LOGIN>(X, E);
+                                continue;
+                            }
+                            if (!short_) f64 = true;
+                            break;
+                        }
+                        if (f64) n = 0;
                     }
                 }
                 double L0d = 0.0, L1d = 0.0;
                 bool have_d = false;
                 if (__ballot(f64)) {
+                    ++dg[4];
                     if (f64) {
-                        L0d = log_intensity64<LOGIN>(q.prev, eps);
-                        L1d = log_intensity64<LOGIN>(I, eps);
+                        const LogPair lp = log_pair64<LOGIN>(q.prev, I, eps);
+                        L0d = lp.L0;
+                        L1d = lp.L1;
                         have_d = true;
                         ++f64count;
-                        const double cp = (double)q.cp, cn = (double)q.cn;
-                        double R = q.L_init +
-                                   ((double)q.nup * cp - (double)q.ndn * cn);
-                        int c = 0;
-                        if (L1d >= R + cp) {
-                            up = true;
-                            do {
-                                ++c;
-                                R = q.L_init + ((double)(q.nup + c) * cp -
-                                                (double)q.ndn * cn);
-                            } while (L1d >= R + cp && c < kMaxCross);
-                        } else if (L1d <= R - cn) {
-                            up = false;
-                            do {
-                                ++c;
-                                R = q.L_init + ((double)q.nup * cp -
-                                                (double)(q.ndn + c) * cn);
-                            } while (L1d <= R - cn && c < kMaxCross);
-                        }
-                        n = c;
+                        ++dg[0];
+                        const Count64 c =
+                            count64(q.L_init, q.nup, q.ndn, q.cp, q.cn, L1d);
+                        n = c.n;
+                        up = c.up != 0;
                     }
                 }
                 // ---- (frame, pixel, k) slots within the wave
                 const int incl = wave_incl_scan(n);
-                const int total = __shfl(incl, kWave - 1, kWave);
+                const int total = wave_last(incl);
                 const int excl = incl - n;
                 if (total > 0) {
-                    // FP32 timestamp setup
-                    float a0 = 0.f, bst = 0.f, et = 1.f;
+                    ++dg[7];
+                    // interpolation fraction of crossing j: N_j / D with
+                    // N_j = ln(X_j / x0), D = ln(x1 / x0) (log input: plain
+                    // differences), N_j = N_1 + j * step
+                    float D = 1.f, invD = 1.f, relD = 0.f;
+                    float N1 = 0.f, relN1 = 0.f, absN = 0.f, cstep = 0.f;
                     if (n > 0 && !f64) {
-                        const float r = __fdividef((float)dt, L - q.Lprev);
-                        const float base = up ? q.hi : q.lo;
-                        a0 = (base - q.Lprev) * r;
-                        bst = (up ? q.cps : -q.cns) * r;
-                        et = fabsf(r) * q.dp + (float)dt * 0x1p-20f + a.eT;
+                        const double X1 = up ? q.Xh : q.Xl;
+                        cstep = up ? q.cp : -q.cn;
+                        if (LOGIN) {
+                            D = (float)((double)I - (double)q.prev);
+                            relD = 0x1p-24f;
+                            N1 = (float)(X1 - (double)q.prev);
+                            relN1 = 0x1p-24f;
+                            absN = (float)(0x1p-36 * (1.0 + fabs(X1)));
+                        } else {
+                            const LnRatio d =
+                                ln_ratio(I - q.prev, (I + q.prev) + 2.0f * eps_f,
+                                         I + eps_f, q.prev + eps_f);
+                            D = d.v;
+                            relD = d.rel;
+                            const double x0d = (double)q.prev + eps;
+                            const LnRatio nn = ln_ratio(
+                                (float)(X1 - x0d), (float)(X1 + x0d), (float)X1,
+                                q.prev + eps_f);
+                            N1 = nn.v;
+                            relN1 = nn.rel;
+                            absN = 0x1p-35f;
+                        }
+                        invD = fast_rcp(D);
                     }
+                    const float dtf = (float)dt;
+                    // |error of tau_j| <= alpha + beta * phi_j (safety 1.25)
+                    const float alpha =
+                        1.25f * dtf * (relN1 * fabsf(N1) + absN) * fabsf(invD) +
+                        a.eT;
+                    const float beta = 1.25f * dtf * (relD + 0x1p-21f + 0x1p-23f);
                     const int tl0 = q.tlast;
                     int win_lo = 0;
                     int win_cap;  // writable entries in this window
@@ -303,8 +519,8 @@ __device__ __forceinline__ void walk_frames(
                         win_cap = total;
                     } else {
                         if (cursor + total > kStepLdsEntries) {
-                            gpos = flush_wave(buf, cursor, a.out_key, a.out_val,
-                                              gpos, a.out_cap);
+                            gpos = flush_wave(buf, cursor, pix0, a.out_key,
+                                              a.out_val, gpos, a.out_cap);
                             cursor = 0;
                         }
                         write = true;
@@ -314,12 +530,16 @@ __device__ __forceinline__ void walk_frames(
                         q.tlast = tl0;
                         int em = 0;
                         for (int j = 0; __ballot(j < n); ++j) {
+                            ++dg[5];
                             int tt = 0;
                             bool need = false;
                             if (j < n) {
                                 need = f64;
                                 if (!need) {
-                                    const float tau = fmaf((float)j, bst, a0);
+                                    const float Nj = fmaf((float)j, cstep, N1);
+                                    const float phi = Nj * invD;
+                                    const float tau = dtf * phi;
+                                    const float et = fmaf(beta, phi, alpha);
                                     const float c1 = ceilf(tau - et);
                                     const float c2 = ceilf(tau + et);
                                     if (c1 == c2 && et < 0.25f)
@@ -329,31 +549,20 @@ __device__ __forceinline__ void walk_frames(
                                 }
                             }
                             if (__ballot(need)) {
+                                ++dg[6];
                                 if (need) {
+                                    ++dg[1];
                                     if (!have_d) {
-                                        L0d = log_intensity64<LOGIN>(q.prev, eps);
-                                        L1d = log_intensity64<LOGIN>(I, eps);
+                                        const LogPair lp =
+                                            log_pair64<LOGIN>(q.prev, I, eps);
+                                        L0d = lp.L0;
+                                        L1d = lp.L1;
                                         have_d = true;
                                     }
                                     ++f64count;
-                                    const double cp = (double)q.cp;
-                                    const double cn = (double)q.cn;
-                                    double lvl;
-                                    if (up) {
-                                        const double R =
-                                            q.L_init + ((double)(q.nup + j) * cp -
-                                                        (double)q.ndn * cn);
-                                        lvl = R + cp;
-                                    } else {
-                                        const double R =
-                                            q.L_init + ((double)q.nup * cp -
-                                                        (double)(q.ndn + j) * cn);
-                                        lvl = R - cn;
-                                    }
-                                    const double tau =
-                                        (double)(a.T0 + (int64_t)tp) +
-                                        (lvl - L0d) / (L1d - L0d) * (double)dt;
-                                    tt = (int)((int64_t)ceil(tau) - a.T0);
+                                    tt = time64(q.L_init, q.nup, q.ndn, q.cp,
+                                                q.cn, up ? 1 : 0, j, L0d, L1d,
+                                                a.T0, tp, dt);
                                 }
                             }
                             if (j < n) {
@@ -363,9 +572,9 @@ __device__ __forceinline__ void walk_frames(
                                 const int idx = excl + j - win_lo;
                                 if (write && idx >= 0 && idx < win_cap) {
                                     buf[cursor + idx] =
-                                        emit ? make_uint2((uint32_t)tt,
-                                                          val_base | (up ? 1u : 0u))
-                                             : make_uint2(kKeyHole, 0u);
+                                        emit ? (((uint32_t)tt << 7) | lane_bits |
+                                                (up ? 1u : 0u))
+                                             : kEntryHole;
                                 }
                             }
                         }
@@ -380,58 +589,87 @@ __device__ __forceinline__ void walk_frames(
                             cursor += used;
                             win_lo += win_cap;
                             if (win_lo >= total) break;
-                            gpos = flush_wave(buf, cursor, a.out_key, a.out_val,
-                                              gpos, a.out_cap);
+                            gpos = flush_wave(buf, cursor, pix0, a.out_key,
+                                              a.out_val, gpos, a.out_cap);
                             cursor = 0;
                         }
                     }
                 }
+                // ---- move the reference by the n crossings
                 if (n > 0) {
                     if (up)
                         q.nup += n;
                     else
                         q.ndn += n;
-                    refresh_levels<LOGIN>(q);
+                    if (f64) {
+                        exact_levels<LOGIN>(q, eps);
+                    } else {
+                        const double E = up ? q.Ep : q.En;
+                        q.Xh = lvl_step<LOGIN>(q.Xh, E);
+                        q.Xl = lvl_step<LOGIN>(q.Xl, E);
+                        for (int i = 1; i < n; ++i) {
+                            q.Xh = lvl_step<LOGIN>(q.Xh, E);
+                            q.Xl = lvl_step<LOGIN>(q.Xl, E);
+                        }
+                        refresh_thresholds<LOGIN>(q, eps);
+                    }
                 }
             }
-            q.Lprev = L;
             q.prev = I;
         }
     }
 }
 
+#ifdef NSIM_TILE_TRACE
+// Diagnostic build only: wall-clock stamps per wave and phase.
+__device__ uint64_t g_tile_trace[1 << 17][8];
+#define TILE_STAMP(slot)                                                  \
+    do {                                                                  \
+        if (lane == 0 && wid < (1 << 17))                                 \
+            g_tile_trace[wid][slot] = wall_clock64();                     \
+    } while (0)
+#else
+#define TILE_STAMP(slot) \
+    do {                 \
+    } while (0)
+#endif
+
+// One wave = 64 consecutive pixels, fully independent of every other wave:
+// it walks the launch's frames, reserves a segment of the staging arrays for
+// its events with one atomic, and writes them there in (frame, pixel, k)
+// order.  The scan and gather kernels restore pixel-block order afterwards.
 template <bool LOGIN, bool MAP>
 __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs a) {
-    __shared__ uint2 s_buf[kStepWaves][kStepLdsEntries];
-    __shared__ int s_tile;
-    __shared__ int s_wemit[kStepWaves];
-    __shared__ int s_wover[kStepWaves];
-    __shared__ int s_f64[kStepWaves];
-    __shared__ int64_t s_base;
+    __shared__ uint32_t s_buf[kStepWaves][kStepLdsEntries];
+    __shared__ float s_frames[kStepWaves][kChunk * kWave];
 
     Header* hdr = a.hdr;
-    if (threadIdx.x == 0) s_tile = (int)atomicAdd(a.tile_ctr, 1u);
-    __syncthreads();
-    const int tile = s_tile;
-    if (tile >= a.ntiles) return;
-    if (hdr->status != 0) return;
-    const int cur = hdr->cur;
     const int w = threadIdx.x / kWave;
     const int lane = lane_id();
-    const int pix = tile * kStepThreads + (int)threadIdx.x;
+    const int wid = blockIdx.x * kStepWaves + w;
+    if (wid >= a.nwaves) return;
+    if (hdr->status != 0) return;
+    TILE_STAMP(0);
+    const int cur = hdr->cur;
+    const int pix = wid * kWave + lane;
+    const uint32_t pix0 = (uint32_t)(wid * kWave);
     const bool valid = pix < a.P;
 
     Px q;
     load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
                       MAP ? a.c_pos_map : nullptr, MAP ? a.c_neg_map : nullptr,
-                      a.c_pos, a.c_neg, pix, valid, a.log_eps_f);
+                      a.c_pos, a.c_neg, pix, valid, a.log_eps);
 
-    uint2* buf = s_buf[w];
+    TILE_STAMP(1);
+    uint32_t* buf = s_buf[w];
     int cursor = 0, emitted = 0, f64count = 0;
     bool over = false;
     int64_t gdummy = 0;
-    walk_frames<LOGIN, false>(a, q, valid, pix, buf, cursor, over, emitted,
-                              f64count, gdummy);
+    int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    walk_frames<LOGIN, false>(a, q, valid, pix, pix0, buf, s_frames[w], cursor,
+                              over, emitted, f64count, gdummy, dg);
+    dg[2] = over ? 1 : 0;
+    TILE_STAMP(2);
 
     // commit-candidate state into the other buffer
     if (valid) {
@@ -447,82 +685,89 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs a) {
 
     const int wemit = wave_sum(emitted);
     const int wf64 = wave_sum(f64count);
-    if (lane == 0) {
-        s_wemit[w] = wemit;
-        s_wover[w] = over ? 1 : 0;
-        s_f64[w] = wf64;
-    }
-    __syncthreads();
-    int agg = 0, before = 0, f64tile = 0;
-    for (int i = 0; i < kStepWaves; ++i) {
-        if (i < w) before += s_wemit[i];
-        agg += s_wemit[i];
-        f64tile += s_f64[i];
-    }
-
-    // decoupled look-back over pixel tiles (wave 0)
-    if (w == 0) {
-        const uint64_t tag = (uint64_t)a.epoch << 34;
-        if (lane == 0)
-            atomic_store_u64(&a.tile_status[tile],
-                             tag | ((uint64_t)(tile == 0 ? kInc : kAgg) << 32) |
-                                 (uint32_t)agg);
-        int64_t excl = 0;
-        int j = tile - 1;
-        uint32_t spins = 0;
-        while (j >= 0) {
-            const int idx = j - lane;
-            uint32_t flag = kInc, val = 0;
-            if (idx >= 0) {
-                const uint64_t s = atomic_load_u64(&a.tile_status[idx]);
-                flag = (s >> 34) == (uint64_t)a.epoch ? (uint32_t)((s >> 32) & 3u)
-                                                      : 0u;
-                val = (uint32_t)s;
-            }
-            const uint64_t inc = __ballot(flag == kInc);
-            const uint64_t notready = __ballot(flag == 0u);
-            const int first = inc ? (__ffsll((unsigned long long)inc) - 1) : kWave;
-            const uint64_t need =
-                first >= kWave - 1 ? ~0ull : ((2ull << first) - 1ull);
-            if (notready & need) {
-                if (++spins > kSpinLimit) {
-                    if (lane == 0) atomicExch(&hdr->internal_err, 1);
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
-                continue;
-            }
-            excl += wave_sum64(lane <= first ? (int64_t)val : 0);
-            if (first < kWave) break;
-            j -= kWave;
-        }
+#ifdef NSIM_STEP_DIAG
+    {
+        // lane-level counters are summed, wave-level ones taken once
+        const int d0 = wave_sum(dg[0]), d1 = wave_sum(dg[1]);
         if (lane == 0) {
-            if (tile > 0)
-                atomic_store_u64(&a.tile_status[tile],
-                                 tag | ((uint64_t)kInc << 32) |
-                                     (uint32_t)(excl + agg));
-            s_base = excl;
-            if (tile == a.ntiles - 1) hdr->n_step = excl + agg;
-            if (f64tile) atomicAdd((unsigned long long*)&hdr->fp64_evals,
-                                   (unsigned long long)f64tile);
+            const int vals[8] = {d0, d1, dg[2], dg[3], dg[4], dg[5], dg[6], dg[7]};
+            for (int i = 0; i < 8; ++i)
+                if (vals[i])
+                    atomicAdd((unsigned long long*)&hdr->diag[i],
+                              (unsigned long long)vals[i]);
         }
     }
-    __syncthreads();
-    int64_t g = s_base + before;
-    if (!s_wover[w]) {
-        flush_wave(buf, cursor, a.out_key, a.out_val, g, a.out_cap);
+#endif
+    // this wave's staging segment: its fixed one, or one from the pool
+    int64_t base = (int64_t)wid * kStepLdsEntries;
+    if (over) {
+        uint64_t b = 0;
+        if (lane == 0)
+            b = atomicAdd((unsigned long long*)&hdr->alloc,
+                          (unsigned long long)wemit);
+        base = (int64_t)a.nwaves * kStepLdsEntries + (int64_t)__shfl(b, 0, kWave);
+    }
+    if (lane == 0) {
+        a.seg_base[wid] = base;
+        a.seg_count[wid] = (uint32_t)wemit;
+        if (wf64)
+            atomicAdd((unsigned long long*)&hdr->fp64_evals,
+                      (unsigned long long)wf64);
+    }
+    TILE_STAMP(3);
+    if (base + wemit > a.out_cap) return;  // the step overflows anyway
+    int64_t g = base;
+    if (!over) {
+        flush_wave(buf, cursor, pix0, a.out_key, a.out_val, g, a.out_cap);
     } else {
         // regenerate this wave's events from the launch's starting state
         load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
                           MAP ? a.c_pos_map : nullptr,
                           MAP ? a.c_neg_map : nullptr, a.c_pos, a.c_neg, pix,
-                          valid, a.log_eps_f);
+                          valid, a.log_eps);
         cursor = 0;
         over = false;
         int e2 = 0, f2 = 0;
-        walk_frames<LOGIN, true>(a, q, valid, pix, buf, cursor, over, e2, f2, g);
-        flush_wave(buf, cursor, a.out_key, a.out_val, g, a.out_cap);
+        int dg2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        walk_frames<LOGIN, true>(a, q, valid, pix, pix0, buf, s_frames[w], cursor,
+                                 over, e2, f2, g, dg2);
+        flush_wave(buf, cursor, pix0, a.out_key, a.out_val, g, a.out_cap);
     }
+    TILE_STAMP(4);
+#ifdef NSIM_TILE_TRACE
+    if (lane == 0 && wid < (1 << 17)) {
+        g_tile_trace[wid][6] = (uint64_t)__smid();
+        g_tile_trace[wid][7] = (uint64_t)(over ? 1 : 0) | ((uint64_t)wemit << 8);
+    }
+#endif
+}
+
+// Exclusive scan of the per-wave counts in wave (= pixel) order, one
+// workgroup: each thread sums a contiguous run, the runs are scanned in
+// LDS, then every thread writes its run's prefixes.
+__global__ __launch_bounds__(1024) void scan_kernel(const ScanArgs a) {
+    __shared__ uint64_t s_part[1024];
+    const int tid = threadIdx.x;
+    const int64_t n = a.nwaves;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t lo = tid * per;
+    const int64_t hi = lo + per < n ? lo + per : n;
+    uint64_t sum = 0;
+    for (int64_t i = lo; i < hi; ++i) sum += a.seg_count[i];
+    s_part[tid] = sum;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+        const uint64_t v = tid >= d ? s_part[tid - d] : 0;
+        __syncthreads();
+        s_part[tid] += v;
+        __syncthreads();
+    }
+    uint64_t run = s_part[tid] - sum;
+    for (int64_t i = lo; i < hi; ++i) {
+        a.pref[i] = (uint32_t)(run < 0xFFFFFFFFull ? run : 0xFFFFFFFFull);
+        run += a.seg_count[i];
+    }
+    if (tid == 1023) a.hdr->n_step = (int64_t)s_part[1023];
 }
 
 __global__ void init_kernel(const InitArgs a) {
@@ -546,7 +791,9 @@ __device__ __forceinline__ bool step_fits(const Header* hdr, int64_t scap,
            (hdr->tail - hdr->head) + n <= qcap;
 }
 
-__global__ __launch_bounds__(256) void hist_kernel(const HistArgs a) {
+// Copy every wave's segment to its pixel-order position and count the
+// radix digits of all passes; also clears the passes' look-back words.
+__global__ __launch_bounds__(256) void gather_kernel(const GatherArgs a) {
     __shared__ uint32_t s_h[kMaxPasses * kDigits];
     int64_t n;
     const bool ok = step_fits(a.hdr, a.scratch_cap, a.qcap, &n);
@@ -555,17 +802,27 @@ __global__ __launch_bounds__(256) void hist_kernel(const HistArgs a) {
     const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
     const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    // clear the look-back status words of the passes of this step
     for (int p = 0; p < a.npass; ++p) {
         uint32_t* st = a.status + (int64_t)p * a.max_tiles * kDigits;
         for (int64_t i = gid; i < ntiles * kDigits; i += gsz) st[i] = 0u;
     }
     for (int i = threadIdx.x; i < kMaxPasses * kDigits; i += blockDim.x) s_h[i] = 0u;
     __syncthreads();
-    for (int64_t i = gid; i < n; i += gsz) {
-        const uint32_t k = a.keys[i];
-        for (int p = 0; p < a.npass; ++p)
-            atomicAdd(&s_h[p * kDigits + ((k >> (kDigitBits * p)) & (kDigits - 1))], 1u);
+    const int lane = lane_id();
+    const int64_t wstride = (int64_t)gridDim.x * (blockDim.x / kWave);
+    for (int64_t wv = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+         wv < a.nwaves; wv += wstride) {
+        const int64_t sb = a.seg_base[wv];
+        const uint32_t sc = a.seg_count[wv];
+        const int64_t dst = a.pref[wv];
+        for (uint32_t j = lane; j < sc; j += kWave) {
+            const uint32_t k = a.skey[sb + j];
+            a.dkey[dst + j] = k;
+            a.dval[dst + j] = a.sval[sb + j];
+            for (int p = 0; p < a.npass; ++p)
+                atomicAdd(&s_h[p * kDigits + ((k >> (kDigitBits * p)) & (kDigits - 1))],
+                          1u);
+        }
     }
     __syncthreads();
     for (int i = threadIdx.x; i < a.npass * kDigits; i += blockDim.x)
@@ -743,12 +1000,12 @@ __global__ void commit_kernel(const CommitArgs a) {
             h->dropped_t = a.t_first;
         }
         h->n_step = 0;
-        *a.step_tile_ctr = 0u;
+        h->alloc = 0;
     }
     for (int i = threadIdx.x; i < kMaxPasses * kDigits; i += blockDim.x) a.hist[i] = 0u;
 }
 
-__global__ void reset_kernel(Header* h, uint32_t* hist, uint32_t* step_tile_ctr) {
+__global__ void reset_kernel(Header* h, uint32_t* hist) {
     if (threadIdx.x == 0) {
         h->cur = 0;
         h->status = 0;
@@ -758,7 +1015,7 @@ __global__ void reset_kernel(Header* h, uint32_t* hist, uint32_t* step_tile_ctr)
         h->t_prev = 0;
         h->dropped_t = 0;
         h->internal_err = 0;
-        *step_tile_ctr = 0u;
+        h->alloc = 0;
     }
     for (int i = threadIdx.x; i < kMaxPasses * kDigits; i += blockDim.x) hist[i] = 0u;
 }
@@ -815,7 +1072,7 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s) {
 
 hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
                        hipStream_t s) {
-    const dim3 grid(a.ntiles), block(kStepThreads);
+    const dim3 grid((a.nwaves + kStepWaves - 1) / kStepWaves), block(kStepThreads);
     if (log_input) {
         if (has_map)
             hipLaunchKernelGGL((step_kernel<true, true>), grid, block, 0, s, a);
@@ -830,8 +1087,13 @@ hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
     return hipGetLastError();
 }
 
-hipError_t launch_hist(const HistArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(hist_kernel, dim3(512), dim3(256), 0, s, a);
+hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(gather_kernel, dim3(512), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -845,10 +1107,8 @@ hipError_t launch_commit(const CommitArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_reset_header(Header* hdr, uint32_t* hist,
-                               uint32_t* step_tile_ctr, hipStream_t s) {
-    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, hdr, hist,
-                       step_tile_ctr);
+hipError_t launch_reset_header(Header* hdr, uint32_t* hist, hipStream_t s) {
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, s, hdr, hist);
     return hipGetLastError();
 }
 
@@ -863,6 +1123,13 @@ hipError_t launch_state_copy(const StateCopyArgs& a, hipStream_t s) {
                        0, s, a);
     return hipGetLastError();
 }
+
+#ifdef NSIM_TILE_TRACE
+extern "C" int nsim_debug_read_trace(void* host, int64_t bytes) {
+    return (int)hipMemcpyFromSymbol(host, HIP_SYMBOL(g_tile_trace), bytes, 0,
+                                    hipMemcpyDeviceToHost);
+}
+#endif
 
 hipError_t launch_fast_log2(const float* x, float* out, int64_t n,
                             hipStream_t s) {

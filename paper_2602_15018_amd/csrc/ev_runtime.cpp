@@ -30,9 +30,8 @@ struct nsim_ev {
     int64_t qcap = 0;     // queue capacity (events)
     int64_t scap = 0;     // per-launch scratch capacity (events)
     int32_t max_frames = 0;
-    int32_t ntiles = 0;
+    int32_t nwaves = 0;
     int64_t max_sort_tiles = 0;
-    uint32_t epoch = 0;
 
     // device memory
     Header* hdr = nullptr;
@@ -42,14 +41,18 @@ struct nsim_ev {
     int32_t* tlast[2] = {nullptr, nullptr};
     float* cpos_map = nullptr;
     float* cneg_map = nullptr;
-    uint32_t* skey[2] = {nullptr, nullptr};
+    uint32_t* skey[2] = {nullptr, nullptr};   // dense, radix ping-pong
     uint32_t* sval[2] = {nullptr, nullptr};
+    uint32_t* stage_key = nullptr;            // per-wave segments
+    uint32_t* stage_val = nullptr;
+    int64_t* seg_base = nullptr;
+    uint32_t* seg_count = nullptr;
+    uint32_t* pref = nullptr;
+    int64_t stage_cap = 0;                    // fixed segments + pool
     int64_t* q_t = nullptr;
     uint16_t* q_x = nullptr;
     uint16_t* q_y = nullptr;
     int8_t* q_p = nullptr;
-    uint64_t* tile_status = nullptr;
-    uint32_t* step_tile_ctr = nullptr;
     uint32_t* hist = nullptr;
     uint32_t* pass_status = nullptr;
     uint32_t* pass_ctr = nullptr;
@@ -112,8 +115,9 @@ void free_all(nsim_ev* h) {
                     h->prev[1], h->tlast[0], h->tlast[1], h->cpos_map,
                     h->cneg_map, h->skey[0], h->skey[1], h->sval[0],
                     h->sval[1], h->q_t, h->q_x, h->q_y, h->q_p,
-                    h->tile_status, h->step_tile_ctr, h->hist, h->pass_status,
-                    h->pass_ctr};
+                    h->stage_key, h->stage_val, h->seg_base, h->seg_count,
+                    h->pref, h->hist,
+                    h->pass_status, h->pass_ctr};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hdr_host) (void)hipHostFree(h->hdr_host);
@@ -199,8 +203,8 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
             const int64_t gap = t_us[i] - prev_t;
             if (t_us[i] <= prev_t)
                 return fail(h, NSIM_EINVAL, "timestamps must strictly increase");
-            if (gap >= (int64_t(1) << 30))
-                return fail(h, NSIM_EINVAL, "frame gap must be below 2^30 us");
+            if (gap > nsim::kMaxLaunchSpan)
+                return fail(h, NSIM_EINVAL, "frame gap must be below 2^25 us");
         }
         prev_t = t_us[i];
     }
@@ -229,13 +233,15 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
     while (k < K) {
         const int64_t T0 = h->t_expect;
         int32_t kl = 0;
+        // automatic mode: 64 frames per launch (amortises the per-pixel
+        // state round trip while keeping the wave's staged events in LDS),
+        // fewer once the time span needs a third radix digit
         const int32_t cap_frames =
-            h->max_frames > 0 ? h->max_frames : nsim::kMaxFramesPerLaunch;
+            h->max_frames > 0 ? h->max_frames : nsim::kAutoFramesPerLaunch;
         while (k + kl < K && kl < cap_frames) {
             const int64_t span = t_us[k + kl] - T0;
-            if (span >= (int64_t(1) << 30)) break;
-            // automatic mode: keep two radix passes once 32 frames are in
-            if (h->max_frames == 0 && kl >= 32 && span > 65535) break;
+            if (span > nsim::kMaxLaunchSpan) break;
+            if (h->max_frames == 0 && kl >= 8 && span > 65535) break;
             ++kl;
         }
         if (kl == 0) kl = 1;  // a single frame always fits (gap < 2^30)
@@ -245,7 +251,7 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
         a.K = kl;
         a.P = h->P;
         a.width = h->W;
-        a.ntiles = h->ntiles;
+        a.nwaves = h->nwaves;
         a.L_init = h->L_init;
         for (int i = 0; i < 2; ++i) {
             a.nud[i] = h->nud[i];
@@ -264,19 +270,12 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
         const double amax =
             std::max(std::fabs((double)T0), std::fabs((double)tmax));
         a.eT = (float)std::max(0x1p-12, amax * 0x1p-51);
-        a.out_key = h->skey[0];
-        a.out_val = h->sval[0];
-        a.out_cap = h->scap;
+        a.out_key = h->stage_key;
+        a.out_val = h->stage_val;
+        a.out_cap = h->stage_cap;
+        a.seg_base = h->seg_base;
+        a.seg_count = h->seg_count;
         a.hdr = h->hdr;
-        a.tile_status = h->tile_status;
-        a.tile_ctr = h->step_tile_ctr;
-        h->epoch += 1;
-        if (h->epoch >= (1u << 30)) {
-            NSIM_HIP(h, hipMemsetAsync(h->tile_status, 0,
-                                       sizeof(uint64_t) * h->ntiles, h->stream));
-            h->epoch = 1;
-        }
-        a.epoch = h->epoch;
         a.flags = h->flags;
         for (int32_t i = 0; i < kl; ++i) a.toff[i] = (int32_t)(t_us[k + i] - T0);
 
@@ -295,17 +294,30 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
         const int64_t span = a.toff[kl - 1];
         const int nbits = bits_for(span);
         const int npass = (nbits + nsim::kDigitBits - 1) / nsim::kDigitBits;
-        nsim::HistArgs ha{};
-        ha.keys = h->skey[0];
-        ha.hdr = h->hdr;
-        ha.scratch_cap = h->scap;
-        ha.qcap = h->qcap;
-        ha.npass = npass;
-        ha.hist = h->hist;
-        ha.status = h->pass_status;
-        ha.max_tiles = h->max_sort_tiles;
-        ha.pass_ctr = h->pass_ctr;
-        NSIM_HIP(h, nsim::launch_hist(ha, h->stream));
+        nsim::ScanArgs sa{};
+        sa.seg_count = h->seg_count;
+        sa.pref = h->pref;
+        sa.nwaves = h->nwaves;
+        sa.hdr = h->hdr;
+        NSIM_HIP(h, nsim::launch_scan(sa, h->stream));
+        nsim::GatherArgs ga{};
+        ga.seg_base = h->seg_base;
+        ga.seg_count = h->seg_count;
+        ga.pref = h->pref;
+        ga.nwaves = h->nwaves;
+        ga.npass = npass;
+        ga.skey = h->stage_key;
+        ga.sval = h->stage_val;
+        ga.dkey = h->skey[0];
+        ga.dval = h->sval[0];
+        ga.hdr = h->hdr;
+        ga.scratch_cap = h->scap;
+        ga.qcap = h->qcap;
+        ga.hist = h->hist;
+        ga.status = h->pass_status;
+        ga.max_tiles = h->max_sort_tiles;
+        ga.pass_ctr = h->pass_ctr;
+        NSIM_HIP(h, nsim::launch_gather(ga, h->stream));
         for (int p = 0; p < npass; ++p) {
             nsim::PassArgs pa{};
             pa.kin = h->skey[p & 1];
@@ -338,7 +350,6 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
         ca.t_first = t_us[k];
         ca.pixel_updates = P * kl;
         ca.hist = h->hist;
-        ca.step_tile_ctr = h->step_tile_ctr;
         NSIM_HIP(h, nsim::launch_commit(ca, h->stream));
 
         h->stats.step_launches += 1;
@@ -401,7 +412,7 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out) {
     h->qcap = cfg->capacity_events;
     h->scap = cfg->capacity_events;
     h->max_frames = cfg->max_frames_per_launch;
-    h->ntiles = (h->P + nsim::kStepThreads - 1) / nsim::kStepThreads;
+    h->nwaves = (h->P + nsim::kWave - 1) / nsim::kWave;
     h->max_sort_tiles = (h->scap + nsim::kSortTile - 1) / nsim::kSortTile + 1;
 
     const int64_t P = h->P;
@@ -426,8 +437,12 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out) {
     chk(dmalloc(&h->q_x, h->qcap));
     chk(dmalloc(&h->q_y, h->qcap));
     chk(dmalloc(&h->q_p, h->qcap));
-    chk(dmalloc(&h->tile_status, h->ntiles));
-    chk(dmalloc(&h->step_tile_ctr, 1));
+    h->stage_cap = (int64_t)h->nwaves * nsim::kStepLdsEntries + h->scap;
+    chk(dmalloc(&h->stage_key, h->stage_cap));
+    chk(dmalloc(&h->stage_val, h->stage_cap));
+    chk(dmalloc(&h->seg_base, h->nwaves));
+    chk(dmalloc(&h->seg_count, h->nwaves));
+    chk(dmalloc(&h->pref, h->nwaves));
     chk(dmalloc(&h->hist, nsim::kMaxPasses * nsim::kDigits));
     chk(dmalloc(&h->pass_status,
                 (size_t)nsim::kMaxPasses * h->max_sort_tiles * nsim::kDigits));
@@ -444,7 +459,6 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out) {
     }
     hipStream_t s = h->stream;
     chk(hipMemsetAsync(h->hdr, 0, sizeof(Header), s));
-    chk(hipMemsetAsync(h->tile_status, 0, sizeof(uint64_t) * h->ntiles, s));
     chk(hipMemsetAsync(h->pass_ctr, 0, sizeof(uint32_t) * nsim::kMaxPasses, s));
     if (h->has_map) {
         chk(hipMemcpyAsync(h->cpos_map, cfg->c_pos_map, sizeof(float) * P,
@@ -452,7 +466,7 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out) {
         chk(hipMemcpyAsync(h->cneg_map, cfg->c_neg_map, sizeof(float) * P,
                            hipMemcpyDeviceToDevice, s));
     }
-    chk(nsim::launch_reset_header(h->hdr, h->hist, h->step_tile_ctr, s));
+    chk(nsim::launch_reset_header(h->hdr, h->hist, s));
     chk(hipStreamSynchronize(s));
     if (e != hipSuccess) {
         free_all(h);
@@ -547,8 +561,7 @@ int nsim_ev_committed_time(nsim_ev_t* h, int64_t* t_us) {
 int nsim_ev_reset(nsim_ev_t* h) {
     if (!h) return NSIM_EINVAL;
     DeviceGuard dg(h->device);
-    NSIM_HIP(h, nsim::launch_reset_header(h->hdr, h->hist, h->step_tile_ctr,
-                                          h->stream));
+    NSIM_HIP(h, nsim::launch_reset_header(h->hdr, h->hist, h->stream));
     h->initialized = false;
     h->t_expect = 0;
     return NSIM_OK;
@@ -638,6 +651,7 @@ int nsim_ev_get_stats(nsim_ev_t* h, nsim_ev_stats* out) {
     h->stats.events = h->hdr_host->events_total;
     h->stats.fp64_evaluations = h->hdr_host->fp64_evals;
     h->stats.packed_event_bytes = 8 * h->hdr_host->events_total;
+    for (int i = 0; i < 8; ++i) h->stats.diag[i] = h->hdr_host->diag[i];
     *out = h->stats;
     return NSIM_OK;
 }

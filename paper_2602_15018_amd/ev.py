@@ -68,10 +68,13 @@ class Stats(ctypes.Structure):
         ("fp64_evaluations", ctypes.c_int64),
         ("sort_passes", ctypes.c_int64),
         ("packed_event_bytes", ctypes.c_int64),
+        ("diag", ctypes.c_int64 * 8),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["diag"] = list(d["diag"])
+        return d
 
 
 _lib = None
