@@ -58,7 +58,33 @@ def parse():
                     help="frame intervals of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-frames-per-launch", type=int, default=0)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="first run a plain 1 GiB device copy (the reference "
+                         "dispatch that scales profiler byte counters)")
     return ap.parse_args()
+
+
+TRAFFIC_FILE = os.path.join(ROOT, "profiles",
+                            "step_kernel_hd1280x720_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_2602_15018_amd", "csrc",
+                          "ev_kernels.hip")
+
+
+def kernel_hash():
+    import hashlib
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per step-kernel launch from the committed counter profile,
+    or None when it was taken on a different kernel source."""
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_hash") != kernel_hash():
+        return None
+    return rec.get("bytes_per_launch")
 
 
 def cpu_baseline(frames_dev, t, cp, cn, w, n_intervals):
@@ -106,6 +132,13 @@ def main():
     from paper_2602_15018_amd.ev import EventSim
 
     dev = torch.device("cuda", 0)
+    if args.calib_copy:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration copy: 1 GiB read + 1 GiB written")
     w = scene.WORKLOADS[WORKLOAD]
     F = args.frames or w.frames
     t = scene.frame_times(w, 0, F)
@@ -193,7 +226,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": measured_traffic(),
             "avg_launch_ms": k1_ms,
             "alg_bytes_per_launch": alg_bytes_launch,
             "launches_per_step": launches_per_step,
