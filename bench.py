@@ -58,6 +58,11 @@ def parse():
                     help="frame intervals of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-frames-per-launch", type=int, default=0)
+    ap.add_argument("--workload", default="hd",
+                    choices=["hd", "batch64"],
+                    help="hd: the 1280x720 stream (default); batch64: 64 "
+                         "environments of uneven size stepped together, "
+                         "against the same environments as separate streams")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (the reference "
                          "dispatch that scales profiler byte counters)")
@@ -120,16 +125,181 @@ def cpu_baseline(frames_dev, t, cp, cn, w, n_intervals):
     }
 
 
+def make_sim(w, F, cp, cn, max_frames_per_launch=0):
+    """The event path exactly as the benchmark times it: queue sized for the
+    whole stream, default frames per launch unless overridden."""
+    from paper_2602_15018_amd.ev import EventSim
+
+    est_events = int(0.09 * w.pixels * (F - 1)) + (1 << 20)
+    cap = min(est_events, (1 << 30) - 1)
+    sim = EventSim(w.width, w.height, c_pos_map=cp, c_neg_map=cn,
+                   log_eps=w.log_eps, refractory_us=w.refractory_us,
+                   capacity_events=cap,
+                   max_frames_per_launch=max_frames_per_launch)
+    return sim, cap
+
+
+def bench_batch(args):
+    """64 environments of uneven resolution, one frame per call (the
+    reinforcement-learning pattern), 500 frames at 1000 FPS.  One timed step
+    = the whole 500-frame run of the batch (reset, 500 calls; every call's
+    events left on the device for a consumer).  Beside it: the same
+    environments as 64 separate streams, each stepped once per frame in
+    turn, and the step kernel's HBM roofline in the batch."""
+    import torch
+
+    from paper_2602_15018_amd import scene
+    from paper_2602_15018_amd.ev import EventBatch
+
+    dev = torch.device("cuda", 0)
+    ws = scene.batch_envs()
+    F = args.frames or ws[0].frames
+    t = scene.frame_times(ws[0], 0, F)
+    envs = []
+    for w in ws:
+        cp, cn = scene.threshold_maps(w)
+        envs.append(dict(width=w.width, height=w.height, c_pos_map=cp,
+                         c_neg_map=cn))
+    log("rendering %d frames of %d environments" % (F, len(ws)))
+    flat = scene.render_batch(ws, 0, F, device=dev)
+    torch.cuda.synchronize()
+    total = flat.shape[1]
+    log("frames resident (%.2f GB)" % (flat.numel() * 4 / 1e9))
+    cap = int(0.2 * total) + (1 << 20)
+    b = EventBatch(envs, refractory_us=100, capacity_events=cap)
+
+    def run_batch(bb):
+        bb.reset()
+        for k in range(F):
+            bb.step(flat[k:k + 1], t[k:k + 1])
+
+    for _ in range(args.warmup):
+        run_batch(b)
+        b.sync()
+    log("tuning: %s" % json.dumps(b.tuning()))
+    base = b.stats()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_batch(b)
+    b.sync()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = b.stats()
+    tun = b.tuning()
+    b.close()
+    ms_batch = el * 1e3 / args.steps
+    pu = total * (F - 1)
+    ev_step = (st["events"] - base["events"]) / args.steps
+
+    # step kernel alone (direct launches, same knobs, HIP events on the
+    # batch's stream)
+    bp = EventBatch(envs, refractory_us=100, capacity_events=cap,
+                    autotune=False, stage_entries=tun["stage_entries"],
+                    waves_per_block=tun["waves_per_block"],
+                    step_blocks=tun["step_blocks"], use_graph=0)
+    run_batch(bp)
+    bp.sync()
+    s0 = bp.stats()
+    bp.set_profiling(True)
+    run_batch(bp)
+    bp.sync()
+    s1 = bp.stats()
+    bp.close()
+    k1_ms = (s1["step_kernel_ms"] - s0["step_kernel_ms"]) / max(
+        1, s1["step_timed"] - s0["step_timed"])
+    launches = s1["step_launches"] - s0["step_launches"]
+    ev_prof = s1["events"] - s0["events"]
+    alg = (total * (FRAME_B + STATE_READ_B + STATE_WRITE_B) +
+           PACKED_EVENT_B * ev_prof / max(1, launches))
+    achieved = alg / (k1_ms * 1e-3) / 1e9
+
+    # the same environments as separate streams, stepped in turn
+    from paper_2602_15018_amd.ev import EventSim
+    offs = np.cumsum([0] + [w.pixels for w in ws])
+    sims = [EventSim(w.width, w.height, c_pos_map=e["c_pos_map"],
+                     c_neg_map=e["c_neg_map"], refractory_us=100,
+                     capacity_events=max(1 << 16, int(0.2 * w.pixels) * 4))
+            for w, e in zip(ws, envs)]
+    views = [flat[:, offs[i]:offs[i + 1]].reshape(F, w.height, w.width)
+             for i, w in enumerate(ws)]
+
+    def run_plain():
+        for s_ in sims:
+            s_.reset()
+        for k in range(F):
+            for i, s_ in enumerate(sims):
+                s_.step(views[i][k:k + 1], t[k:k + 1])
+                if k % 16 == 15:
+                    s_.drain()
+
+    run_plain()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    run_plain()
+    for s_ in sims:
+        s_.sync()
+    torch.cuda.synchronize()
+    el_plain = time.perf_counter() - t1
+    for s_ in sims:
+        s_.close()
+
+    result = {
+        "metric": METRIC,
+        "value": pu * args.steps / el / 1e9,
+        "unit": "Gpixel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_batch,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": scene.BATCH_WORKLOAD,
+            "environments": len(ws), "pixels_per_frame": total,
+            "frames": F, "fps": ws[0].fps, "frames_per_call": 1,
+            "refractory_us": 100, "threshold_mismatch": True,
+        },
+        "events_per_s": ev_step * args.steps / el,
+        "events_per_step": ev_step,
+        "us_per_call": ms_batch * 1e3 / F,
+        "tuning": {k: tun[k] for k in ("stage_entries", "waves_per_block",
+                                       "step_blocks", "use_graph")},
+        "plain_separate_streams": {
+            "ms_per_step": el_plain * 1e3,
+            "value": pu / el_plain / 1e9,
+            "speedup_of_batch": el_plain * 1e3 / ms_batch,
+        },
+        "roofline": {
+            "kernel": "step_kernel",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_ms": k1_ms,
+            "alg_bytes_per_launch": alg,
+        },
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print("bench.py runs on one GPU only; this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batch64":
+        bench_batch(args)
+        return
     import torch
 
     from paper_2602_15018_amd import scene
-    from paper_2602_15018_amd.ev import EventSim
 
     dev = torch.device("cuda", 0)
     if args.calib_copy:
@@ -149,12 +319,7 @@ def main():
     torch.cuda.synchronize()
     log("frames resident (%.2f GB)" % (frames.numel() * 4 / 1e9))
 
-    est_events = int(0.09 * w.pixels * (F - 1)) + (1 << 20)
-    cap = min(est_events, (1 << 30) - 1)
-    sim = EventSim(w.width, w.height, c_pos_map=cp, c_neg_map=cn,
-                   log_eps=w.log_eps, refractory_us=w.refractory_us,
-                   capacity_events=cap,
-                   max_frames_per_launch=args.max_frames_per_launch)
+    sim, cap = make_sim(w, F, cp, cn, args.max_frames_per_launch)
     out = (torch.empty(cap, dtype=torch.int64, device=dev),
            torch.empty(cap, dtype=torch.uint16, device=dev),
            torch.empty(cap, dtype=torch.uint16, device=dev),

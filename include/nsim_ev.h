@@ -2,9 +2,10 @@
  * nsim_ev.h -- C ABI of the MI355X DVS event generator (libnsim_ev.so).
  *
  * Operation (paper Sec. 2, event-camera simulation paragraph; Fig. 3
- * caption): "process a new intensity frame, trigger events based on the
- * contrast threshold model, update the internal pixel states, and output the
- * event stream".  Each pixel keeps the level of its last triggered event;
+ * caption): each new intensity frame is compared pixel by pixel with the
+ * contrast-threshold model, which triggers events, moves the per-pixel state
+ * and appends to the output stream.  Each pixel keeps the level of its last
+ * triggered event;
  * events are tuples (t, x, y, p) with t an integer number of microseconds and
  * p = +1 / -1 (Sec. 1, event tuple); every frame yields a variable number of
  * events (Sec. 2, kernel paragraph).
@@ -71,8 +72,9 @@ typedef struct nsim_ev_config {
 
 typedef struct nsim_ev nsim_ev_t;
 
-/* Create a stream.  Allocates state (about 28 B per pixel), scratch and the
- * event queue (13 B per event of capacity plus 16 B of sort scratch).
+/* Create a stream.  Allocates state (about 40 B per pixel with threshold
+ * maps), per-wave staging (8 KB per 64 pixels), and per event of capacity
+ * 13 B of queue plus 24 B of staging and sort scratch.
  * Returns NSIM_EINVAL for a bad config (out is set to NULL). */
 int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out);
 
@@ -152,6 +154,121 @@ typedef struct nsim_ev_stats {
 
 int nsim_ev_set_profiling(nsim_ev_t* h, int on);
 int nsim_ev_get_stats(nsim_ev_t* h, nsim_ev_stats* out);
+
+/* ------------------------------------------------------------------------
+ * Batched environments: many independent sensors stepped together, one per
+ * simulation instance (the paper collects reinforcement-learning rollouts
+ * from several concurrent instances on one GPU, appendix on the
+ * event-based RL setup).  Every environment has its own size, thresholds and pixel
+ * state; all share log_eps, refractory period, flags and the frame clock.
+ * One call steps all environments with one fused launch sequence, replayed
+ * from a HIP graph once captured; launch parameters are chosen by timing
+ * candidates on the first stepping call (autotuning), unless fixed.
+ *
+ * Frames: device float32 [K][total], total = sum of width*height, each flat
+ * frame the concatenation of the environments' row-major frames in order.
+ * Output of a call: the events of that call only (the previous call's
+ * output is replaced), ordered by (environment, t, y, x); environment e's
+ * events are [env_offsets[e], env_offsets[e+1]).
+ * ---------------------------------------------------------------------- */
+typedef struct nsim_evb nsim_evb_t;
+
+typedef struct nsim_evb_env {
+    int32_t width;            /* 1 .. 65535 */
+    int32_t height;           /* 1 .. 65535 */
+    float c_pos;              /* scalar thresholds if the maps are NULL */
+    float c_neg;
+    const float* c_pos_map;   /* device [height*width] or NULL; copied */
+    const float* c_neg_map;
+} nsim_evb_env;
+
+typedef struct nsim_evb_config {
+    double log_eps;           /* as nsim_ev_config */
+    int64_t refractory_us;    /* as nsim_ev_config */
+    int64_t capacity_events;  /* most events one call may produce, < 2^30 */
+    uint32_t flags;           /* NSIM_INPUT_LOG | NSIM_FORCE_FP64 */
+    int32_t autotune;         /* 1: time candidates on the first stepping
+                                 call for every knob left at 0 / -1 */
+    int32_t stage_entries;    /* 0 = tuned/default, else 64 .. 2000 events
+                                 staged in LDS per 64 pixels */
+    int32_t waves_per_block;  /* 0 = tuned/default, else 1 .. 4 */
+    int32_t use_graph;        /* -1 = tuned/default (on), 0 off, 1 on */
+    int32_t step_blocks;      /* -1 = tuned/default (0); 0 = one wave per
+                                 64-pixel tile; n > 0 = persistent grid of
+                                 n workgroups looping over the tiles */
+} nsim_evb_config;
+
+/* Create a batch of n_env (1 .. 4096) environments on `stream`.  The sum of
+ * pixels, padded to 64 per environment, must stay below 2^31.  Returns
+ * NSIM_EINVAL for a bad description (out set to NULL). */
+int nsim_evb_create(const nsim_evb_env* envs, int32_t n_env,
+                    const nsim_evb_config* cfg, void* stream,
+                    nsim_evb_t** out);
+
+/* Step every environment by K frames (device [K][total] as above, valid
+ * until the stream has executed the call) at the host timestamps t_us[K]
+ * (strictly increasing across calls).  The first frame ever only
+ * initialises.  The frames after it must fit one launch: at most 256 frames
+ * and a span t_us[K-1] - t_prev below 2^(32 - ceil(log2 n_env)) - 1 and
+ * below 2^25 - 1 microseconds; otherwise NSIM_EINVAL.  Asynchronous
+ * (except the autotuning call, which synchronises).  All-or-nothing as
+ * nsim_ev_step: on overflow nothing is committed, the output is empty and
+ * the next sync / drain reports NSIM_EOVERFLOW; later calls are no-ops
+ * until then. */
+int nsim_evb_step(nsim_evb_t* h, const float* frames, const int64_t* t_us,
+                  int32_t K);
+
+/* Synchronise and copy the last call's events to caller device arrays (t,
+ * x, y, p as nsim_ev_drain) and its n_env + 1 offsets to env_offsets
+ * (host).  *n_out (host) = number of events.  If cap is smaller, nothing is
+ * copied, *n_out tells the size needed and NSIM_EINVAL is returned.  Does
+ * not consume: the output stays until the next step call. */
+int nsim_evb_drain(nsim_evb_t* h, int64_t* env_offsets, int64_t* t,
+                   uint16_t* x, uint16_t* y, int8_t* p, int64_t cap,
+                   int64_t* n_out);
+
+/* Zero-copy view of the last call's output: device pointers to the event
+ * arrays and to the n_env + 1 int64 offsets (device; the event count is
+ * env_offsets[n_env]).  No synchronisation: the contents are valid once the
+ * stream has executed the call, until the next step call is enqueued. */
+int nsim_evb_events(nsim_evb_t* h, const int64_t** t, const uint16_t** x,
+                    const uint16_t** y, const int8_t** p,
+                    const int64_t** env_offsets);
+
+/* Synchronise; returns the sticky error, if any. */
+int nsim_evb_sync(nsim_evb_t* h);
+
+/* Drop pixel state and output; the next call starts new streams. */
+int nsim_evb_reset(nsim_evb_t* h);
+
+/* Synchronise, free everything (graphs included).  Accepts NULL. */
+int nsim_evb_destroy(nsim_evb_t* h);
+
+const char* nsim_evb_last_error(const nsim_evb_t* h);
+
+/* Launch parameters in use, and how they were chosen. */
+typedef struct nsim_evb_tuning {
+    int32_t stage_entries;
+    int32_t waves_per_block;
+    int32_t use_graph;
+    int32_t step_blocks;
+    int32_t tuned;            /* 1 if chosen by timing */
+    int32_t n_candidates;     /* timed candidates (at most 32) */
+    float candidate_ms[32];   /* best time of each candidate's launch
+                                 sequence, ms */
+    int32_t candidate_stage[32];
+    int32_t candidate_waves[32];
+    int32_t candidate_blocks[32];
+    int32_t candidate_graph[32];
+} nsim_evb_tuning;
+
+int nsim_evb_get_tuning(nsim_evb_t* h, nsim_evb_tuning* out);
+
+/* Counters as nsim_ev_stats; with profiling on, step_kernel_ms times the
+ * step kernel of each call (direct launches) or the whole launch sequence
+ * (graph replay). */
+int nsim_evb_set_profiling(nsim_evb_t* h, int on);
+int nsim_evb_get_stats(nsim_evb_t* h, nsim_ev_stats* out);
 
 /* Diagnostic: out[i] = the step kernel's FP32 base-2 logarithm of x[i]
  * (device arrays of n floats), so its error bound can be checked. */

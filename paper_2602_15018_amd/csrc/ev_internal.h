@@ -8,9 +8,12 @@
 namespace nsim {
 
 constexpr int kWave = 64;
-constexpr int kStepThreads = 256;            // 4 waves, one pixel per lane
-constexpr int kStepWaves = kStepThreads / kWave;
-constexpr int kStepLdsEntries = 2000;        // staged events per wave (4 B each)
+constexpr int kStepMaxThreads = 256;         // at most 4 waves per workgroup
+constexpr int kStepWaves = 4;                // default waves per workgroup
+constexpr int kStepLdsEntries = 2000;        // default staged events per wave
+constexpr int kStepMaxLdsEntries = 2000;     // (4 B each, in LDS)
+constexpr int kScanTile = 1024;              // per-wave counts per scan block
+constexpr int kMaxEnvs = 4096;
 constexpr int kChunk = 8;                     // frames prefetched per chunk
 constexpr int kMaxFramesPerLaunch = 256;
 constexpr int kAutoFramesPerLaunch = 64;
@@ -22,6 +25,18 @@ constexpr int kDigits = 1 << kDigitBits;
 constexpr int kMaxPasses = 4;
 constexpr int32_t kTlastNone = -(1 << 30);   // no emitted event that matters
 constexpr int64_t kMaxLaunchSpan = (int64_t(1) << 25) - 2;  // us per launch
+
+// One environment of a batch: its pixels occupy waves [wave0, wave0 +
+// ceil(npix / 64)) of the padded pixel space (state arrays are indexed by
+// wave * 64 + lane), and samples [frame_off, frame_off + npix) of every flat
+// frame.  A single stream is a batch of one environment.
+struct EnvRec {
+    int64_t frame_off;
+    int32_t wave0;
+    int32_t npix;
+    int32_t width;
+    int32_t height;
+};
 
 // Device-resident stream header.  Written by kernels, read by the host only
 // after a stream synchronisation.
@@ -49,15 +64,18 @@ struct alignas(64) Header {
 
 // Arguments of the fused step kernel.  Frame times travel by value.  Each
 // wave of 64 pixels is independent: it owns the staging segment
-// [wave * kStepLdsEntries, +kStepLdsEntries); a wave whose events outgrow its
+// [wave * stage_entries, +stage_entries); a wave whose events outgrow its
 // LDS staging takes a segment from the overflow pool behind the fixed
 // segments with one atomic.  (base, count) go to seg_base / seg_count.
 struct StepArgs {
-    const float* frames;   // [K][P]
+    const float* frames;   // [K][frame_stride]
+    int64_t frame_stride;  // samples per flat frame (all environments)
     int32_t K;
-    int32_t P;
-    int32_t width;
-    int32_t nwaves;        // ceil(P / 64)
+    int32_t nwaves;        // waves of the padded pixel space
+    const EnvRec* envs;
+    const int32_t* wave_env;  // [nwaves] environment of each wave
+    int32_t stage_entries; // LDS staging entries per wave (<= 2000)
+    int32_t key_tbits;     // key = env << key_tbits | time offset
     const double* L_init;  // [P]
     int2* nud[2];          // (n_up, n_down) [P], ping-pong
     float* prev[2];        // previous sample (I or L) [P], ping-pong
@@ -72,7 +90,7 @@ struct StepArgs {
     int64_t T0;            // absolute time of the frame before frames[0]
     float eT;              // absolute-time rounding allowance of FP64 tau
     float pad0;
-    uint32_t* out_key;     // staging: key = t - T0
+    uint32_t* out_key;     // staging: key as above
     uint32_t* out_val;     //          val = pixel << 1 | (p > 0)
     int64_t out_cap;       // staging entries: fixed segments + overflow pool
     int64_t* seg_base;     // [nwaves] first staging entry of the wave
@@ -83,11 +101,15 @@ struct StepArgs {
     int32_t toff[kMaxFramesPerLaunch];  // frame k time minus T0
 };
 
-// Exclusive scan of the per-wave event counts (wave order = pixel order).
+// Exclusive scan of the per-wave event counts (wave order = pixel order),
+// in blocks of kScanTile counts: block sums first, then every block adds the
+// sums of the blocks before it.
 struct ScanArgs {
     const uint32_t* seg_count;
     uint32_t* pref;
     int32_t nwaves;
+    int32_t restart_queue; // 1: this step's output starts the queue afresh
+    uint64_t* tile_sum;    // [ceil(nwaves / kScanTile)]
     Header* hdr;
 };
 
@@ -113,9 +135,11 @@ struct GatherArgs {
 };
 
 struct InitArgs {
-    const float* frame;
-    int32_t P;
+    const float* frame;    // one flat frame
+    int32_t nwaves;
     uint32_t flags;
+    const EnvRec* envs;
+    const int32_t* wave_env;
     double log_eps;
     double* L_init;
     int2* nud[2];
@@ -123,6 +147,8 @@ struct InitArgs {
     int32_t* tlast[2];
     Header* hdr;
     int64_t t0;
+    int64_t* env_off;      // [n_env + 1] zeroed, or NULL
+    int32_t n_env;
 };
 
 struct PassArgs {
@@ -138,7 +164,8 @@ struct PassArgs {
     int32_t final_pass;
     int32_t shift;
     int32_t bits;
-    int32_t width;
+    int32_t key_tbits;
+    const EnvRec* envs;
     int64_t T0;
     const uint32_t* hist;    // this pass's digit counts
     uint32_t* status;        // this pass's [max_tiles][kDigits]
@@ -155,6 +182,11 @@ struct CommitArgs {
     int64_t t_first;         // absolute time of the step's first frame
     int64_t pixel_updates;
     uint32_t* hist;
+    int32_t dry;             // 1: timing trial, commit nothing
+    int32_t n_env;
+    int64_t* env_off;        // [n_env + 1] output offsets, or NULL
+    const uint32_t* pref;    // per-wave exclusive prefix of the step
+    const EnvRec* envs;
 };
 
 struct StateCopyArgs {
@@ -171,7 +203,7 @@ struct StateCopyArgs {
 // Launchers (ev_kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
-                       hipStream_t s);
+                       int waves_per_block, int max_blocks, hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, hipStream_t s);

@@ -76,6 +76,15 @@ __device__ __forceinline__ int64_t wave_sum64(int64_t v) {
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
     return v;
 }
+__device__ __forceinline__ uint64_t wave_incl_scan_u64(uint64_t v) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint64_t o = __shfl_up(v, d, kWave);
+        if (lane >= d) v += o;
+    }
+    return v;
+}
 
 __device__ __forceinline__ int wave_sum(int v) {
 #pragma unroll
@@ -335,11 +344,12 @@ __device__ __forceinline__ void exact_levels(Px& q, double eps) {
 
 // Copy a wave's staged entries to the packed output, dropping suppressed
 // crossings; returns the next output position.  Entry layout:
-// (time offset << 7) | (lane << 1) | (p > 0).
+// (time offset << 7) | (lane << 1) | (p > 0); the output key is the time
+// offset under the environment's high bits.
 __device__ __forceinline__ int64_t flush_wave(const uint32_t* buf, int count,
-                                              uint32_t pix0, uint32_t* okey,
-                                              uint32_t* oval, int64_t g,
-                                              int64_t cap) {
+                                              uint32_t pix0, uint32_t key_hi,
+                                              uint32_t* okey, uint32_t* oval,
+                                              int64_t g, int64_t cap) {
     const uint64_t lt = lanemask_lt();
     for (int j0 = 0; j0 < count; j0 += kWave) {
         const int j = j0 + lane_id();
@@ -349,7 +359,7 @@ __device__ __forceinline__ int64_t flush_wave(const uint32_t* buf, int count,
         const uint64_t m = __ballot(v);
         const int64_t pos = g + __popcll(m & lt);
         if (v && pos < cap) {
-            okey[pos] = e >> 7;
+            okey[pos] = key_hi | (e >> 7);
             oval[pos] = ((pix0 + ((e >> 1) & 63u)) << 1) | (e & 1u);
         }
         g += __popcll(m);
@@ -363,17 +373,17 @@ __device__ __forceinline__ int64_t flush_wave(const uint32_t* buf, int count,
 // buffer to global memory whenever it fills.
 template <bool LOGIN, bool RERUN>
 __device__ __forceinline__ void walk_frames(
-    const StepArgs& a, Px& q, bool valid, int pix, uint32_t pix0,
-    uint32_t* buf, float* fslab, int& cursor, bool& over, int& emitted,
-    int& f64count, int64_t& gpos, int* dg) {
+    const StepArgs& a, Px& q, bool valid, const float* fr, uint32_t pix0,
+    uint32_t key_hi, uint32_t* buf, float* fslab, int& cursor, bool& over,
+    int& emitted, int& f64count, int64_t& gpos, int* dg) {
     const float eps_f = a.log_eps_f;
     const double eps = a.log_eps;
     const int tref = a.tref;
     const bool force64 = (a.flags & 0x2u) != 0;
     const uint32_t lane_bits = ((uint32_t)lane_id()) << 1;
-    const float* fr = a.frames + pix;
-    const int64_t P = a.P;
+    const int64_t P = a.frame_stride;
     const int K = a.K;
+    const int S = a.stage_entries;
 
     // Frames are prefetched a chunk of kChunk frames ahead into registers;
     // at the start of each chunk the registers (loaded one chunk earlier)
@@ -514,17 +524,18 @@ __device__ __forceinline__ void walk_frames(
                     int win_cap;  // writable entries in this window
                     bool write;
                     if (!RERUN) {
-                        write = !over && (cursor + total <= kStepLdsEntries);
+                        write = !over && (cursor + total <= S);
                         if (!write) over = true;
                         win_cap = total;
                     } else {
-                        if (cursor + total > kStepLdsEntries) {
-                            gpos = flush_wave(buf, cursor, pix0, a.out_key,
-                                              a.out_val, gpos, a.out_cap);
+                        if (cursor + total > S) {
+                            gpos = flush_wave(buf, cursor, pix0, key_hi,
+                                              a.out_key, a.out_val, gpos,
+                                              a.out_cap);
                             cursor = 0;
                         }
                         write = true;
-                        win_cap = total < kStepLdsEntries ? total : kStepLdsEntries;
+                        win_cap = total < S ? total : S;
                     }
                     for (;;) {
                         q.tlast = tl0;
@@ -589,8 +600,9 @@ __device__ __forceinline__ void walk_frames(
                             cursor += used;
                             win_lo += win_cap;
                             if (win_lo >= total) break;
-                            gpos = flush_wave(buf, cursor, pix0, a.out_key,
-                                              a.out_val, gpos, a.out_cap);
+                            gpos = flush_wave(buf, cursor, pix0, key_hi,
+                                              a.out_key, a.out_val, gpos,
+                                              a.out_cap);
                             cursor = 0;
                         }
                     }
@@ -634,26 +646,25 @@ __device__ uint64_t g_tile_trace[1 << 17][8];
     } while (0)
 #endif
 
-// One wave = 64 consecutive pixels, fully independent of every other wave:
-// it walks the launch's frames, reserves a segment of the staging arrays for
-// its events with one atomic, and writes them there in (frame, pixel, k)
-// order.  The scan and gather kernels restore pixel-block order afterwards.
+// One tile = one wave of 64 consecutive pixels of one environment, fully
+// independent of every other tile: the wave walks the launch's frames,
+// stages its events in LDS in (frame, pixel, k) order and writes them to the
+// tile's own staging segment (or one from the overflow pool).  The scan and
+// gather kernels restore pixel-block order afterwards.
 template <bool LOGIN, bool MAP>
-__global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs a) {
-    __shared__ uint32_t s_buf[kStepWaves][kStepLdsEntries];
-    __shared__ float s_frames[kStepWaves][kChunk * kWave];
-
+__device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
+                                          uint32_t* buf, float* fslab) {
     Header* hdr = a.hdr;
-    const int w = threadIdx.x / kWave;
     const int lane = lane_id();
-    const int wid = blockIdx.x * kStepWaves + w;
-    if (wid >= a.nwaves) return;
-    if (hdr->status != 0) return;
     TILE_STAMP(0);
-    const int cur = hdr->cur;
+    const int env = a.wave_env[wid];
+    const EnvRec er = a.envs[env];
+    const int local = (wid - er.wave0) * kWave + lane;
     const int pix = wid * kWave + lane;
     const uint32_t pix0 = (uint32_t)(wid * kWave);
-    const bool valid = pix < a.P;
+    const bool valid = local < er.npix;
+    const float* fr = a.frames + er.frame_off + local;
+    const uint32_t key_hi = (uint32_t)env << a.key_tbits;
 
     Px q;
     load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
@@ -661,13 +672,12 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs a) {
                       a.c_pos, a.c_neg, pix, valid, a.log_eps);
 
     TILE_STAMP(1);
-    uint32_t* buf = s_buf[w];
     int cursor = 0, emitted = 0, f64count = 0;
     bool over = false;
     int64_t gdummy = 0;
     int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    walk_frames<LOGIN, false>(a, q, valid, pix, pix0, buf, s_frames[w], cursor,
-                              over, emitted, f64count, gdummy, dg);
+    walk_frames<LOGIN, false>(a, q, valid, fr, pix0, key_hi, buf, fslab,
+                              cursor, over, emitted, f64count, gdummy, dg);
     dg[2] = over ? 1 : 0;
     TILE_STAMP(2);
 
@@ -683,7 +693,9 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs a) {
         a.tlast[nxt][pix] = tl;
     }
 
-    const int wemit = wave_sum(emitted);
+    // (64-bit: pathological inputs may exceed 2^31 crossings per wave; the
+    // count saturates and the step then reports an overflow)
+    const int64_t wemit = wave_sum64(emitted);
     const int wf64 = wave_sum(f64count);
 #ifdef NSIM_STEP_DIAG
     {
@@ -699,17 +711,17 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs a) {
     }
 #endif
     // this wave's staging segment: its fixed one, or one from the pool
-    int64_t base = (int64_t)wid * kStepLdsEntries;
+    int64_t base = (int64_t)wid * a.stage_entries;
     if (over) {
         uint64_t b = 0;
         if (lane == 0)
             b = atomicAdd((unsigned long long*)&hdr->alloc,
                           (unsigned long long)wemit);
-        base = (int64_t)a.nwaves * kStepLdsEntries + (int64_t)__shfl(b, 0, kWave);
+        base = (int64_t)a.nwaves * a.stage_entries + (int64_t)__shfl(b, 0, kWave);
     }
     if (lane == 0) {
         a.seg_base[wid] = base;
-        a.seg_count[wid] = (uint32_t)wemit;
+        a.seg_count[wid] = (uint32_t)(wemit < 0xFFFFFFFFll ? wemit : 0xFFFFFFFFll);
         if (wf64)
             atomicAdd((unsigned long long*)&hdr->fp64_evals,
                       (unsigned long long)wf64);
@@ -718,7 +730,8 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs a) {
     if (base + wemit > a.out_cap) return;  // the step overflows anyway
     int64_t g = base;
     if (!over) {
-        flush_wave(buf, cursor, pix0, a.out_key, a.out_val, g, a.out_cap);
+        flush_wave(buf, cursor, pix0, key_hi, a.out_key, a.out_val, g,
+                   a.out_cap);
     } else {
         // regenerate this wave's events from the launch's starting state
         load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
@@ -729,9 +742,10 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs a) {
         over = false;
         int e2 = 0, f2 = 0;
         int dg2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        walk_frames<LOGIN, true>(a, q, valid, pix, pix0, buf, s_frames[w], cursor,
-                                 over, e2, f2, g, dg2);
-        flush_wave(buf, cursor, pix0, a.out_key, a.out_val, g, a.out_cap);
+        walk_frames<LOGIN, true>(a, q, valid, fr, pix0, key_hi, buf, fslab,
+                                 cursor, over, e2, f2, g, dg2);
+        flush_wave(buf, cursor, pix0, key_hi, a.out_key, a.out_val, g,
+                   a.out_cap);
     }
     TILE_STAMP(4);
 #ifdef NSIM_TILE_TRACE
@@ -742,40 +756,84 @@ __global__ __launch_bounds__(kStepThreads) void step_kernel(const StepArgs a) {
 #endif
 }
 
-// Exclusive scan of the per-wave counts in wave (= pixel) order, one
-// workgroup: each thread sums a contiguous run, the runs are scanned in
-// LDS, then every thread writes its run's prefixes.
-__global__ __launch_bounds__(1024) void scan_kernel(const ScanArgs a) {
-    __shared__ uint64_t s_part[1024];
-    const int tid = threadIdx.x;
-    const int64_t n = a.nwaves;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t lo = tid * per;
-    const int64_t hi = lo + per < n ? lo + per : n;
-    uint64_t sum = 0;
-    for (int64_t i = lo; i < hi; ++i) sum += a.seg_count[i];
-    s_part[tid] = sum;
+// The step launch: a grid-stride loop of waves over the tiles of the padded
+// pixel space of all environments, so the same kernel runs as one wave per
+// tile or as a persistent grid sized to the chip.  LDS per wave (dynamic):
+// stage_entries 4-byte entries, then the kChunk x 64 frame slab.
+template <bool LOGIN, bool MAP>
+__global__ __launch_bounds__(kStepMaxThreads) void step_kernel(const StepArgs a) {
+    extern __shared__ uint32_t s_dyn[];
+    const int wpb = blockDim.x / kWave;
+    const int w = threadIdx.x / kWave;
+    if (a.hdr->status != 0) return;
+    const int cur = a.hdr->cur;
+    uint32_t* buf = s_dyn + w * (a.stage_entries + kChunk * kWave);
+    float* fslab = reinterpret_cast<float*>(buf + a.stage_entries);
+    const int stride = gridDim.x * wpb;
+    for (int wid = blockIdx.x * wpb + w; wid < a.nwaves; wid += stride)
+        step_tile<LOGIN, MAP>(a, wid, cur, buf, fslab);
+}
+
+// Exclusive scan of the per-wave counts in wave (= pixel) order, two
+// kernels over blocks of kScanTile counts.  scan_sum_kernel: one block sum
+// per tile.  scan_down_kernel: each block adds up the sums of the tiles
+// before it (a few thousand at most, read from L2), scans its own counts
+// with wave scans, and the last block publishes the step's total.
+__device__ __forceinline__ uint64_t block_sum64(uint64_t v, uint64_t* s_w) {
+    const int lane = lane_id(), w = threadIdx.x / kWave;
+    v = (uint64_t)wave_sum64((int64_t)v);
+    if (lane == 0) s_w[w] = v;
     __syncthreads();
-    for (int d = 1; d < 1024; d <<= 1) {
-        const uint64_t v = tid >= d ? s_part[tid - d] : 0;
-        __syncthreads();
-        s_part[tid] += v;
-        __syncthreads();
+    uint64_t t = 0;
+    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += s_w[i];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(kScanTile) void scan_sum_kernel(const ScanArgs a) {
+    __shared__ uint64_t s_w[kScanTile / kWave];
+    const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
+    const uint64_t c = i < a.nwaves ? a.seg_count[i] : 0u;
+    const uint64_t t = block_sum64(c, s_w);
+    if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(kScanTile) void scan_down_kernel(const ScanArgs a) {
+    __shared__ uint64_t s_w[kScanTile / kWave];
+    __shared__ uint64_t s_scan[kScanTile / kWave];
+    const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
+    uint64_t before = 0;
+    for (int64_t j = tid; j < blockIdx.x; j += kScanTile) before += a.tile_sum[j];
+    const uint64_t base = block_sum64(before, s_w);
+    const int64_t i = (int64_t)blockIdx.x * kScanTile + tid;
+    const uint32_t c = i < a.nwaves ? a.seg_count[i] : 0u;
+    const uint64_t incl = wave_incl_scan_u64(c);
+    if (lane == kWave - 1) s_scan[w] = incl;
+    __syncthreads();
+    uint64_t off = base;
+    for (int k = 0; k < w; ++k) off += s_scan[k];
+    const uint64_t ex = off + (incl - c);
+    if (i < a.nwaves) a.pref[i] = (uint32_t)(ex < 0xFFFFFFFFull ? ex : 0xFFFFFFFFull);
+    if (blockIdx.x == gridDim.x - 1 && tid == kScanTile - 1) {
+        a.hdr->n_step = (int64_t)(ex + c);
+        if (a.restart_queue) {
+            a.hdr->head = 0;
+            a.hdr->tail = 0;
+        }
     }
-    uint64_t run = s_part[tid] - sum;
-    for (int64_t i = lo; i < hi; ++i) {
-        a.pref[i] = (uint32_t)(run < 0xFFFFFFFFull ? run : 0xFFFFFFFFull);
-        run += a.seg_count[i];
-    }
-    if (tid == 1023) a.hdr->n_step = (int64_t)s_part[1023];
 }
 
 __global__ void init_kernel(const InitArgs a) {
     const int cur = a.hdr->cur;
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
     if (pix == 0) a.hdr->t_prev = a.t0;
-    if (pix >= a.P) return;
-    const float v = a.frame[pix];
+    if (a.env_off && pix <= a.n_env) a.env_off[pix] = 0;  // no output yet
+    const int wid = pix / kWave;
+    if (wid >= a.nwaves) return;
+    const EnvRec er = a.envs[a.wave_env[wid]];
+    const int local = pix - er.wave0 * kWave;
+    if (local >= er.npix) return;
+    const float v = a.frame[er.frame_off + local];
     const double L = (a.flags & 0x1u) ? (double)v : log((double)v + a.log_eps);
     a.L_init[pix] = L;
     a.nud[cur][pix] = make_int2(0, 0);
@@ -971,10 +1029,13 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
             if (a.final_pass) {
                 int64_t r = tailm + gpos;
                 if (r >= a.qcap) r -= a.qcap;
-                const uint32_t px = v >> 1;
-                a.t_out[r] = a.T0 + (int64_t)k;
-                a.x_out[r] = (uint16_t)(px % (uint32_t)a.width);
-                a.y_out[r] = (uint16_t)(px / (uint32_t)a.width);
+                const uint32_t env = k >> a.key_tbits;
+                const uint32_t toff = k & ((1u << a.key_tbits) - 1u);
+                const EnvRec er = a.envs[env];
+                const uint32_t px = (v >> 1) - (uint32_t)er.wave0 * kWave;
+                a.t_out[r] = a.T0 + (int64_t)toff;
+                a.x_out[r] = (uint16_t)(px % (uint32_t)er.width);
+                a.y_out[r] = (uint16_t)(px / (uint32_t)er.width);
                 a.p_out[r] = (v & 1u) ? (int8_t)1 : (int8_t)-1;
             } else {
                 a.kout[gpos] = k;
@@ -985,12 +1046,18 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
     }
 }
 
+// All-or-nothing end of a launch.  With env_off set it also publishes the
+// output offset of every environment (all zero when nothing was committed).
 __global__ void commit_kernel(const CommitArgs a) {
+    __shared__ int s_ok;
+    __shared__ int64_t s_n;
     Header* h = a.hdr;
     if (threadIdx.x == 0) {
         int64_t n;
         const bool ok = step_fits(h, a.scratch_cap, a.qcap, &n);
-        if (ok) {
+        if (a.dry) {
+            // timing trial: leave state, queue and status untouched
+        } else if (ok) {
             h->tail += n;
             h->cur ^= 1;
             h->t_prev = a.t_last;
@@ -999,10 +1066,20 @@ __global__ void commit_kernel(const CommitArgs a) {
             h->status = h->internal_err ? -5 : -3;
             h->dropped_t = a.t_first;
         }
+        s_ok = (ok && !a.dry) ? 1 : 0;
+        s_n = n;
         h->n_step = 0;
         h->alloc = 0;
     }
+    __syncthreads();
     for (int i = threadIdx.x; i < kMaxPasses * kDigits; i += blockDim.x) a.hist[i] = 0u;
+    if (a.env_off) {
+        for (int e = threadIdx.x; e <= a.n_env; e += blockDim.x) {
+            int64_t v = 0;
+            if (s_ok) v = e < a.n_env ? (int64_t)a.pref[a.envs[e].wave0] : s_n;
+            a.env_off[e] = v;
+        }
+    }
 }
 
 __global__ void reset_kernel(Header* h, uint32_t* hist) {
@@ -1065,30 +1142,43 @@ __global__ void fast_log2_kernel(const float* x, float* out, int64_t n) {
 }  // namespace
 
 hipError_t launch_init(const InitArgs& a, hipStream_t s) {
-    const int blocks = (a.P + 255) / 256;
+    const int blocks = (int)(((int64_t)a.nwaves * kWave + 255) / 256);
     hipLaunchKernelGGL(init_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
-                       hipStream_t s) {
-    const dim3 grid((a.nwaves + kStepWaves - 1) / kStepWaves), block(kStepThreads);
+                       int waves_per_block, int max_blocks, hipStream_t s) {
+    if (waves_per_block < 1 || waves_per_block * kWave > kStepMaxThreads ||
+        a.stage_entries < kWave || a.stage_entries > kStepMaxLdsEntries ||
+        max_blocks < 0)
+        return hipErrorInvalidValue;
+    int blocks = (a.nwaves + waves_per_block - 1) / waves_per_block;
+    if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
+    const dim3 grid(blocks);
+    const dim3 block(waves_per_block * kWave);
+    const size_t lds = (size_t)waves_per_block *
+                       (a.stage_entries + kChunk * kWave) * sizeof(uint32_t);
     if (log_input) {
         if (has_map)
-            hipLaunchKernelGGL((step_kernel<true, true>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((step_kernel<true, true>), grid, block, lds, s, a);
         else
-            hipLaunchKernelGGL((step_kernel<true, false>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((step_kernel<true, false>), grid, block, lds, s, a);
     } else {
         if (has_map)
-            hipLaunchKernelGGL((step_kernel<false, true>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((step_kernel<false, true>), grid, block, lds, s, a);
         else
-            hipLaunchKernelGGL((step_kernel<false, false>), grid, block, 0, s, a);
+            hipLaunchKernelGGL((step_kernel<false, false>), grid, block, lds, s, a);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, a);
+    const int tiles = (a.nwaves + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(scan_sum_kernel, dim3(tiles), dim3(kScanTile), 0, s, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(scan_down_kernel, dim3(tiles), dim3(kScanTile), 0, s, a);
     return hipGetLastError();
 }
 

@@ -18,10 +18,29 @@
 
 using nsim::Header;
 
+// Graph of one launch sequence (step, scan, gather, radix passes, commit)
+// for a given key width; per call only the step, final-pass and commit
+// nodes get new arguments.
+struct GraphSlot {
+    int nbits = 0, stage = 0, wpb = 0, blocks = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t n_step = nullptr, n_final = nullptr, n_commit = nullptr;
+    hipKernelNodeParams p_step{}, p_final{}, p_commit{};
+};
+
+// One stream or one batch of environments (a stream is a batch of one whose
+// output is a queue; a batch's output is the last call's events).
 struct nsim_ev {
     int device = 0;
     hipStream_t stream = nullptr;
-    int32_t W = 0, H = 0, P = 0;
+    bool batched = false;
+    int32_t n_env = 1;
+    int32_t env_bits = 0;              // ceil(log2 n_env)
+    std::vector<nsim::EnvRec> env_host;
+    int32_t W = 0, H = 0;              // single stream
+    int64_t P = 0;                     // pixels (all environments)
+    int64_t frame_stride = 0;          // samples per flat frame (= P)
     bool log_input = false, has_map = false;
     uint32_t flags = 0;
     float c_pos = 0.f, c_neg = 0.f;
@@ -30,11 +49,24 @@ struct nsim_ev {
     int64_t qcap = 0;     // queue capacity (events)
     int64_t scap = 0;     // per-launch scratch capacity (events)
     int32_t max_frames = 0;
-    int32_t nwaves = 0;
+    int32_t nwaves = 0;   // waves of the padded pixel space
     int64_t max_sort_tiles = 0;
+    int32_t stage_entries = nsim::kStepLdsEntries;
+    int32_t stage_alloc = nsim::kStepLdsEntries;   // staging sized for this
+    int32_t waves_per_block = nsim::kStepWaves;
+    int32_t step_blocks = 0;           // 0: one wave per tile; else persistent
+    int32_t n_cu = 256;
+    int32_t use_graph = 0;
+    bool autotune = false, tuned = false;
+    int32_t want_stage = 0, want_wpb = 0, want_graph = -1;  // caller's knobs
+    int32_t want_blocks = -1;
+    nsim_evb_tuning tuning{};
+    int64_t fp64_trial = 0;            // FP64 evaluations of timing trials
 
     // device memory
     Header* hdr = nullptr;
+    nsim::EnvRec* envs = nullptr;
+    int32_t* wave_env = nullptr;
     double* L_init = nullptr;
     int2* nud[2] = {nullptr, nullptr};
     float* prev[2] = {nullptr, nullptr};
@@ -48,6 +80,7 @@ struct nsim_ev {
     int64_t* seg_base = nullptr;
     uint32_t* seg_count = nullptr;
     uint32_t* pref = nullptr;
+    uint64_t* tile_sum = nullptr;
     int64_t stage_cap = 0;                    // fixed segments + pool
     int64_t* q_t = nullptr;
     uint16_t* q_x = nullptr;
@@ -56,6 +89,7 @@ struct nsim_ev {
     uint32_t* hist = nullptr;
     uint32_t* pass_status = nullptr;
     uint32_t* pass_ctr = nullptr;
+    int64_t* env_off = nullptr;               // batched: [n_env + 1]
 
     // host side
     Header* hdr_host = nullptr;   // pinned
@@ -64,10 +98,17 @@ struct nsim_ev {
     int64_t t_expect = 0;         // time of the last enqueued frame
     std::string err;
 
+    hipStream_t cap_stream = nullptr;         // graph capture only
+    std::vector<GraphSlot> graphs;
+
     bool profiling = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending;
     std::vector<hipEvent_t> event_pool;
     nsim_ev_stats stats{};
+};
+
+struct nsim_evb {
+    nsim_ev core;
 };
 
 namespace {
@@ -110,14 +151,23 @@ hipError_t dmalloc(T** p, size_t count) {
     return hipMalloc((void**)p, count * sizeof(T));
 }
 
+void destroy_graphs(nsim_ev* h) {
+    for (GraphSlot& g : h->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    h->graphs.clear();
+}
+
 void free_all(nsim_ev* h) {
-    void* ptrs[] = {h->hdr, h->L_init, h->nud[0], h->nud[1], h->prev[0],
-                    h->prev[1], h->tlast[0], h->tlast[1], h->cpos_map,
-                    h->cneg_map, h->skey[0], h->skey[1], h->sval[0],
-                    h->sval[1], h->q_t, h->q_x, h->q_y, h->q_p,
-                    h->stage_key, h->stage_val, h->seg_base, h->seg_count,
-                    h->pref, h->hist,
-                    h->pass_status, h->pass_ctr};
+    destroy_graphs(h);
+    void* ptrs[] = {h->hdr, h->envs, h->wave_env, h->L_init, h->nud[0],
+                    h->nud[1], h->prev[0], h->prev[1], h->tlast[0],
+                    h->tlast[1], h->cpos_map, h->cneg_map, h->skey[0],
+                    h->skey[1], h->sval[0], h->sval[1], h->q_t, h->q_x,
+                    h->q_y, h->q_p, h->stage_key, h->stage_val, h->seg_base,
+                    h->seg_count, h->pref, h->tile_sum, h->hist,
+                    h->pass_status, h->pass_ctr, h->env_off};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hdr_host) (void)hipHostFree(h->hdr_host);
@@ -127,6 +177,7 @@ void free_all(nsim_ev* h) {
         (void)hipEventDestroy(pr.second);
     }
     for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
+    if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
 }
 
 int read_header(nsim_ev* h) {
@@ -194,9 +245,374 @@ int bits_for(int64_t span) {
     return b;
 }
 
-int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
-    if (!frames || !t_us) return fail(h, NSIM_EINVAL, "null frames or times");
-    if (K < 1) return fail(h, NSIM_EINVAL, "K must be >= 1");
+// Arguments of one launch sequence: step, scan, gather, radix passes and
+// commit for kl frames starting at `frames`, with T0 the time of the frame
+// before them.
+struct LaunchSet {
+    nsim::StepArgs step;
+    nsim::ScanArgs scan;
+    nsim::GatherArgs gather;
+    nsim::PassArgs pass[nsim::kMaxPasses];
+    nsim::CommitArgs commit;
+    int npass = 0;
+    int nbits = 0;
+    int32_t kl = 0;
+};
+
+void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
+                  const int64_t* t_us, int32_t kl, int64_t T0, bool dry) {
+    L = LaunchSet{};
+    L.kl = kl;
+    nsim::StepArgs& a = L.step;
+    a.frames = frames;
+    a.frame_stride = h->frame_stride;
+    a.K = kl;
+    a.nwaves = h->nwaves;
+    a.envs = h->envs;
+    a.wave_env = h->wave_env;
+    a.stage_entries = h->stage_entries;
+    a.L_init = h->L_init;
+    for (int i = 0; i < 2; ++i) {
+        a.nud[i] = h->nud[i];
+        a.prev[i] = h->prev[i];
+        a.tlast[i] = h->tlast[i];
+    }
+    a.c_pos_map = h->cpos_map;
+    a.c_neg_map = h->cneg_map;
+    a.c_pos = h->c_pos;
+    a.c_neg = h->c_neg;
+    a.log_eps = h->log_eps;
+    a.log_eps_f = (float)h->log_eps;
+    a.tref = h->tref;
+    a.T0 = T0;
+    const int64_t tmax = t_us[kl - 1];
+    const double amax = std::max(std::fabs((double)T0), std::fabs((double)tmax));
+    a.eT = (float)std::max(0x1p-12, amax * 0x1p-51);
+    a.out_key = h->stage_key;
+    a.out_val = h->stage_val;
+    a.out_cap = h->stage_cap;
+    a.seg_base = h->seg_base;
+    a.seg_count = h->seg_count;
+    a.hdr = h->hdr;
+    a.flags = h->flags;
+    for (int32_t i = 0; i < kl; ++i) a.toff[i] = (int32_t)(t_us[i] - T0);
+    const int tbits = bits_for(a.toff[kl - 1]);
+    a.key_tbits = tbits;
+    L.nbits = tbits + h->env_bits;
+    L.npass = (L.nbits + nsim::kDigitBits - 1) / nsim::kDigitBits;
+
+    nsim::ScanArgs& sa = L.scan;
+    sa.seg_count = h->seg_count;
+    sa.pref = h->pref;
+    sa.nwaves = h->nwaves;
+    sa.restart_queue = h->batched ? 1 : 0;
+    sa.tile_sum = h->tile_sum;
+    sa.hdr = h->hdr;
+
+    nsim::GatherArgs& ga = L.gather;
+    ga.seg_base = h->seg_base;
+    ga.seg_count = h->seg_count;
+    ga.pref = h->pref;
+    ga.nwaves = h->nwaves;
+    ga.npass = L.npass;
+    ga.skey = h->stage_key;
+    ga.sval = h->stage_val;
+    ga.dkey = h->skey[0];
+    ga.dval = h->sval[0];
+    ga.hdr = h->hdr;
+    ga.scratch_cap = h->scap;
+    ga.qcap = h->qcap;
+    ga.hist = h->hist;
+    ga.status = h->pass_status;
+    ga.max_tiles = h->max_sort_tiles;
+    ga.pass_ctr = h->pass_ctr;
+
+    for (int p = 0; p < L.npass; ++p) {
+        nsim::PassArgs& pa = L.pass[p];
+        pa.kin = h->skey[p & 1];
+        pa.vin = h->sval[p & 1];
+        pa.kout = h->skey[(p + 1) & 1];
+        pa.vout = h->sval[(p + 1) & 1];
+        pa.t_out = h->q_t;
+        pa.x_out = h->q_x;
+        pa.y_out = h->q_y;
+        pa.p_out = h->q_p;
+        pa.qcap = h->qcap;
+        pa.final_pass = (p == L.npass - 1) ? 1 : 0;
+        pa.shift = nsim::kDigitBits * p;
+        pa.bits = std::min(nsim::kDigitBits, L.nbits - nsim::kDigitBits * p);
+        pa.key_tbits = tbits;
+        pa.envs = h->envs;
+        pa.T0 = T0;
+        pa.hist = h->hist + p * nsim::kDigits;
+        pa.status = h->pass_status + (int64_t)p * h->max_sort_tiles * nsim::kDigits;
+        pa.tile_ctr = h->pass_ctr + p;
+        pa.hdr = h->hdr;
+        pa.scratch_cap = h->scap;
+    }
+
+    nsim::CommitArgs& ca = L.commit;
+    ca.hdr = h->hdr;
+    ca.scratch_cap = h->scap;
+    ca.qcap = h->qcap;
+    ca.t_last = tmax;
+    ca.t_first = t_us[0];
+    ca.pixel_updates = h->P * kl;
+    ca.hist = h->hist;
+    ca.dry = dry ? 1 : 0;
+    ca.n_env = h->n_env;
+    ca.env_off = h->batched ? h->env_off : nullptr;
+    ca.pref = h->pref;
+    ca.envs = h->envs;
+}
+
+// Enqueue a launch sequence with ordinary launches.  With `ev` set, HIP
+// events bracket the step kernel.
+hipError_t enqueue_direct(nsim_ev* h, const LaunchSet& L, hipStream_t s,
+                          std::pair<hipEvent_t, hipEvent_t>* ev) {
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev->first, s)) != hipSuccess) return e;
+    if ((e = nsim::launch_step(L.step, h->log_input, h->has_map,
+                               h->waves_per_block, h->step_blocks, s)) !=
+        hipSuccess)
+        return e;
+    if (ev && (e = hipEventRecord(ev->second, s)) != hipSuccess) return e;
+    if ((e = nsim::launch_scan(L.scan, s)) != hipSuccess) return e;
+    if ((e = nsim::launch_gather(L.gather, s)) != hipSuccess) return e;
+    for (int p = 0; p < L.npass; ++p)
+        if ((e = nsim::launch_pass(L.pass[p], s)) != hipSuccess) return e;
+    return nsim::launch_commit(L.commit, s);
+}
+
+// Capture the launch sequence of L on the private capture stream and keep
+// the nodes whose arguments change from call to call.
+int capture_graph(nsim_ev* h, const LaunchSet& L, GraphSlot** out) {
+    if (!h->cap_stream)
+        NSIM_HIP(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    GraphSlot g;
+    g.nbits = L.nbits;
+    g.stage = h->stage_entries;
+    g.wpb = h->waves_per_block;
+    g.blocks = h->step_blocks;
+    NSIM_HIP(h, hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeRelaxed));
+    const hipError_t le = enqueue_direct(h, L, h->cap_stream, nullptr);
+    hipGraph_t graph = nullptr;
+    const hipError_t ce = hipStreamEndCapture(h->cap_stream, &graph);
+    if (le != hipSuccess || ce != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(h, le != hipSuccess ? le : ce, "graph capture");
+    }
+    g.graph = graph;
+    std::vector<hipGraphNode_t> chain;
+    size_t nroot = 0;
+    hipError_t e = hipGraphGetRootNodes(graph, nullptr, &nroot);
+    if (e == hipSuccess && nroot == 1) {
+        hipGraphNode_t node = nullptr;
+        e = hipGraphGetRootNodes(graph, &node, &nroot);
+        while (e == hipSuccess && node && chain.size() < 64) {
+            chain.push_back(node);
+            size_t nd = 0;
+            e = hipGraphNodeGetDependentNodes(node, nullptr, &nd);
+            if (e != hipSuccess || nd == 0) break;
+            if (nd != 1) {
+                e = hipErrorInvalidValue;
+                break;
+            }
+            e = hipGraphNodeGetDependentNodes(node, &node, &nd);
+        }
+    } else if (e == hipSuccess) {
+        e = hipErrorInvalidValue;
+    }
+    const size_t expect = 5 + (size_t)L.npass;
+    if (e == hipSuccess && chain.size() != expect) e = hipErrorInvalidValue;
+    for (size_t i = 0; e == hipSuccess && i < chain.size(); ++i) {
+        hipGraphNodeType ty;
+        e = hipGraphNodeGetType(chain[i], &ty);
+        if (e == hipSuccess && ty != hipGraphNodeTypeKernel) e = hipErrorInvalidValue;
+    }
+    if (e == hipSuccess) {
+        g.n_step = chain[0];
+        g.n_final = chain[3 + L.npass];
+        g.n_commit = chain.back();
+        e = hipGraphKernelNodeGetParams(g.n_step, &g.p_step);
+        if (e == hipSuccess) e = hipGraphKernelNodeGetParams(g.n_final, &g.p_final);
+        if (e == hipSuccess) e = hipGraphKernelNodeGetParams(g.n_commit, &g.p_commit);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&g.exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(h, e, "graph capture: unexpected node layout");
+    }
+    h->graphs.push_back(g);
+    *out = &h->graphs.back();
+    return NSIM_OK;
+}
+
+GraphSlot* find_graph(nsim_ev* h, const LaunchSet& L) {
+    for (GraphSlot& g : h->graphs)
+        if (g.nbits == L.nbits && g.stage == h->stage_entries &&
+            g.wpb == h->waves_per_block && g.blocks == h->step_blocks)
+            return &g;
+    return nullptr;
+}
+
+// Replay the graph for L: new arguments for the step, final pass and
+// commit nodes, then one graph launch on the handle's stream.
+int enqueue_graph(nsim_ev* h, const LaunchSet& L,
+                  std::pair<hipEvent_t, hipEvent_t>* ev) {
+    GraphSlot* g = find_graph(h, L);
+    if (!g) {
+        const int rc = capture_graph(h, L, &g);
+        if (rc) return rc;
+    }
+    nsim::StepArgs sa = L.step;
+    nsim::PassArgs pa = L.pass[L.npass - 1];
+    nsim::CommitArgs ca = L.commit;
+    void* a0[] = {&sa};
+    void* a1[] = {&pa};
+    void* a2[] = {&ca};
+    hipKernelNodeParams p = g->p_step;
+    p.kernelParams = a0;
+    p.extra = nullptr;
+    NSIM_HIP(h, hipGraphExecKernelNodeSetParams(g->exec, g->n_step, &p));
+    p = g->p_final;
+    p.kernelParams = a1;
+    p.extra = nullptr;
+    NSIM_HIP(h, hipGraphExecKernelNodeSetParams(g->exec, g->n_final, &p));
+    p = g->p_commit;
+    p.kernelParams = a2;
+    p.extra = nullptr;
+    NSIM_HIP(h, hipGraphExecKernelNodeSetParams(g->exec, g->n_commit, &p));
+    if (ev) NSIM_HIP(h, hipEventRecord(ev->first, h->stream));
+    NSIM_HIP(h, hipGraphLaunch(g->exec, h->stream));
+    if (ev) NSIM_HIP(h, hipEventRecord(ev->second, h->stream));
+    return NSIM_OK;
+}
+
+int enqueue(nsim_ev* h, const LaunchSet& L, bool graph) {
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (h->profiling) {
+        NSIM_HIP(h, get_event(h, &ev.first));
+        NSIM_HIP(h, get_event(h, &ev.second));
+    }
+    auto* evp = h->profiling ? &ev : nullptr;
+    if (graph) {
+        const int rc = enqueue_graph(h, L, evp);
+        if (rc) return rc;
+    } else {
+        NSIM_HIP(h, enqueue_direct(h, L, h->stream, evp));
+    }
+    if (h->profiling) h->pending.push_back(ev);
+    return NSIM_OK;
+}
+
+// Time one configuration: a warm-up and `reps` dry runs of the whole launch
+// sequence (nothing committed); best time in ms.
+int time_trial(nsim_ev* h, const float* frames, const int64_t* t_us,
+               int32_t kl, int64_t T0, bool graph, int reps, float* best) {
+    LaunchSet L;
+    build_launch(h, L, frames, t_us, kl, T0, true);
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    NSIM_HIP(h, get_event(h, &ev.first));
+    NSIM_HIP(h, get_event(h, &ev.second));
+    *best = 1e30f;
+    int rc = NSIM_OK;
+    for (int r = 0; r <= reps && rc == NSIM_OK; ++r) {
+        if (graph) {
+            rc = enqueue_graph(h, L, &ev);
+        } else {
+            hipError_t e = hipEventRecord(ev.first, h->stream);
+            if (e == hipSuccess) e = enqueue_direct(h, L, h->stream, nullptr);
+            if (e == hipSuccess) e = hipEventRecord(ev.second, h->stream);
+            if (e != hipSuccess) rc = hip_fail(h, e, "timing trial");
+        }
+        float ms = 0.f;
+        if (rc == NSIM_OK) {
+            hipError_t e = hipEventSynchronize(ev.second);
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, ev.first, ev.second);
+            if (e != hipSuccess) rc = hip_fail(h, e, "timing trial");
+        }
+        if (rc == NSIM_OK && r > 0) *best = std::min(*best, ms);
+    }
+    h->event_pool.push_back(ev.first);
+    h->event_pool.push_back(ev.second);
+    return rc;
+}
+
+void record_candidate(nsim_ev* h, float ms, int32_t graph) {
+    nsim_evb_tuning& tu = h->tuning;
+    if (tu.n_candidates >= 32) return;
+    const int i = tu.n_candidates++;
+    tu.candidate_ms[i] = ms;
+    tu.candidate_stage[i] = h->stage_entries;
+    tu.candidate_waves[i] = h->waves_per_block;
+    tu.candidate_blocks[i] = h->step_blocks;
+    tu.candidate_graph[i] = graph;
+}
+
+// Choose stage entries, waves per block, grid (one wave per tile or a
+// persistent grid) and graph use for a batch by timing dry runs of the
+// first stepping call's launch.  Knobs fixed by the caller are kept.
+int autotune(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t kl,
+             int64_t T0) {
+    NSIM_HIP(h, hipStreamSynchronize(h->stream));
+    int rc = read_header(h);
+    if (rc) return rc;
+    if (h->hdr_host->status != 0 || h->hdr_host->internal_err != 0) return NSIM_OK;
+    const int64_t fp64_before = h->hdr_host->fp64_evals;
+    std::vector<int32_t> stages, wpbs;
+    if (h->want_stage) stages.push_back(h->want_stage);
+    else
+        for (int32_t st : {128, 512, 2000})
+            if (st <= h->stage_alloc) stages.push_back(st);
+    if (h->want_wpb) wpbs.push_back(h->want_wpb);
+    else wpbs = {1, 2, 4};
+    h->tuning = nsim_evb_tuning{};
+    float best = 1e30f;
+    int32_t bs = h->stage_entries, bw = h->waves_per_block, bb = h->step_blocks;
+    for (int32_t st : stages) {
+        for (int32_t wp : wpbs) {
+            std::vector<int32_t> grids;
+            if (h->want_blocks >= 0) grids.push_back(h->want_blocks);
+            else grids = {0, 8 * h->n_cu / wp, 16 * h->n_cu / wp};
+            for (int32_t gb : grids) {
+                h->stage_entries = st;
+                h->waves_per_block = wp;
+                h->step_blocks = gb;
+                float ms = 0.f;
+                rc = time_trial(h, frames, t_us, kl, T0, false, 2, &ms);
+                if (rc) return rc;
+                record_candidate(h, ms, 0);
+                if (ms < best) {
+                    best = ms;
+                    bs = st;
+                    bw = wp;
+                    bb = gb;
+                }
+            }
+        }
+    }
+    h->stage_entries = bs;
+    h->waves_per_block = bw;
+    h->step_blocks = bb;
+    int32_t graph = h->want_graph;
+    if (graph < 0) {
+        float gms = 0.f;
+        rc = time_trial(h, frames, t_us, kl, T0, true, 2, &gms);
+        if (rc) return rc;
+        record_candidate(h, gms, 1);
+        graph = gms <= best ? 1 : 0;
+    }
+    h->use_graph = graph;
+    NSIM_HIP(h, hipStreamSynchronize(h->stream));
+    rc = read_header(h);
+    if (rc) return rc;
+    h->fp64_trial += h->hdr_host->fp64_evals - fp64_before;
+    h->tuning.tuned = 1;
+    return NSIM_OK;
+}
+
+int check_times(nsim_ev* h, const int64_t* t_us, int32_t K) {
     int64_t prev_t = h->t_expect;
     for (int32_t i = 0; i < K; ++i) {
         if (i > 0 || h->initialized) {
@@ -208,24 +624,46 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
         }
         prev_t = t_us[i];
     }
+    return NSIM_OK;
+}
+
+hipError_t enqueue_init(nsim_ev* h, const float* frame, int64_t t0) {
+    nsim::InitArgs ia{};
+    ia.frame = frame;
+    ia.nwaves = h->nwaves;
+    ia.flags = h->flags;
+    ia.envs = h->envs;
+    ia.wave_env = h->wave_env;
+    ia.log_eps = h->log_eps;
+    ia.L_init = h->L_init;
+    for (int i = 0; i < 2; ++i) {
+        ia.nud[i] = h->nud[i];
+        ia.prev[i] = h->prev[i];
+        ia.tlast[i] = h->tlast[i];
+    }
+    ia.hdr = h->hdr;
+    ia.t0 = t0;
+    ia.env_off = h->batched ? h->env_off : nullptr;
+    ia.n_env = h->n_env;
+    return nsim::launch_init(ia, h->stream);
+}
+
+void count_launch(nsim_ev* h, const LaunchSet& L) {
+    h->stats.step_launches += 1;
+    h->stats.pixel_updates += h->P * L.kl;
+    h->stats.sort_passes += L.npass;
+}
+
+int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
+    if (!frames || !t_us) return fail(h, NSIM_EINVAL, "null frames or times");
+    if (K < 1) return fail(h, NSIM_EINVAL, "K must be >= 1");
+    int rc = check_times(h, t_us, K);
+    if (rc) return rc;
     DeviceGuard dg(h->device);
-    const int64_t P = h->P;
+    const int64_t P = h->frame_stride;
     int32_t k = 0;
     if (!h->initialized) {
-        nsim::InitArgs ia{};
-        ia.frame = frames;
-        ia.P = h->P;
-        ia.flags = h->flags;
-        ia.log_eps = h->log_eps;
-        ia.L_init = h->L_init;
-        for (int i = 0; i < 2; ++i) {
-            ia.nud[i] = h->nud[i];
-            ia.prev[i] = h->prev[i];
-            ia.tlast[i] = h->tlast[i];
-        }
-        ia.hdr = h->hdr;
-        ia.t0 = t_us[0];
-        NSIM_HIP(h, nsim::launch_init(ia, h->stream));
+        NSIM_HIP(h, enqueue_init(h, frames, t_us[0]));
         h->initialized = true;
         h->t_expect = t_us[0];
         k = 1;
@@ -244,120 +682,211 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
             if (h->max_frames == 0 && kl >= 8 && span > 65535) break;
             ++kl;
         }
-        if (kl == 0) kl = 1;  // a single frame always fits (gap < 2^30)
-
-        nsim::StepArgs a{};
-        a.frames = frames + (int64_t)k * P;
-        a.K = kl;
-        a.P = h->P;
-        a.width = h->W;
-        a.nwaves = h->nwaves;
-        a.L_init = h->L_init;
-        for (int i = 0; i < 2; ++i) {
-            a.nud[i] = h->nud[i];
-            a.prev[i] = h->prev[i];
-            a.tlast[i] = h->tlast[i];
-        }
-        a.c_pos_map = h->cpos_map;
-        a.c_neg_map = h->cneg_map;
-        a.c_pos = h->c_pos;
-        a.c_neg = h->c_neg;
-        a.log_eps = h->log_eps;
-        a.log_eps_f = (float)h->log_eps;
-        a.tref = h->tref;
-        a.T0 = T0;
-        const int64_t tmax = t_us[k + kl - 1];
-        const double amax =
-            std::max(std::fabs((double)T0), std::fabs((double)tmax));
-        a.eT = (float)std::max(0x1p-12, amax * 0x1p-51);
-        a.out_key = h->stage_key;
-        a.out_val = h->stage_val;
-        a.out_cap = h->stage_cap;
-        a.seg_base = h->seg_base;
-        a.seg_count = h->seg_count;
-        a.hdr = h->hdr;
-        a.flags = h->flags;
-        for (int32_t i = 0; i < kl; ++i) a.toff[i] = (int32_t)(t_us[k + i] - T0);
-
-        hipEvent_t e0 = nullptr, e1 = nullptr;
-        if (h->profiling) {
-            NSIM_HIP(h, get_event(h, &e0));
-            NSIM_HIP(h, get_event(h, &e1));
-            NSIM_HIP(h, hipEventRecord(e0, h->stream));
-        }
-        NSIM_HIP(h, nsim::launch_step(a, h->log_input, h->has_map, h->stream));
-        if (h->profiling) {
-            NSIM_HIP(h, hipEventRecord(e1, h->stream));
-            h->pending.emplace_back(e0, e1);
-        }
-
-        const int64_t span = a.toff[kl - 1];
-        const int nbits = bits_for(span);
-        const int npass = (nbits + nsim::kDigitBits - 1) / nsim::kDigitBits;
-        nsim::ScanArgs sa{};
-        sa.seg_count = h->seg_count;
-        sa.pref = h->pref;
-        sa.nwaves = h->nwaves;
-        sa.hdr = h->hdr;
-        NSIM_HIP(h, nsim::launch_scan(sa, h->stream));
-        nsim::GatherArgs ga{};
-        ga.seg_base = h->seg_base;
-        ga.seg_count = h->seg_count;
-        ga.pref = h->pref;
-        ga.nwaves = h->nwaves;
-        ga.npass = npass;
-        ga.skey = h->stage_key;
-        ga.sval = h->stage_val;
-        ga.dkey = h->skey[0];
-        ga.dval = h->sval[0];
-        ga.hdr = h->hdr;
-        ga.scratch_cap = h->scap;
-        ga.qcap = h->qcap;
-        ga.hist = h->hist;
-        ga.status = h->pass_status;
-        ga.max_tiles = h->max_sort_tiles;
-        ga.pass_ctr = h->pass_ctr;
-        NSIM_HIP(h, nsim::launch_gather(ga, h->stream));
-        for (int p = 0; p < npass; ++p) {
-            nsim::PassArgs pa{};
-            pa.kin = h->skey[p & 1];
-            pa.vin = h->sval[p & 1];
-            pa.kout = h->skey[(p + 1) & 1];
-            pa.vout = h->sval[(p + 1) & 1];
-            pa.t_out = h->q_t;
-            pa.x_out = h->q_x;
-            pa.y_out = h->q_y;
-            pa.p_out = h->q_p;
-            pa.qcap = h->qcap;
-            pa.final_pass = (p == npass - 1) ? 1 : 0;
-            pa.shift = nsim::kDigitBits * p;
-            pa.bits = std::min(nsim::kDigitBits, nbits - nsim::kDigitBits * p);
-            pa.width = h->W;
-            pa.T0 = T0;
-            pa.hist = h->hist + p * nsim::kDigits;
-            pa.status = h->pass_status +
-                        (int64_t)p * h->max_sort_tiles * nsim::kDigits;
-            pa.tile_ctr = h->pass_ctr + p;
-            pa.hdr = h->hdr;
-            pa.scratch_cap = h->scap;
-            NSIM_HIP(h, nsim::launch_pass(pa, h->stream));
-        }
-        nsim::CommitArgs ca{};
-        ca.hdr = h->hdr;
-        ca.scratch_cap = h->scap;
-        ca.qcap = h->qcap;
-        ca.t_last = tmax;
-        ca.t_first = t_us[k];
-        ca.pixel_updates = P * kl;
-        ca.hist = h->hist;
-        NSIM_HIP(h, nsim::launch_commit(ca, h->stream));
-
-        h->stats.step_launches += 1;
-        h->stats.pixel_updates += P * kl;
-        h->stats.sort_passes += npass;
-        h->t_expect = tmax;
+        if (kl == 0) kl = 1;  // a single frame always fits (gap < 2^25)
+        LaunchSet L;
+        build_launch(h, L, frames + (int64_t)k * P, t_us + k, kl, T0, false);
+        rc = enqueue(h, L, false);
+        if (rc) return rc;
+        count_launch(h, L);
+        h->t_expect = t_us[k + kl - 1];
         k += kl;
     }
+    return NSIM_OK;
+}
+
+// One call of a batch: at most one launch, so that the output is ordered by
+// environment.
+int do_batch_step(nsim_ev* h, const float* frames, const int64_t* t_us,
+                  int32_t K) {
+    if (!frames || !t_us) return fail(h, NSIM_EINVAL, "null frames or times");
+    if (K < 1) return fail(h, NSIM_EINVAL, "K must be >= 1");
+    int rc = check_times(h, t_us, K);
+    if (rc) return rc;
+    const int32_t k0 = h->initialized ? 0 : 1;
+    const int32_t kl = K - k0;
+    if (kl > 0) {
+        const int64_t T0 = h->initialized ? h->t_expect : t_us[0];
+        const int64_t span = t_us[K - 1] - T0;
+        const int64_t lim = std::min<int64_t>(
+            nsim::kMaxLaunchSpan, (int64_t(1) << (32 - h->env_bits)) - 2);
+        if (kl > nsim::kMaxFramesPerLaunch || span > lim)
+            return fail(h, NSIM_EINVAL,
+                        "a batched call must fit one launch: at most 256 "
+                        "frames and a short enough time span");
+    }
+    DeviceGuard dg(h->device);
+    if (!h->initialized) {
+        NSIM_HIP(h, enqueue_init(h, frames, t_us[0]));
+        h->initialized = true;
+        h->t_expect = t_us[0];
+    }
+    if (kl == 0) return NSIM_OK;
+    const int64_t P = h->frame_stride;
+    const float* fr = frames + (int64_t)k0 * P;
+    const int64_t T0 = h->t_expect;
+    if (!h->tuned) {
+        h->tuned = true;
+        if (h->autotune) {
+            rc = autotune(h, fr, t_us + k0, kl, T0);
+            if (rc) return rc;
+        }
+    }
+    LaunchSet L;
+    build_launch(h, L, fr, t_us + k0, kl, T0, false);
+    rc = enqueue(h, L, h->use_graph != 0);
+    if (rc) return rc;
+    count_launch(h, L);
+    h->t_expect = t_us[K - 1];
+    return NSIM_OK;
+}
+
+// Per-environment description for the common constructor.
+struct EnvDesc {
+    int32_t width, height;
+    float c_pos, c_neg;
+    const float* c_pos_map;
+    const float* c_neg_map;
+};
+
+bool valid_thresholds(const EnvDesc& d) {
+    if ((d.c_pos_map == nullptr) != (d.c_neg_map == nullptr)) return false;
+    if (d.c_pos_map) return true;
+    return d.c_pos > 0.f && d.c_neg > 0.f && std::isfinite(d.c_pos) &&
+           std::isfinite(d.c_neg);
+}
+
+// Allocate and initialise a handle for the given environments.
+int create_core(nsim_ev* h, const std::vector<EnvDesc>& envs, double log_eps,
+                int64_t refractory_us, int64_t capacity, uint32_t flags,
+                int32_t max_frames, int32_t stage_alloc, void* stream) {
+    if (hipGetDevice(&h->device) != hipSuccess) return NSIM_EHIP;
+    int ncu = 0;
+    if (hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount,
+                              h->device) == hipSuccess &&
+        ncu > 0)
+        h->n_cu = ncu;
+    h->stream = (hipStream_t)stream;
+    h->n_env = (int32_t)envs.size();
+    h->env_bits = bits_for(h->n_env - 1);
+    h->flags = flags;
+    h->log_input = (flags & NSIM_INPUT_LOG) != 0;
+    h->log_eps = h->log_input ? 0.0 : log_eps;
+    h->tref = (int32_t)refractory_us;
+    h->qcap = capacity;
+    h->scap = capacity;
+    h->max_frames = max_frames;
+    h->stage_alloc = stage_alloc;
+    h->max_sort_tiles = (h->scap + nsim::kSortTile - 1) / nsim::kSortTile + 1;
+
+    int64_t off = 0, wave = 0;
+    bool any_map = false, same_scalar = true;
+    for (const EnvDesc& d : envs) {
+        nsim::EnvRec r{};
+        r.frame_off = off;
+        r.wave0 = (int32_t)wave;
+        r.npix = d.width * d.height;
+        r.width = d.width;
+        r.height = d.height;
+        h->env_host.push_back(r);
+        off += r.npix;
+        wave += (r.npix + nsim::kWave - 1) / nsim::kWave;
+        any_map = any_map || d.c_pos_map != nullptr;
+        same_scalar = same_scalar && d.c_pos == envs[0].c_pos &&
+                      d.c_neg == envs[0].c_neg;
+    }
+    h->P = off;
+    h->frame_stride = off;
+    h->nwaves = (int32_t)wave;
+    h->has_map = any_map || !same_scalar;
+    h->c_pos = envs[0].c_pos;
+    h->c_neg = envs[0].c_neg;
+    if (h->n_env == 1) {
+        h->W = envs[0].width;
+        h->H = envs[0].height;
+    }
+    const int64_t npad = (int64_t)h->nwaves * nsim::kWave;
+
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) {
+        if (e == hipSuccess && x != hipSuccess) e = x;
+    };
+    chk(dmalloc(&h->hdr, 1));
+    chk(dmalloc(&h->envs, h->n_env));
+    chk(dmalloc(&h->wave_env, h->nwaves));
+    chk(dmalloc(&h->L_init, npad));
+    for (int i = 0; i < 2; ++i) {
+        chk(dmalloc(&h->nud[i], npad));
+        chk(dmalloc(&h->prev[i], npad));
+        chk(dmalloc(&h->tlast[i], npad));
+        chk(dmalloc(&h->skey[i], h->scap));
+        chk(dmalloc(&h->sval[i], h->scap));
+    }
+    if (h->has_map) {
+        chk(dmalloc(&h->cpos_map, npad));
+        chk(dmalloc(&h->cneg_map, npad));
+    }
+    chk(dmalloc(&h->q_t, h->qcap));
+    chk(dmalloc(&h->q_x, h->qcap));
+    chk(dmalloc(&h->q_y, h->qcap));
+    chk(dmalloc(&h->q_p, h->qcap));
+    h->stage_cap = (int64_t)h->nwaves * h->stage_alloc + h->scap;
+    chk(dmalloc(&h->stage_key, h->stage_cap));
+    chk(dmalloc(&h->stage_val, h->stage_cap));
+    chk(dmalloc(&h->seg_base, h->nwaves));
+    chk(dmalloc(&h->seg_count, h->nwaves));
+    chk(dmalloc(&h->pref, h->nwaves));
+    chk(dmalloc(&h->tile_sum, (h->nwaves + nsim::kScanTile - 1) / nsim::kScanTile));
+    chk(dmalloc(&h->hist, nsim::kMaxPasses * nsim::kDigits));
+    chk(dmalloc(&h->pass_status,
+                (size_t)nsim::kMaxPasses * h->max_sort_tiles * nsim::kDigits));
+    chk(dmalloc(&h->pass_ctr, nsim::kMaxPasses));
+    if (h->batched) chk(dmalloc(&h->env_off, h->n_env + 1));
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&h->hdr_host, sizeof(Header), 0);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void**)&h->xfer_host, sizeof(int64_t), 0);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return e == hipErrorOutOfMemory ? NSIM_ENOMEM : NSIM_EHIP;
+    }
+    std::vector<int32_t> wenv((size_t)h->nwaves);
+    for (int32_t i = 0; i < h->n_env; ++i) {
+        const nsim::EnvRec& r = h->env_host[i];
+        const int32_t nw = (r.npix + nsim::kWave - 1) / nsim::kWave;
+        for (int32_t j = 0; j < nw; ++j) wenv[(size_t)r.wave0 + j] = i;
+    }
+    hipStream_t s = h->stream;
+    chk(hipMemcpy(h->envs, h->env_host.data(),
+                  sizeof(nsim::EnvRec) * h->n_env, hipMemcpyHostToDevice));
+    chk(hipMemcpy(h->wave_env, wenv.data(), sizeof(int32_t) * h->nwaves,
+                  hipMemcpyHostToDevice));
+    chk(hipMemsetAsync(h->hdr, 0, sizeof(Header), s));
+    chk(hipMemsetAsync(h->pass_ctr, 0, sizeof(uint32_t) * nsim::kMaxPasses, s));
+    if (h->env_off)
+        chk(hipMemsetAsync(h->env_off, 0, sizeof(int64_t) * (h->n_env + 1), s));
+    if (h->has_map) {
+        for (int32_t i = 0; i < h->n_env; ++i) {
+            const EnvDesc& d = envs[i];
+            const nsim::EnvRec& r = h->env_host[i];
+            float* cp = h->cpos_map + (int64_t)r.wave0 * nsim::kWave;
+            float* cn = h->cneg_map + (int64_t)r.wave0 * nsim::kWave;
+            if (d.c_pos_map) {
+                chk(hipMemcpyAsync(cp, d.c_pos_map, sizeof(float) * r.npix,
+                                   hipMemcpyDeviceToDevice, s));
+                chk(hipMemcpyAsync(cn, d.c_neg_map, sizeof(float) * r.npix,
+                                   hipMemcpyDeviceToDevice, s));
+            } else {
+                uint32_t bp, bn;
+                memcpy(&bp, &d.c_pos, 4);
+                memcpy(&bn, &d.c_neg, 4);
+                chk(hipMemsetD32Async((hipDeviceptr_t)cp, (int)bp, r.npix, s));
+                chk(hipMemsetD32Async((hipDeviceptr_t)cn, (int)bn, r.npix, s));
+            }
+        }
+    }
+    chk(nsim::launch_reset_header(h->hdr, h->hist, s));
+    chk(hipStreamSynchronize(s));
+    if (e != hipSuccess) return NSIM_EHIP;
     return NSIM_OK;
 }
 
@@ -371,7 +900,7 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out) {
     if (!cfg) return NSIM_EINVAL;
     if (cfg->width < 1 || cfg->width > 65535 || cfg->height < 1 ||
         cfg->height > 65535 ||
-        (int64_t)cfg->width * cfg->height >= (int64_t(1) << 31))
+        (int64_t)cfg->width * cfg->height >= (int64_t(1) << 31) - 64)
         return NSIM_EINVAL;
     if (cfg->refractory_us < 0 || cfg->refractory_us > (int64_t(1) << 30))
         return NSIM_EINVAL;
@@ -385,93 +914,20 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out) {
     const bool log_in = (cfg->flags & NSIM_INPUT_LOG) != 0;
     if (!log_in && !(cfg->log_eps >= 0.0 && std::isfinite(cfg->log_eps)))
         return NSIM_EINVAL;
-    if ((cfg->c_pos_map == nullptr) != (cfg->c_neg_map == nullptr))
-        return NSIM_EINVAL;
-    if (!cfg->c_pos_map && !(cfg->c_pos > 0.f && cfg->c_neg > 0.f &&
-                             std::isfinite(cfg->c_pos) &&
-                             std::isfinite(cfg->c_neg)))
-        return NSIM_EINVAL;
+    const EnvDesc d{cfg->width, cfg->height, cfg->c_pos, cfg->c_neg,
+                    cfg->c_pos_map, cfg->c_neg_map};
+    if (!valid_thresholds(d)) return NSIM_EINVAL;
 
     nsim_ev* h = new (std::nothrow) nsim_ev();
     if (!h) return NSIM_ENOMEM;
-    if (hipGetDevice(&h->device) != hipSuccess) {
-        delete h;
-        return NSIM_EHIP;
-    }
-    h->stream = (hipStream_t)stream;
-    h->W = cfg->width;
-    h->H = cfg->height;
-    h->P = cfg->width * cfg->height;
-    h->flags = cfg->flags;
-    h->log_input = log_in;
-    h->has_map = cfg->c_pos_map != nullptr;
-    h->c_pos = cfg->c_pos;
-    h->c_neg = cfg->c_neg;
-    h->log_eps = log_in ? 0.0 : cfg->log_eps;
-    h->tref = (int32_t)cfg->refractory_us;
-    h->qcap = cfg->capacity_events;
-    h->scap = cfg->capacity_events;
-    h->max_frames = cfg->max_frames_per_launch;
-    h->nwaves = (h->P + nsim::kWave - 1) / nsim::kWave;
-    h->max_sort_tiles = (h->scap + nsim::kSortTile - 1) / nsim::kSortTile + 1;
-
-    const int64_t P = h->P;
-    hipError_t e = hipSuccess;
-    auto chk = [&](hipError_t x) {
-        if (e == hipSuccess && x != hipSuccess) e = x;
-    };
-    chk(dmalloc(&h->hdr, 1));
-    chk(dmalloc(&h->L_init, P));
-    for (int i = 0; i < 2; ++i) {
-        chk(dmalloc(&h->nud[i], P));
-        chk(dmalloc(&h->prev[i], P));
-        chk(dmalloc(&h->tlast[i], P));
-        chk(dmalloc(&h->skey[i], h->scap));
-        chk(dmalloc(&h->sval[i], h->scap));
-    }
-    if (h->has_map) {
-        chk(dmalloc(&h->cpos_map, P));
-        chk(dmalloc(&h->cneg_map, P));
-    }
-    chk(dmalloc(&h->q_t, h->qcap));
-    chk(dmalloc(&h->q_x, h->qcap));
-    chk(dmalloc(&h->q_y, h->qcap));
-    chk(dmalloc(&h->q_p, h->qcap));
-    h->stage_cap = (int64_t)h->nwaves * nsim::kStepLdsEntries + h->scap;
-    chk(dmalloc(&h->stage_key, h->stage_cap));
-    chk(dmalloc(&h->stage_val, h->stage_cap));
-    chk(dmalloc(&h->seg_base, h->nwaves));
-    chk(dmalloc(&h->seg_count, h->nwaves));
-    chk(dmalloc(&h->pref, h->nwaves));
-    chk(dmalloc(&h->hist, nsim::kMaxPasses * nsim::kDigits));
-    chk(dmalloc(&h->pass_status,
-                (size_t)nsim::kMaxPasses * h->max_sort_tiles * nsim::kDigits));
-    chk(dmalloc(&h->pass_ctr, nsim::kMaxPasses));
-    if (e == hipSuccess)
-        e = hipHostMalloc((void**)&h->hdr_host, sizeof(Header), 0);
-    if (e == hipSuccess)
-        e = hipHostMalloc((void**)&h->xfer_host, sizeof(int64_t), 0);
-    if (e != hipSuccess) {
+    const int rc = create_core(h, {d}, cfg->log_eps, cfg->refractory_us,
+                               cfg->capacity_events, cfg->flags,
+                               cfg->max_frames_per_launch,
+                               nsim::kStepLdsEntries, stream);
+    if (rc) {
         free_all(h);
         delete h;
-        (void)hipGetLastError();
-        return e == hipErrorOutOfMemory ? NSIM_ENOMEM : NSIM_EHIP;
-    }
-    hipStream_t s = h->stream;
-    chk(hipMemsetAsync(h->hdr, 0, sizeof(Header), s));
-    chk(hipMemsetAsync(h->pass_ctr, 0, sizeof(uint32_t) * nsim::kMaxPasses, s));
-    if (h->has_map) {
-        chk(hipMemcpyAsync(h->cpos_map, cfg->c_pos_map, sizeof(float) * P,
-                           hipMemcpyDeviceToDevice, s));
-        chk(hipMemcpyAsync(h->cneg_map, cfg->c_neg_map, sizeof(float) * P,
-                           hipMemcpyDeviceToDevice, s));
-    }
-    chk(nsim::launch_reset_header(h->hdr, h->hist, s));
-    chk(hipStreamSynchronize(s));
-    if (e != hipSuccess) {
-        free_all(h);
-        delete h;
-        return NSIM_EHIP;
+        return rc;
     }
     *out = h;
     return NSIM_OK;
@@ -649,11 +1105,197 @@ int nsim_ev_get_stats(nsim_ev_t* h, nsim_ev_stats* out) {
     rc = read_header(h);
     if (rc) return rc;
     h->stats.events = h->hdr_host->events_total;
-    h->stats.fp64_evaluations = h->hdr_host->fp64_evals;
+    h->stats.fp64_evaluations = h->hdr_host->fp64_evals - h->fp64_trial;
     h->stats.packed_event_bytes = 8 * h->hdr_host->events_total;
     for (int i = 0; i < 8; ++i) h->stats.diag[i] = h->hdr_host->diag[i];
     *out = h->stats;
     return NSIM_OK;
+}
+
+// ---------------------------------------------------------------- batches
+
+int nsim_evb_create(const nsim_evb_env* envs, int32_t n_env,
+                    const nsim_evb_config* cfg, void* stream,
+                    nsim_evb_t** out) {
+    if (!out) return NSIM_EINVAL;
+    *out = nullptr;
+    if (!envs || !cfg || n_env < 1 || n_env > nsim::kMaxEnvs) return NSIM_EINVAL;
+    if (cfg->refractory_us < 0 || cfg->refractory_us > (int64_t(1) << 30))
+        return NSIM_EINVAL;
+    if (cfg->capacity_events < 1 || cfg->capacity_events >= (int64_t(1) << 30))
+        return NSIM_EINVAL;
+    if ((cfg->flags & ~(NSIM_INPUT_LOG | NSIM_FORCE_FP64)) != 0)
+        return NSIM_EINVAL;
+    const bool log_in = (cfg->flags & NSIM_INPUT_LOG) != 0;
+    if (!log_in && !(cfg->log_eps >= 0.0 && std::isfinite(cfg->log_eps)))
+        return NSIM_EINVAL;
+    if (cfg->stage_entries != 0 &&
+        (cfg->stage_entries < nsim::kWave ||
+         cfg->stage_entries > nsim::kStepMaxLdsEntries))
+        return NSIM_EINVAL;
+    if (cfg->waves_per_block < 0 ||
+        cfg->waves_per_block * nsim::kWave > nsim::kStepMaxThreads)
+        return NSIM_EINVAL;
+    if (cfg->use_graph < -1 || cfg->use_graph > 1) return NSIM_EINVAL;
+    if (cfg->step_blocks < -1) return NSIM_EINVAL;
+    std::vector<EnvDesc> ds;
+    int64_t padded = 0;
+    for (int32_t i = 0; i < n_env; ++i) {
+        const nsim_evb_env& e = envs[i];
+        if (e.width < 1 || e.width > 65535 || e.height < 1 || e.height > 65535)
+            return NSIM_EINVAL;
+        const EnvDesc d{e.width, e.height, e.c_pos, e.c_neg, e.c_pos_map,
+                        e.c_neg_map};
+        if (!valid_thresholds(d)) return NSIM_EINVAL;
+        padded += ((int64_t)e.width * e.height + nsim::kWave - 1) / nsim::kWave *
+                  nsim::kWave;
+        ds.push_back(d);
+    }
+    if (padded >= (int64_t(1) << 31)) return NSIM_EINVAL;
+    const int64_t nwaves = padded / nsim::kWave;
+    // staging sized for the largest candidate that keeps it under 2 GiB
+    int32_t stage_alloc = cfg->stage_entries;
+    if (stage_alloc == 0) {
+        stage_alloc = 128;
+        for (int32_t s : {512, 2000})
+            if (nwaves * s * 8 <= (int64_t(1) << 31)) stage_alloc = s;
+    }
+
+    nsim_evb* b = new (std::nothrow) nsim_evb();
+    if (!b) return NSIM_ENOMEM;
+    nsim_ev* h = &b->core;
+    h->batched = true;
+    const int rc = create_core(h, ds, cfg->log_eps, cfg->refractory_us,
+                               cfg->capacity_events, cfg->flags, 0,
+                               stage_alloc, stream);
+    if (rc) {
+        free_all(h);
+        delete b;
+        return rc;
+    }
+    h->autotune = cfg->autotune != 0;
+    h->stage_entries = cfg->stage_entries ? cfg->stage_entries
+                                          : std::min(stage_alloc, 512);
+    h->waves_per_block =
+        cfg->waves_per_block ? cfg->waves_per_block : nsim::kStepWaves;
+    h->use_graph = cfg->use_graph < 0 ? 1 : cfg->use_graph;
+    h->tuning.stage_entries = h->stage_entries;
+    h->tuning.waves_per_block = h->waves_per_block;
+    h->tuning.use_graph = h->use_graph;
+    h->want_stage = cfg->stage_entries;
+    h->want_wpb = cfg->waves_per_block;
+    h->want_graph = cfg->use_graph;
+    h->want_blocks = cfg->step_blocks;
+    if (cfg->step_blocks >= 0) h->step_blocks = cfg->step_blocks;
+    *out = b;
+    return NSIM_OK;
+}
+
+int nsim_evb_step(nsim_evb_t* b, const float* frames, const int64_t* t_us,
+                  int32_t K) {
+    if (!b) return NSIM_EINVAL;
+    nsim_ev* h = &b->core;
+    return do_batch_step(h, frames, t_us, K);
+}
+
+int nsim_evb_drain(nsim_evb_t* b, int64_t* env_offsets, int64_t* t,
+                   uint16_t* x, uint16_t* y, int8_t* p, int64_t cap,
+                   int64_t* n_out) {
+    if (!b) return NSIM_EINVAL;
+    nsim_ev* h = &b->core;
+    if (!n_out || !env_offsets) return fail(h, NSIM_EINVAL, "null n_out or offsets");
+    *n_out = 0;
+    if (cap < 0) return fail(h, NSIM_EINVAL, "negative cap");
+    DeviceGuard dg(h->device);
+    const int st = sync_and_status(h);
+    if (st == NSIM_EHIP) return st;
+    NSIM_HIP(h, hipMemcpy(env_offsets, h->env_off,
+                          sizeof(int64_t) * (h->n_env + 1),
+                          hipMemcpyDeviceToHost));
+    const int64_t n = env_offsets[h->n_env];
+    *n_out = n;
+    if (n > cap) return fail(h, NSIM_EINVAL, "cap is smaller than the output");
+    if (n > 0) {
+        if (!t || !x || !y || !p)
+            return fail(h, NSIM_EINVAL, "null destination array");
+        NSIM_HIP(h, hipMemcpyAsync(t, h->q_t, 8 * n, hipMemcpyDeviceToDevice,
+                                   h->stream));
+        NSIM_HIP(h, hipMemcpyAsync(x, h->q_x, 2 * n, hipMemcpyDeviceToDevice,
+                                   h->stream));
+        NSIM_HIP(h, hipMemcpyAsync(y, h->q_y, 2 * n, hipMemcpyDeviceToDevice,
+                                   h->stream));
+        NSIM_HIP(h, hipMemcpyAsync(p, h->q_p, n, hipMemcpyDeviceToDevice,
+                                   h->stream));
+        NSIM_HIP(h, hipStreamSynchronize(h->stream));
+    }
+    return st;
+}
+
+int nsim_evb_events(nsim_evb_t* b, const int64_t** t, const uint16_t** x,
+                    const uint16_t** y, const int8_t** p,
+                    const int64_t** env_offsets) {
+    if (!b || !t || !x || !y || !p || !env_offsets) return NSIM_EINVAL;
+    nsim_ev* h = &b->core;
+    *t = h->q_t;
+    *x = h->q_x;
+    *y = h->q_y;
+    *p = h->q_p;
+    *env_offsets = h->env_off;
+    return NSIM_OK;
+}
+
+int nsim_evb_sync(nsim_evb_t* b) {
+    if (!b) return NSIM_EINVAL;
+    DeviceGuard dg(b->core.device);
+    return sync_and_status(&b->core);
+}
+
+int nsim_evb_reset(nsim_evb_t* b) {
+    if (!b) return NSIM_EINVAL;
+    nsim_ev* h = &b->core;
+    DeviceGuard dg(h->device);
+    NSIM_HIP(h, nsim::launch_reset_header(h->hdr, h->hist, h->stream));
+    NSIM_HIP(h, hipMemsetAsync(h->env_off, 0, sizeof(int64_t) * (h->n_env + 1),
+                               h->stream));
+    h->initialized = false;
+    h->t_expect = 0;
+    return NSIM_OK;
+}
+
+int nsim_evb_destroy(nsim_evb_t* b) {
+    if (!b) return NSIM_OK;
+    nsim_ev* h = &b->core;
+    DeviceGuard dg(h->device);
+    (void)hipStreamSynchronize(h->stream);
+    free_all(h);
+    delete b;
+    return NSIM_OK;
+}
+
+const char* nsim_evb_last_error(const nsim_evb_t* b) {
+    if (!b) return kNoHandle;
+    return b->core.err.c_str();
+}
+
+int nsim_evb_get_tuning(nsim_evb_t* b, nsim_evb_tuning* out) {
+    if (!b || !out) return NSIM_EINVAL;
+    const nsim_ev* h = &b->core;
+    *out = h->tuning;
+    out->stage_entries = h->stage_entries;
+    out->waves_per_block = h->waves_per_block;
+    out->use_graph = h->use_graph;
+    out->step_blocks = h->step_blocks;
+    return NSIM_OK;
+}
+
+int nsim_evb_set_profiling(nsim_evb_t* b, int on) {
+    if (!b) return NSIM_EINVAL;
+    return nsim_ev_set_profiling(&b->core, on);
+}
+
+int nsim_evb_get_stats(nsim_evb_t* b, nsim_ev_stats* out) {
+    if (!b) return NSIM_EINVAL;
+    return nsim_ev_get_stats(&b->core, out);
 }
 
 int nsim_diag_fast_log2(const float* x, float* out, int64_t n, void* stream) {

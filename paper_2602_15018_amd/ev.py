@@ -77,6 +77,63 @@ class Stats(ctypes.Structure):
         return d
 
 
+class _EnvDesc(ctypes.Structure):
+    _fields_ = [
+        ("width", ctypes.c_int32),
+        ("height", ctypes.c_int32),
+        ("c_pos", ctypes.c_float),
+        ("c_neg", ctypes.c_float),
+        ("c_pos_map", ctypes.c_void_p),
+        ("c_neg_map", ctypes.c_void_p),
+    ]
+
+
+class _BatchConfig(ctypes.Structure):
+    _fields_ = [
+        ("log_eps", ctypes.c_double),
+        ("refractory_us", ctypes.c_int64),
+        ("capacity_events", ctypes.c_int64),
+        ("flags", ctypes.c_uint32),
+        ("autotune", ctypes.c_int32),
+        ("stage_entries", ctypes.c_int32),
+        ("waves_per_block", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+        ("step_blocks", ctypes.c_int32),
+    ]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [
+        ("stage_entries", ctypes.c_int32),
+        ("waves_per_block", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32),
+        ("step_blocks", ctypes.c_int32),
+        ("tuned", ctypes.c_int32),
+        ("n_candidates", ctypes.c_int32),
+        ("candidate_ms", ctypes.c_float * 32),
+        ("candidate_stage", ctypes.c_int32 * 32),
+        ("candidate_waves", ctypes.c_int32 * 32),
+        ("candidate_blocks", ctypes.c_int32 * 32),
+        ("candidate_graph", ctypes.c_int32 * 32),
+    ]
+
+    def as_dict(self):
+        n = self.n_candidates
+        return {
+            "stage_entries": self.stage_entries,
+            "waves_per_block": self.waves_per_block,
+            "use_graph": self.use_graph,
+            "step_blocks": self.step_blocks,
+            "tuned": self.tuned,
+            "candidates": [
+                {"stage_entries": self.candidate_stage[i],
+                 "waves_per_block": self.candidate_waves[i],
+                 "step_blocks": self.candidate_blocks[i],
+                 "graph": self.candidate_graph[i],
+                 "ms": self.candidate_ms[i]} for i in range(n)],
+        }
+
+
 _lib = None
 
 # Names every build must export (the declarations of include/nsim_ev.h).
@@ -86,6 +143,10 @@ EXPORTED = [
     "nsim_ev_reset", "nsim_ev_destroy", "nsim_ev_last_error",
     "nsim_ev_state_bytes", "nsim_ev_get_state", "nsim_ev_set_state",
     "nsim_ev_set_profiling", "nsim_ev_get_stats", "nsim_diag_fast_log2",
+    "nsim_evb_create", "nsim_evb_step", "nsim_evb_drain", "nsim_evb_events",
+    "nsim_evb_sync", "nsim_evb_reset", "nsim_evb_destroy",
+    "nsim_evb_last_error", "nsim_evb_get_tuning", "nsim_evb_set_profiling",
+    "nsim_evb_get_stats",
 ]
 
 
@@ -122,6 +183,20 @@ def load_library(path: str = _LIB_PATH):
         "nsim_ev_set_profiling": ([vp, c_int], c_int),
         "nsim_ev_get_stats": ([vp, ctypes.POINTER(Stats)], c_int),
         "nsim_diag_fast_log2": ([vp, vp, i64, vp], c_int),
+        "nsim_evb_create": ([ctypes.POINTER(_EnvDesc), i32,
+                             ctypes.POINTER(_BatchConfig), vp,
+                             ctypes.POINTER(vp)], c_int),
+        "nsim_evb_step": ([vp, vp, vp, i32], c_int),
+        "nsim_evb_drain": ([vp, vp, vp, vp, vp, vp, i64,
+                            ctypes.POINTER(i64)], c_int),
+        "nsim_evb_events": ([vp] + [ctypes.POINTER(vp)] * 5, c_int),
+        "nsim_evb_sync": ([vp], c_int),
+        "nsim_evb_reset": ([vp], c_int),
+        "nsim_evb_destroy": ([vp], c_int),
+        "nsim_evb_last_error": ([vp], ctypes.c_char_p),
+        "nsim_evb_get_tuning": ([vp, ctypes.POINTER(Tuning)], c_int),
+        "nsim_evb_set_profiling": ([vp, c_int], c_int),
+        "nsim_evb_get_stats": ([vp, ctypes.POINTER(Stats)], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -295,6 +370,165 @@ class EventSim:
     def stats(self) -> dict:
         s = Stats()
         self._check(self._lib.nsim_ev_get_stats(self._h, ctypes.byref(s)))
+        return s.as_dict()
+
+
+class EventBatch:
+    """Many independent event cameras stepped together (include/nsim_ev.h,
+    batched environments).
+
+    ``envs`` is a list of dicts with ``width``, ``height`` and either
+    ``c_pos``/``c_neg`` scalars or ``c_pos_map``/``c_neg_map`` arrays.
+    ``step(frames, t_us)`` takes a float32 device tensor [K][total] (each row
+    the concatenation of the environments' row-major frames) and returns
+    nothing; ``drain()`` returns (offsets, (t, x, y, p)) of the last call,
+    ordered by (environment, t, y, x).
+    """
+
+    def __init__(self, envs, log_eps=1e-3, refractory_us=0,
+                 capacity_events=1 << 22, input_is_log=False,
+                 force_fp64=False, autotune=True, stage_entries=0,
+                 waves_per_block=0, use_graph=-1, step_blocks=-1,
+                 stream=None):
+        import torch
+
+        if not torch.cuda.is_available():
+            raise RuntimeError("EventBatch needs a HIP device")
+        self._lib = load_library()
+        self._torch = torch
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        n = len(envs)
+        arr = (_EnvDesc * n)()
+        keep = []
+        self.sizes = []
+        for i, e in enumerate(envs):
+            W, H = int(e["width"]), int(e["height"])
+            self.sizes.append((W, H))
+            arr[i].width, arr[i].height = W, H
+            arr[i].c_pos = float(e.get("c_pos", 0.2))
+            arr[i].c_neg = float(e.get("c_neg", 0.2))
+            if e.get("c_pos_map") is not None:
+                for name in ("c_pos_map", "c_neg_map"):
+                    m = e[name]
+                    t = torch.as_tensor(np.asarray(m, np.float32)
+                                        if not torch.is_tensor(m) else m)
+                    t = t.to(self.device, torch.float32).contiguous().reshape(-1)
+                    if t.numel() != W * H:
+                        raise ValueError("threshold map has the wrong size")
+                    keep.append(t)
+                    setattr(arr[i], name, t.data_ptr())
+        self.n_env = n
+        self.total = sum(W * H for W, H in self.sizes)
+        cfg = _BatchConfig()
+        cfg.log_eps = float(log_eps)
+        cfg.refractory_us = int(refractory_us)
+        cfg.capacity_events = int(capacity_events)
+        cfg.flags = (NSIM_INPUT_LOG if input_is_log else 0) | \
+            (NSIM_FORCE_FP64 if force_fp64 else 0)
+        cfg.autotune = 1 if autotune else 0
+        cfg.stage_entries = int(stage_entries)
+        cfg.waves_per_block = int(waves_per_block)
+        cfg.use_graph = int(use_graph)
+        cfg.step_blocks = int(step_blocks)
+        self.capacity = int(capacity_events)
+        h = ctypes.c_void_p()
+        rc = self._lib.nsim_evb_create(arr, n, ctypes.byref(cfg),
+                                       _stream_ptr(stream), ctypes.byref(h))
+        del keep
+        if rc != NSIM_OK:
+            raise NsimError(rc, "nsim_evb_create rejected the description")
+        self._h = h
+
+    def _check(self, rc):
+        if rc != NSIM_OK:
+            msg = self._lib.nsim_evb_last_error(self._h).decode()
+            if rc == NSIM_EOVERFLOW:
+                raise OverflowError_(rc, msg)
+            raise NsimError(rc, msg)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.nsim_evb_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def step(self, frames, t_us):
+        torch = self._torch
+        if frames.dim() == 1:
+            frames = frames.unsqueeze(0)
+        if frames.dtype != torch.float32 or not frames.is_cuda:
+            raise TypeError("frames must be a float32 device tensor")
+        if frames.dim() != 2 or frames.shape[1] != self.total:
+            raise ValueError("frames must be [K][%d]" % self.total)
+        frames = frames.contiguous()
+        t = np.ascontiguousarray(np.asarray(t_us, dtype=np.int64).reshape(-1))
+        if t.shape[0] != frames.shape[0]:
+            raise ValueError("need one timestamp per frame")
+        self._check(self._lib.nsim_evb_step(self._h, _dev_ptr(frames),
+                                            ctypes.c_void_p(t.ctypes.data),
+                                            int(t.shape[0])))
+        self._last_frames = frames
+
+    def drain(self, out=None):
+        """(offsets [n_env + 1] numpy, (t, x, y, p) device tensors)."""
+        torch = self._torch
+        off = np.zeros(self.n_env + 1, np.int64)
+        got = ctypes.c_int64()
+        if out is None:
+            rc = self._lib.nsim_evb_drain(self._h,
+                                          ctypes.c_void_p(off.ctypes.data),
+                                          None, None, None, None, 0,
+                                          ctypes.byref(got))
+            if rc not in (NSIM_OK, NSIM_EINVAL):
+                self._check(rc)
+            n = int(got.value)
+            out = (torch.empty(n, dtype=torch.int64, device=self.device),
+                   torch.empty(n, dtype=torch.uint16, device=self.device),
+                   torch.empty(n, dtype=torch.uint16, device=self.device),
+                   torch.empty(n, dtype=torch.int8, device=self.device))
+        t, x, y, p = out
+        rc = self._lib.nsim_evb_drain(self._h, ctypes.c_void_p(off.ctypes.data),
+                                      _dev_ptr(t), _dev_ptr(x), _dev_ptr(y),
+                                      _dev_ptr(p), t.numel(), ctypes.byref(got))
+        self._check(rc)
+        m = int(got.value)
+        return off, (t[:m], x[:m], y[:m], p[:m])
+
+    def events_view(self):
+        """Device pointers (t, x, y, p, offsets) of the last call's output."""
+        ptrs = [ctypes.c_void_p() for _ in range(5)]
+        self._check(self._lib.nsim_evb_events(
+            self._h, *[ctypes.byref(q) for q in ptrs]))
+        return tuple(int(q.value or 0) for q in ptrs)
+
+    def sync(self):
+        self._check(self._lib.nsim_evb_sync(self._h))
+
+    def reset(self):
+        self._check(self._lib.nsim_evb_reset(self._h))
+
+    def tuning(self) -> dict:
+        tu = Tuning()
+        self._check(self._lib.nsim_evb_get_tuning(self._h, ctypes.byref(tu)))
+        return tu.as_dict()
+
+    def set_profiling(self, on=True):
+        self._check(self._lib.nsim_evb_set_profiling(self._h, 1 if on else 0))
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self._lib.nsim_evb_get_stats(self._h, ctypes.byref(s)))
         return s.as_dict()
 
 

@@ -76,6 +76,46 @@ WORKLOADS = {
 }
 
 
+# Many environments of uneven resolution stepped together: 16 at 240x180,
+# 16 at 346x260, 24 at 640x480 and 8 at 1280x720, 500 frames at 1000 FPS.
+# Environment i has its own seed 4000 + i, scene and threshold map
+# (mismatch N(0.2, 0.03) clipped, refractory 100 us); the two small sizes use
+# the 240x180 stream's scene mix (8 gratings, 16 blobs), the larger ones the
+# 640x480 stream's (24 gratings, 64 blobs), all at 50-500 px/s and +-1 rad/s.
+BATCH_SIZES = ([(240, 180)] * 16 + [(346, 260)] * 16 + [(640, 480)] * 24 +
+               [(1280, 720)] * 8)
+BATCH_WORKLOAD = "batch64_mixed_500f_1000fps"
+
+
+def batch_envs(frames: int = 500, fps: int = 1000, base_seed: int = 4000,
+               sizes=None):
+    """The environments of the batched workload, as one Workload each."""
+    out = []
+    for i, (W, H) in enumerate(BATCH_SIZES if sizes is None else sizes):
+        small = W * H < 100_000
+        out.append(Workload("batch_env%02d_%dx%d" % (i, W, H), H, W, frames,
+                            fps, 8 if small else 24, 16 if small else 64,
+                            50.0, 500.0, 1.0, True, 100, base_seed + i))
+    return out
+
+
+def render_batch(envs, first: int, count: int, device="cpu", out=None):
+    """Flat frames [count][sum H*W] of several environments: each row is the
+    concatenation of the environments' row-major frames."""
+    import torch
+
+    total = sum(w.pixels for w in envs)
+    if out is None:
+        out = torch.empty((count, total), dtype=torch.float32, device=device)
+    off = 0
+    for w in envs:
+        fr = render_workload(w, first, count, device=device)
+        out[:, off:off + w.pixels].copy_(fr.view(count, -1))
+        off += w.pixels
+        del fr
+    return out
+
+
 def frame_times(w: Workload, first: int = 0, count: int | None = None):
     """Integer microsecond timestamps t_f = t0 + f * dt of frames
     first .. first + count - 1."""
