@@ -1,4 +1,5 @@
-"""Build libnsim_ev.so in-tree with hipcc for gfx950."""
+"""Build the HIP libraries in-tree with hipcc for gfx950: libnsim_ev.so (the
+event path) and libnsim_up.so (the learned temporal upsampler)."""
 from __future__ import annotations
 
 import os
@@ -11,6 +12,8 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libnsim_ev.so")
 SOURCES = ["ev_kernels.hip", "ev_runtime.cpp"]
+UP_LIB = os.path.join(PKG, "libnsim_up.so")
+UP_SOURCES = ["up_kernels.hip", "up_runtime.cpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
@@ -26,10 +29,9 @@ def hipcc() -> str:
     return os.path.join(rocm, "bin", "hipcc")
 
 
-def build(verbose: bool = False, extra=()) -> str:
-    """Compile every source and link the shared library (always rebuilds)."""
+def build_one(lib, sources, verbose=False, extra=()) -> str:
     objs = []
-    for src in SOURCES:
+    for src in sources:
         obj = os.path.join(CSRC, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc(), *HIPCC_FLAGS, *extra, "-I", INCLUDE, "-I", CSRC,
                "-c", os.path.join(CSRC, src), "-o", obj]
@@ -39,16 +41,22 @@ def build(verbose: bool = False, extra=()) -> str:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)
         objs.append(obj)
-    tmp = LIB + ".tmp%d" % os.getpid()
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=gfx950", "-shared", "-fPIC", *objs,
            "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     for o in objs:
         os.remove(o)
-    return LIB
+    return lib
+
+
+def build(verbose: bool = False, extra=()) -> str:
+    """Compile every source and link both libraries (always rebuilds)."""
+    build_one(UP_LIB, UP_SOURCES, verbose, extra)
+    return build_one(LIB, SOURCES, verbose, extra)
 
 
 if __name__ == "__main__":

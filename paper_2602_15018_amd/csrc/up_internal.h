@@ -1,0 +1,101 @@
+// Internal layout shared by the upsampler runtime (up_runtime.cpp) and its
+// kernels (up_kernels.hip).  Not part of the public ABI.
+//
+// Activations and activation gradients are bfloat16 (uint16 storage) in
+// NHWC order; weights used by the convolutions are bfloat16 copies of the
+// FP32 master weights, laid out as GEMM operands [out channel][K] with
+// K = tap * C_in + c (tap = 3 ky + kx), zero-padded to Kpad (a multiple of
+// 16).  All accumulation is FP32.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nup {
+
+constexpr int kWave = 64;
+constexpr int kConvThreads = 256;     // 4 waves, 64 output pixels each
+constexpr int kWgradThreads = 256;    // 4 waves over one pixel range
+constexpr int kWgradKTile = 64;       // K columns per weight-gradient block
+constexpr int kHeadIn = 16;
+constexpr int kHeadOut = 7;
+
+// Implicit-GEMM 3x3 convolution (zero padding 1).  Input channels
+// [0, Ca) come from inA, [Ca, Ca + Cb) from inB (optionally at half
+// resolution: nearest 2x upsampling folded into the read).  With maskA set,
+// inA elements whose mask element is not positive read as zero (the ReLU
+// derivative of a backward pass).  Output channels [0, CoA) go to outA
+// (optionally added to its contents), the rest to outB.
+struct ConvArgs {
+    const uint16_t* inA;
+    const uint16_t* inB;
+    const uint16_t* maskA;
+    const uint16_t* wt;     // [Cout][Kpad]
+    const float* bias;      // [Cout] or null
+    uint16_t* outA;
+    uint16_t* outB;
+    int32_t N, H, W;
+    int32_t Ca, Cb, Cin;
+    int32_t Cout, CoA;
+    int32_t K, Kpad;
+    int32_t b_half;
+    int32_t relu;
+    int32_t accumA;
+};
+
+// Weight gradient of a 3x3 convolution: dW[co][k] = sum over pixels m of
+// dz[m][co] * X[m][k], X the im2col of the input (sources as ConvArgs),
+// dz = dy where y > 0.  Block (kt, pb) writes its partial sums of K columns
+// [64 kt, 64 kt + 64) over pixel block pb to part_w[pb][Cout][Kpad]; blocks
+// of kt == 0 also write the bias partial part_b[pb][Cout].
+struct WgradArgs {
+    const uint16_t* inA;
+    const uint16_t* inB;
+    const uint16_t* dy;
+    const uint16_t* y;
+    float* part_w;
+    float* part_b;
+    int32_t N, H, W;
+    int32_t Ca, Cb, Cin;
+    int32_t Cout, K, Kpad;
+    int32_t b_half;
+    int32_t pix_per_block;
+};
+
+hipError_t launch_conv(const ConvArgs& a, hipStream_t s);
+hipError_t launch_wgrad(const WgradArgs& a, int n_pix_blocks, hipStream_t s);
+// out[i] = sum over b of part[b * stride + src(i)], with src remapping the
+// padded [Cout][9][Cpad] layout to [Cout][9][Ci] (identity for biases).
+hipError_t launch_reduce(const float* part, int nblk, int64_t stride,
+                         int Cout, int Ci, int Cpad, int Kpad, int taps,
+                         float* out, hipStream_t s);
+hipError_t launch_make_input(const float* L0, const float* L8, uint16_t* x,
+                             int64_t M, hipStream_t s);
+hipError_t launch_pool(const uint16_t* x, uint16_t* y, int N, int H, int W,
+                       int C, hipStream_t s);
+hipError_t launch_pool_bwd_acc(uint16_t* ds, const uint16_t* dp, int N, int H,
+                               int W, int C, hipStream_t s);
+hipError_t launch_up_bwd(const uint16_t* dfull, uint16_t* dlow, int N, int H,
+                         int W, int C, hipStream_t s);
+hipError_t launch_head_fwd(const uint16_t* d1, const float* wh, const float* bh,
+                           const float* L0, const float* L8, float* pred,
+                           int N, int H, int W, hipStream_t s);
+hipError_t launch_loss_head_bwd(const float* pred, const float* target,
+                                const float* wh, float* g, uint16_t* dd1,
+                                float* part_loss, int N, int H, int W,
+                                int nblk, hipStream_t s);
+hipError_t launch_head_wgrad(const float* g, const uint16_t* d1, float* part,
+                             int64_t M, int nblk, hipStream_t s);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n,
+                       float lr, float c1, float c2, hipStream_t s);
+hipError_t launch_pack_weights(const float* w, uint16_t* fwd, uint16_t* bwd,
+                               int Cout, int Ci, int Cpad, int Kpad,
+                               int KpadB, hipStream_t s);
+hipError_t launch_log_frames(const float* I, float* L, int64_t n, float eps,
+                             hipStream_t s);
+hipError_t launch_mfma_probe(const uint16_t* A, const uint16_t* B, float* C,
+                             hipStream_t s);
+hipError_t launch_sum(const float* x, int n, float scale, float* out,
+                      hipStream_t s);
+
+}  // namespace nup

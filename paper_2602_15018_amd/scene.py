@@ -116,6 +116,25 @@ def render_batch(envs, first: int, count: int, device="cpu", out=None):
     return out
 
 
+# Learned-upsampler sequences: the 640x480 stream's scene generator, nine
+# frames at 1000 FPS (inputs 0 and 8, targets 1..7).  Training seeds are
+# 1_000_000 + s, evaluation seeds 2_000_000 + s (disjoint).
+UPSAMPLER_SCENE = "vga640x480_1000f_1000fps"
+TRAIN_SEED0 = 1_000_000
+EVAL_SEED0 = 2_000_000
+
+
+def upsampler_sequence(seed: int, crop=None, t0_frame: int = 0, n: int = 9,
+                       device="cpu"):
+    """Intensity frames [n][h][w] of the scene with ``seed`` (the 640x480
+    stream's generator) at 1000 FPS from frame t0_frame, optionally a crop
+    (y0, x0, h, w)."""
+    w = WORKLOADS[UPSAMPLER_SCENE]
+    p = scene_params(w, seed=seed)
+    t = w.t0_us + (t0_frame + np.arange(n, dtype=np.int64)) * w.dt_us
+    return render(p, t, device=device, crop=crop)
+
+
 def frame_times(w: Workload, first: int = 0, count: int | None = None):
     """Integer microsecond timestamps t_f = t0 + f * dt of frames
     first .. first + count - 1."""
@@ -200,20 +219,22 @@ def scene_params(w: Workload, seed: int | None = None,
     return p
 
 
-def render(p: SceneParams, t_us, device="cpu", out=None):
+def render(p: SceneParams, t_us, device="cpu", out=None, crop=None):
     """Render intensity frames [len(t_us)][H][W] float32 at the given times.
 
     Gratings rotate about, and translate with, their own centre; blobs are
-    anisotropic Gaussians whose centres wrap around the image (toroidal)."""
+    anisotropic Gaussians whose centres wrap around the image (toroidal).
+    ``crop = (y0, x0, h, w)`` renders only that window of the scene."""
     import torch
 
     t_s = torch.as_tensor(np.asarray(t_us, dtype=np.float64) * 1e-6,
                           dtype=torch.float64)
     B = t_s.shape[0]
     H, W = p.height, p.width
-    ys = torch.arange(H, dtype=torch.float32, device=device).view(1, H, 1)
-    xs = torch.arange(W, dtype=torch.float32, device=device).view(1, 1, W)
-    acc = torch.zeros((B, H, W), dtype=torch.float32, device=device)
+    y0, x0, h, w = (0, 0, H, W) if crop is None else crop
+    ys = (torch.arange(h, dtype=torch.float32, device=device) + float(y0)).view(1, h, 1)
+    xs = (torch.arange(w, dtype=torch.float32, device=device) + float(x0)).view(1, 1, w)
+    acc = torch.zeros((B, h, w), dtype=torch.float32, device=device)
 
     def per_frame(values):  # float64 host math -> [B,1,1] float32 on device
         return torch.as_tensor(values, dtype=torch.float32).to(device).view(B, 1, 1)

@@ -1,5 +1,5 @@
-"""Host-side checks of the C ABI: the library builds, loads, and exports
-exactly what include/nsim_ev.h declares (no GPU needed, no compute calls)."""
+"""Host-side checks of the C ABIs: each library builds, loads, and exports
+exactly what its header declares (no GPU needed, no compute calls)."""
 import ctypes
 import os
 import re
@@ -7,41 +7,59 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "nsim_ev.h")
-LIB = os.path.join(ROOT, "paper_2602_15018_amd", "libnsim_ev.so")
+PKG = os.path.join(ROOT, "paper_2602_15018_amd")
+LIBS = {
+    "ev": (os.path.join(ROOT, "include", "nsim_ev.h"),
+           os.path.join(PKG, "libnsim_ev.so")),
+    "up": (os.path.join(ROOT, "include", "nsim_up.h"),
+           os.path.join(PKG, "libnsim_up.so")),
+}
 
 
-def declared_functions():
-    src = open(HEADER).read()
+def declared_functions(which="ev"):
+    src = open(LIBS[which][0]).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(nsim_\w+)\s*\(", src)))
 
 
 def test_header_declares_expected_api():
-    names = declared_functions()
+    names = declared_functions("ev")
     for n in ("nsim_ev_create", "nsim_ev_step", "nsim_ev_drain",
-              "nsim_ev_destroy"):
+              "nsim_ev_destroy", "nsim_evb_create", "nsim_evb_step",
+              "nsim_evb_drain", "nsim_evb_destroy"):
+        assert n in names
+    names = declared_functions("up")
+    for n in ("nsim_up_create", "nsim_up_forward", "nsim_up_train_step",
+              "nsim_up_destroy"):
         assert n in names
 
 
-def test_library_exports_every_declared_symbol():
-    if not os.path.exists(LIB):
+@pytest.mark.parametrize("which", sorted(LIBS))
+def test_library_exports_every_declared_symbol(which):
+    lib_path = LIBS[which][1]
+    if not os.path.exists(lib_path):
         pytest.skip("library not built (run __graft_entry__.build())")
     import torch  # noqa: F401  (same HIP runtime as the binding uses)
-    lib = ctypes.CDLL(LIB)
-    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    lib = ctypes.CDLL(lib_path)
+    missing = [n for n in declared_functions(which) if not hasattr(lib, n)]
     assert not missing, missing
 
 
 def test_binding_knows_every_declared_symbol():
-    from paper_2602_15018_amd import ev
-    assert sorted(ev.EXPORTED) == declared_functions()
+    from paper_2602_15018_amd import ev, up
+    assert sorted(ev.EXPORTED) == declared_functions("ev")
+    assert sorted(up.EXPORTED) == declared_functions("up")
 
 
 def test_binding_fails_loudly_without_device():
     import torch
     if torch.cuda.is_available():
         pytest.skip("a device is present")
-    from paper_2602_15018_amd.ev import EventSim
+    from paper_2602_15018_amd.ev import EventBatch, EventSim
+    from paper_2602_15018_amd.up import Upsampler
     with pytest.raises(RuntimeError):
         EventSim(8, 8)
+    with pytest.raises(RuntimeError):
+        EventBatch([dict(width=8, height=8)])
+    with pytest.raises(RuntimeError):
+        Upsampler(1024)
