@@ -36,11 +36,11 @@ HBM_PEAK_GBS = 8000.0
 # the state (L_init 8, counters 8, previous sample 4, refractory time 4) and
 # both threshold maps (8), and writes counters, previous sample and
 # refractory time (16); per pixel-update it reads one float32 frame sample
-# (4); per event it writes one packed event (8).
+# (4); per event it writes one packed staging entry (4).
 STATE_READ_B = 32
 STATE_WRITE_B = 16
 FRAME_B = 4
-PACKED_EVENT_B = 8
+PACKED_EVENT_B = 4
 
 
 def log(msg):
@@ -59,10 +59,14 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-frames-per-launch", type=int, default=0)
     ap.add_argument("--workload", default="hd",
-                    choices=["hd", "batch64"],
+                    choices=["hd", "batch64", "learned"],
                     help="hd: the 1280x720 stream (default); batch64: 64 "
                          "environments of uneven size stepped together, "
-                         "against the same environments as separate streams")
+                         "against the same environments as separate streams; "
+                         "learned: train the upsampler, then 125-FPS frames "
+                         "-> upsampler -> events against the 1000-FPS path")
+    ap.add_argument("--train-sequences", type=int, default=10_000)
+    ap.add_argument("--eval-pairs", type=int, default=16)
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (the reference "
                          "dispatch that scales profiler byte counters)")
@@ -288,6 +292,164 @@ def bench_batch(args):
     print(json.dumps(result), flush=True)
 
 
+def bench_learned(args):
+    """Learned upsampler: one pass over seeded training sequences (batch 16,
+    256x256 crops), then on held-out 640x480 scenes the event-count and
+    timestamp error of (125-FPS frames -> upsampler -> events at 1000 FPS)
+    and of linear interpolation against the 1000-FPS stream, and the time of
+    both paths.  One timed step = one 640x480 stream of 8 * eval_pairs
+    frame intervals through the learned path (render at 125 FPS, log,
+    upsample, events)."""
+    import torch
+
+    from paper_2602_15018_amd import learned, scene
+    from paper_2602_15018_amd.up import Upsampler, log_frames
+    from oracle import unet
+
+    dev = torch.device("cuda", 0)
+    w = scene.WORKLOADS[scene.UPSAMPLER_SCENE]
+    H, W = w.height, w.width
+    up = Upsampler(max(16 * 256 * 256, 8 * H * W), seed=1)
+    lin = Upsampler(8 * H * W, seed=1)
+    log("training on %d sequences" % args.train_sequences)
+    losses, t_train, t_wall = learned.train(up, args.train_sequences, 16, 256,
+                                            log=log)
+    cp, cn = scene.threshold_maps(w)
+    P = args.eval_pairs
+    evals = {"learned": [], "linear": []}
+    for s_ in range(2):
+        I, t = learned.full_rate_frames(scene.EVAL_SEED0 + s_, P, dev)
+        ref = learned.stream_events(I, t, cp, cn, w.refractory_us, False, 1 << 26)
+        Llow = log_frames(I[0::learned.RATE].contiguous())
+        for name, net in (("learned", up), ("linear", lin)):
+            Lf = learned.upsampled_log_frames(net, Llow)
+            got = learned.stream_events(Lf, t, cp, cn, w.refractory_us, True,
+                                        1 << 26)
+            evals[name].append(learned.compare_streams(got, ref, W, H))
+        log("eval seq %d: learned %s linear %s" % (
+            s_, json.dumps(evals["learned"][-1]), json.dumps(evals["linear"][-1])))
+
+    def mean(name, key):
+        return float(np.mean([e[key] for e in evals[name]]))
+
+    # timing: plain full rate vs learned, same scene and interval count
+    seed = scene.EVAL_SEED0 + 7
+    p = scene.scene_params(w, seed=seed)
+    F = learned.RATE * P + 1
+    t_full = w.t0_us + np.arange(F, dtype=np.int64) * w.dt_us
+    t_low = t_full[0::learned.RATE]
+
+    def render(ts):
+        out = torch.empty((len(ts), H, W), dtype=torch.float32, device=dev)
+        for a in range(0, len(ts), 32):
+            out[a:a + 32] = scene.render(p, ts[a:a + 32], device=dev)
+        return out
+
+    def events_of(frames, is_log):
+        from paper_2602_15018_amd.ev import EventSim
+        sim = EventSim(W, H, c_pos_map=cp, c_neg_map=cn, log_eps=1e-3,
+                       refractory_us=w.refractory_us, capacity_events=1 << 26,
+                       input_is_log=is_log)
+        sim.step(frames, t_full)
+        sim.sync()
+        n = sim.pending()
+        sim.close()
+        return n
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+
+    frames_full = render(t_full)
+    frames_low = render(t_low)
+    torch.cuda.synchronize()
+    t_render_full = timed(lambda: render(t_full), 2)
+    t_render_low = timed(lambda: render(t_low), 2)
+    t_events_plain = timed(lambda: events_of(frames_full, False), 2)
+    Llow = log_frames(frames_low)
+    t_upsample = timed(lambda: learned.upsampled_log_frames(up, log_frames(frames_low)), 2)
+    Lf = learned.upsampled_log_frames(up, Llow)
+    t_events_learned = timed(lambda: events_of(Lf, True), 2)
+    steps = max(1, args.steps)
+    t_learned_step = timed(lambda: events_of(
+        learned.upsampled_log_frames(up, log_frames(render(t_low))), True), steps)
+    t_plain_step = t_render_full + t_events_plain
+    # the upsampler forward alone, 8 pairs per call
+    L8 = torch.randn(8, H, W, device=dev) * 0.1 - 1.0
+    t_fwd = timed(lambda: up.forward(L8, L8), 5) / 8
+    flop_pair = 2.0 * unet.macs_per_pixel() * H * W
+    # paper's renderer rate as context: Habitat at VGA about 3000 FPS
+    r_ctx = 1.0 / 3000.0
+    plain_ctx = 8 * P * r_ctx + t_events_plain
+    learned_ctx = P * r_ctx + t_upsample + t_events_learned
+    # CPU: the FP64 oracle's forward on one 640x480 pair
+    par = unet.init_params(1)
+    Lc = np.random.default_rng(0).normal(-1.0, 0.1, size=(1, H, W))
+    c0 = time.perf_counter()
+    unet.forward(par, Lc, Lc)
+    t_cpu_fwd = time.perf_counter() - c0
+    pu = H * W * (F - 1)
+    result = {
+        "metric": METRIC,
+        "value": pu / t_learned_step / 1e9,
+        "unit": "Gpixel-updates/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": 1,
+        "ms_per_step": t_learned_step * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {
+            "workload": "learned_vga640x480_125to1000fps",
+            "height": H, "width": W, "pairs": P, "frames_full_rate": F,
+            "train_sequences": args.train_sequences, "train_batch": 16,
+            "train_crop": 256, "refractory_us": w.refractory_us,
+        },
+        "training": {"seconds_in_steps": t_train, "seconds_wall": t_wall,
+                     "loss_first": losses[0][1], "loss_last": losses[-1][1]},
+        "error_vs_full_rate": {
+            "learned": {k: mean("learned", k) for k in evals["learned"][0]},
+            "linear": {k: mean("linear", k) for k in evals["linear"][0]},
+        },
+        "speedup": {
+            "measured_render": t_plain_step / t_learned_step,
+            "paper_render_rate_context": plain_ctx / learned_ctx,
+            "ms_plain": t_plain_step * 1e3, "ms_learned": t_learned_step * 1e3,
+            "ms_render_full": t_render_full * 1e3,
+            "ms_render_low": t_render_low * 1e3,
+            "ms_events_plain": t_events_plain * 1e3,
+            "ms_events_learned": t_events_learned * 1e3,
+            "ms_upsample": t_upsample * 1e3,
+        },
+        "roofline": {
+            "kernel": "upsampler forward (all layers)",
+            "bound": "mfma",
+            "achieved": flop_pair / t_fwd / 1e12,
+            "peak": 2500.0,
+            "unit": "TFLOP/s",
+            "frac": flop_pair / t_fwd / 1e12 / 2500.0,
+            "traffic": None,
+            "ms_per_pair": t_fwd * 1e3,
+        },
+        "cpu_baseline": {
+            "value": flop_pair / t_cpu_fwd / 1e12, "unit": "TFLOP/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "FP64 oracle forward of one 640x480 pair (%.2f s)" % t_cpu_fwd,
+        },
+    }
+    up.close()
+    lin.close()
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -296,6 +458,9 @@ def main():
         sys.exit(2)
     if args.workload == "batch64":
         bench_batch(args)
+        return
+    if args.workload == "learned":
+        bench_learned(args)
         return
     import torch
 

@@ -74,7 +74,7 @@ typedef struct nsim_ev nsim_ev_t;
 
 /* Create a stream.  Allocates state (about 40 B per pixel with threshold
  * maps), per-wave staging (8 KB per 64 pixels), and per event of capacity
- * 13 B of queue plus 24 B of staging and sort scratch.
+ * 13 B of queue plus 20 B of staging and sort scratch.
  * Returns NSIM_EINVAL for a bad config (out is set to NULL). */
 int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out);
 
@@ -189,8 +189,10 @@ typedef struct nsim_evb_config {
     uint32_t flags;           /* NSIM_INPUT_LOG | NSIM_FORCE_FP64 */
     int32_t autotune;         /* 1: time candidates on the first stepping
                                  call for every knob left at 0 / -1 */
-    int32_t stage_entries;    /* 0 = tuned/default, else 64 .. 2000 events
-                                 staged in LDS per 64 pixels */
+    int32_t stage_entries;    /* 0 = tuned/default, else 64 .. 2^20 staging
+                                 slots (4 B of device memory each) per 64
+                                 pixels; crossings beyond them are staged
+                                 again into an exactly sized pool segment */
     int32_t waves_per_block;  /* 0 = tuned/default, else 1 .. 4 */
     int32_t use_graph;        /* -1 = tuned/default (on), 0 off, 1 on */
     int32_t step_blocks;      /* -1 = tuned/default (0); 0 = one wave per

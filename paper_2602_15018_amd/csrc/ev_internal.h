@@ -10,8 +10,8 @@ namespace nsim {
 constexpr int kWave = 64;
 constexpr int kStepMaxThreads = 256;         // at most 4 waves per workgroup
 constexpr int kStepWaves = 4;                // default waves per workgroup
-constexpr int kStepLdsEntries = 2000;        // default staged events per wave
-constexpr int kStepMaxLdsEntries = 2000;     // (4 B each, in LDS)
+constexpr int kStepLdsEntries = 2048;        // default staging slots per wave
+constexpr int kStepMaxLdsEntries = 1 << 20;  // (4 B each, global memory)
 constexpr int kScanTile = 1024;              // per-wave counts per scan block
 constexpr int kMaxEnvs = 4096;
 constexpr int kChunk = 8;                     // frames prefetched per chunk
@@ -51,7 +51,7 @@ struct alignas(64) Header {
     int64_t events_total; // committed events
     int64_t fp64_evals;   // candidate crossings evaluated in FP64
     int32_t internal_err; // 1: a bounded wait gave up
-    int32_t pad;
+    int32_t stage_full;   // 1: the staging pool could not hold a launch
     int64_t alloc;        // packed-event slots handed out in this launch
     // diagnostic counters (summed over launches):
     // 0 FP64 count evaluations (lanes), 1 FP64 timestamp evaluations
@@ -64,9 +64,11 @@ struct alignas(64) Header {
 
 // Arguments of the fused step kernel.  Frame times travel by value.  Each
 // wave of 64 pixels is independent: it owns the staging segment
-// [wave * stage_entries, +stage_entries); a wave whose events outgrow its
-// LDS staging takes a segment from the overflow pool behind the fixed
-// segments with one atomic.  (base, count) go to seg_base / seg_count.
+// [wave * stage_entries, +stage_entries) of packed entries
+// (time offset << 7 | lane << 1 | p > 0, or a hole for a suppressed
+// crossing); a wave whose crossings outgrow it takes a segment of the exact
+// size from the pool behind the fixed segments with one atomic.  (base,
+// events, slots) go to seg_base / seg_count / seg_slots.
 struct StepArgs {
     const float* frames;   // [K][frame_stride]
     int64_t frame_stride;  // samples per flat frame (all environments)
@@ -74,8 +76,8 @@ struct StepArgs {
     int32_t nwaves;        // waves of the padded pixel space
     const EnvRec* envs;
     const int32_t* wave_env;  // [nwaves] environment of each wave
-    int32_t stage_entries; // LDS staging entries per wave (<= 2000)
-    int32_t key_tbits;     // key = env << key_tbits | time offset
+    int32_t stage_entries; // staging slots per wave
+    int32_t key_tbits;     // sort key = env << key_tbits | time offset
     const double* L_init;  // [P]
     int2* nud[2];          // (n_up, n_down) [P], ping-pong
     float* prev[2];        // previous sample (I or L) [P], ping-pong
@@ -90,11 +92,11 @@ struct StepArgs {
     int64_t T0;            // absolute time of the frame before frames[0]
     float eT;              // absolute-time rounding allowance of FP64 tau
     float pad0;
-    uint32_t* out_key;     // staging: key as above
-    uint32_t* out_val;     //          val = pixel << 1 | (p > 0)
+    uint32_t* out_key;     // staging: packed entries
     int64_t out_cap;       // staging entries: fixed segments + overflow pool
     int64_t* seg_base;     // [nwaves] first staging entry of the wave
     uint32_t* seg_count;   // [nwaves] events of the wave
+    uint32_t* seg_slots;   // [nwaves] staging slots used (holes included)
     Header* hdr;
     uint32_t flags;
     uint32_t pad1;
@@ -113,16 +115,20 @@ struct ScanArgs {
     Header* hdr;
 };
 
-// Gather the per-wave segments into pixel order, build the digit
+// Gather the per-wave segments into pixel order (dropping holes and
+// expanding entries to sort key and pixel value), build the digit
 // histograms of every radix pass and clear the passes' look-back words.
 struct GatherArgs {
     const int64_t* seg_base;
     const uint32_t* seg_count;
+    const uint32_t* seg_slots;
     const uint32_t* pref;
     int32_t nwaves;
     int32_t npass;
-    const uint32_t* skey;    // staging
-    const uint32_t* sval;
+    const uint32_t* skey;    // staging (packed entries)
+    const int32_t* wave_env;
+    int32_t key_tbits;
+    int32_t pad;
     uint32_t* dkey;          // dense, pixel order
     uint32_t* dval;
     Header* hdr;

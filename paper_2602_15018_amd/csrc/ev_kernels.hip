@@ -342,48 +342,260 @@ __device__ __forceinline__ void exact_levels(Px& q, double eps) {
     refresh_thresholds<LOGIN>(q, eps);
 }
 
-// Copy a wave's staged entries to the packed output, dropping suppressed
-// crossings; returns the next output position.  Entry layout:
-// (time offset << 7) | (lane << 1) | (p > 0); the output key is the time
-// offset under the environment's high bits.
-__device__ __forceinline__ int64_t flush_wave(const uint32_t* buf, int count,
-                                              uint32_t pix0, uint32_t key_hi,
-                                              uint32_t* okey, uint32_t* oval,
-                                              int64_t g, int64_t cap) {
-    const uint64_t lt = lanemask_lt();
-    for (int j0 = 0; j0 < count; j0 += kWave) {
-        const int j = j0 + lane_id();
-        uint32_t e = kEntryHole;
-        if (j < count) e = buf[j];
-        const bool v = e != kEntryHole;
-        const uint64_t m = __ballot(v);
-        const int64_t pos = g + __popcll(m & lt);
-        if (v && pos < cap) {
-            okey[pos] = key_hi | (e >> 7);
-            oval[pos] = ((pix0 + ((e >> 1) & 63u)) << 1) | (e & 1u);
-        }
-        g += __popcll(m);
-    }
-    return g;
+// ---- the frame walk, in two phases per wave ----------------------------
+//
+// Phase A walks the frames in lockstep: the per-frame test against the
+// FP32 thresholds, the crossing count of candidate lanes, the staging slots
+// of the frame's crossings ((frame, pixel, k) order: a wave scan of the
+// counts) and the move of the levels.  Each frame with crossings leaves a
+// record in the lane's LDS queue.  Phase B drains the queues in rounds,
+// round r taking every lane's r-th record: timestamps, the refractory
+// filter and the staged entry (or hole) of each crossing.  Only lanes with
+// records work in a round, instead of every lane on every frame that has a
+// crossing somewhere in the wave.
+//
+// Staged entry: (time offset << 7) | (lane << 1) | (p > 0), written straight
+// to the wave's staging segment in global memory; a suppressed crossing
+// leaves a hole.
+
+constexpr int kRecMax = 4;                 // records per lane between drains
+constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // crossings past the segment
+
+struct Rec {
+    uint32_t slot;   // staging slot of the frame's first crossing
+    uint32_t meta;   // n (bits 0..20) | frame (21..28) | up (29) | f64 (30)
+    float I;         // the frame's sample
+    float prev;      // the previous frame's sample
+};
+
+// Phase B's copy of the lattice state: the levels and counts replayed
+// record by record (the same operations as phase A, so the same values),
+// and the refractory time.
+struct Bst {
+    double Xh, Xl;
+    int nup, ndn;
+    int tlast;
+};
+
+__device__ __forceinline__ int wave_max_small(int v) {
+    int m = 0;
+    for (int b = 1; b <= kRecMax; ++b)
+        if (__ballot(v >= b)) m = b;
+    return m;
 }
 
-// Walk the launch's frames for one lane's pixel.  FIRST: stage events in
-// LDS until the wave's buffer would overflow (then only count).  RERUN:
-// regenerate the same events from the same starting state and flush the
-// buffer to global memory whenever it fills.
-template <bool LOGIN, bool RERUN>
-__device__ __forceinline__ void walk_frames(
-    const StepArgs& a, Px& q, bool valid, const float* fr, uint32_t pix0,
-    uint32_t key_hi, uint32_t* buf, float* fslab, int& cursor, bool& over,
-    int& emitted, int& f64count, int64_t& gpos, int* dg) {
+// Crossing count of one frame for the candidate lanes: FP32 certainty for
+// exactly one crossing, an FP64 level walk with a small guard otherwise, the
+// FP64 replica of the definition when even that cannot decide.
+template <bool LOGIN>
+__device__ __forceinline__ void count_frame(const Px& q, float I, bool cand,
+                                            bool force64, double eps, int& n,
+                                            bool& up, bool& f64, int* dg) {
+    n = 0;
+    up = false;
+    f64 = false;
+    bool slow = false;
+    if (cand) {
+        up = I > q.Ahi;
+        const bool one = up ? (I >= q.Bhi && I <= q.Chi)
+                            : (I <= q.Blo && I >= q.Clo);
+        if (force64)
+            f64 = true;
+        else if (one)
+            n = 1;
+        else
+            slow = true;
+    }
+    if (__ballot(slow)) {
+        if (slow) {
+            const double s = LOGIN ? (double)I : (double)I + eps;
+            double X = up ? q.Xh : q.Xl;
+            const double E = up ? q.Ep : q.En;
+            for (;;) {
+                const double lo = lvl_below<LOGIN>(X, kG64, 0.0);
+                const double hi = lvl_above<LOGIN>(X, kG64, 0.0);
+                const bool crossed = up ? (s >= hi) : (s <= lo);
+                const bool short_ = up ? (s < lo) : (s > hi);
+                if (crossed) {
+                    ++n;
+                    if (n >= kFastMaxCross) {
+                        f64 = true;
+                        break;
+                    }
+                    X = lvl_step<LOGIN>(X, E);
+                    continue;
+                }
+                if (!short_) f64 = true;
+                break;
+            }
+            if (f64) n = 0;
+        }
+    }
+    if (__ballot(f64)) {
+        ++dg[4];
+        if (f64) {
+            ++dg[0];
+            const LogPair lp = log_pair64<LOGIN>(q.prev, I, eps);
+            const Count64 c = count64(q.L_init, q.nup, q.ndn, q.cp, q.cn, lp.L1);
+            n = c.n;
+            up = c.up != 0;
+        }
+    }
+}
+
+// Phase B: timestamps, refractory filter and staged entries of the queued
+// records, in rounds over the lanes' queues.
+template <bool LOGIN>
+__device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
+                                              Bst& b, const Rec* recs,
+                                              int rcount, const int* s_toff,
+                                              uint32_t* out, int64_t cap,
+                                              int& emitted, int& f64count,
+                                              int* dg) {
+    const int lane = lane_id();
+    const uint32_t lane_bits = ((uint32_t)lane) << 1;
     const float eps_f = a.log_eps_f;
     const double eps = a.log_eps;
     const int tref = a.tref;
+    const int rmax = wave_max_small(rcount);
+    for (int r = 0; r < rmax; ++r) {
+        const bool act = r < rcount;
+        Rec rc;
+        rc.slot = kNoSlot;
+        rc.meta = 0;
+        rc.I = 1.0f;
+        rc.prev = 1.0f;
+        if (act) rc = recs[r * kWave + lane];
+        const int n = (int)(rc.meta & 0x1FFFFFu);
+        const int k = (int)((rc.meta >> 21) & 0xFFu);
+        const bool up = ((rc.meta >> 29) & 1u) != 0;
+        const bool f64 = ((rc.meta >> 30) & 1u) != 0;
+        const float I = rc.I, prev = rc.prev;
+        const int tp = k > 0 ? s_toff[k - 1] : 0;
+        const int dt = s_toff[k] - tp;
+        ++dg[7];
+        // interpolation fraction of crossing j: N_j / D with N_j =
+        // ln(X_j / x0), D = ln(x1 / x0) (log input: plain differences),
+        // N_j = N_1 + j * step
+        float D = 1.f, invD = 1.f, relD = 0.f;
+        float N1 = 0.f, relN1 = 0.f, absN = 0.f, cstep = 0.f;
+        if (n > 0 && !f64) {
+            const double X1 = up ? b.Xh : b.Xl;
+            cstep = up ? q.cp : -q.cn;
+            if (LOGIN) {
+                D = (float)((double)I - (double)prev);
+                relD = 0x1p-24f;
+                N1 = (float)(X1 - (double)prev);
+                relN1 = 0x1p-24f;
+                absN = (float)(0x1p-36 * (1.0 + fabs(X1)));
+            } else {
+                const LnRatio d = ln_ratio(I - prev, (I + prev) + 2.0f * eps_f,
+                                           I + eps_f, prev + eps_f);
+                D = d.v;
+                relD = d.rel;
+                const double x0d = (double)prev + eps;
+                const LnRatio nn = ln_ratio((float)(X1 - x0d), (float)(X1 + x0d),
+                                            (float)X1, prev + eps_f);
+                N1 = nn.v;
+                relN1 = nn.rel;
+                absN = 0x1p-35f;
+            }
+            invD = fast_rcp(D);
+        }
+        const float dtf = (float)dt;
+        // |error of tau_j| <= alpha + beta * phi_j (safety 1.25)
+        const float alpha =
+            1.25f * dtf * (relN1 * fabsf(N1) + absN) * fabsf(invD) + a.eT;
+        const float beta = 1.25f * dtf * (relD + 0x1p-21f + 0x1p-23f);
+        double L0d = 0.0, L1d = 0.0;
+        bool have_d = false;
+        for (int j = 0; __ballot(j < n); ++j) {
+            ++dg[5];
+            int tt = 0;
+            bool need = false;
+            if (j < n) {
+                need = f64;
+                if (!need) {
+                    const float Nj = fmaf((float)j, cstep, N1);
+                    const float phi = Nj * invD;
+                    const float tau = dtf * phi;
+                    const float et = fmaf(beta, phi, alpha);
+                    const float c1 = ceilf(tau - et);
+                    const float c2 = ceilf(tau + et);
+                    if (c1 == c2 && et < 0.25f)
+                        tt = tp + (int)c2;
+                    else
+                        need = true;
+                }
+            }
+            if (__ballot(need)) {
+                ++dg[6];
+                if (need) {
+                    ++dg[1];
+                    if (!have_d) {
+                        const LogPair lp = log_pair64<LOGIN>(prev, I, eps);
+                        L0d = lp.L0;
+                        L1d = lp.L1;
+                        have_d = true;
+                    }
+                    ++f64count;
+                    tt = time64(q.L_init, b.nup, b.ndn, q.cp, q.cn, up ? 1 : 0, j,
+                                L0d, L1d, a.T0, tp, dt);
+                }
+            }
+            if (j < n) {
+                const bool emit = (tt - b.tlast) >= tref;
+                if (emit) b.tlast = tt;
+                emitted += emit ? 1 : 0;
+                if (rc.slot != kNoSlot) {
+                    const int64_t s = (int64_t)rc.slot + j;
+                    if (s < cap)
+                        out[s] = emit ? (((uint32_t)tt << 7) | lane_bits |
+                                         (up ? 1u : 0u))
+                                      : kEntryHole;
+                }
+            }
+        }
+        // replay the record's move of the levels
+        if (n > 0) {
+            if (up)
+                b.nup += n;
+            else
+                b.ndn += n;
+            if (f64) {
+                const Levels l = levels64<LOGIN>(q.L_init, b.nup, b.ndn, q.cp, q.cn);
+                b.Xh = l.Xh;
+                b.Xl = l.Xl;
+            } else {
+                const double E = up ? q.Ep : q.En;
+                for (int i = 0; i < n; ++i) {
+                    b.Xh = lvl_step<LOGIN>(b.Xh, E);
+                    b.Xl = lvl_step<LOGIN>(b.Xl, E);
+                }
+            }
+        }
+    }
+}
+
+// Walk the launch's frames for one lane's pixel (phase A), draining the
+// record queues (phase B) whenever one fills and at the end.  Crossings get
+// staging slots [0, cap) of `out`; once a frame's crossings do not fit, the
+// segment is marked overflowed and later crossings are only counted.
+// `slots` returns the slots the launch needs (holes included).
+template <bool LOGIN>
+__device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, Bst& b,
+                                           bool valid, const float* fr,
+                                           Rec* recs, float* fslab,
+                                           const int* s_toff, uint32_t* out,
+                                           int64_t cap, int64_t& slots,
+                                           bool& over, int& emitted,
+                                           int& f64count, int* dg) {
+    const double eps = a.log_eps;
     const bool force64 = (a.flags & 0x2u) != 0;
-    const uint32_t lane_bits = ((uint32_t)lane_id()) << 1;
     const int64_t P = a.frame_stride;
     const int K = a.K;
-    const int S = a.stage_entries;
+    const int lane = lane_id();
+    int rcount = 0;
 
     // Frames are prefetched a chunk of kChunk frames ahead into registers;
     // at the start of each chunk the registers (loaded one chunk earlier)
@@ -395,7 +607,6 @@ __device__ __forceinline__ void walk_frames(
     for (int u = 0; u < U; ++u)
         r[u] = (valid && u < K) ? __builtin_nontemporal_load(fr + (int64_t)u * P)
                                 : 1.0f;
-    const int lane = lane_id();
 
     for (int kc = 0; kc < K; kc += U) {
 #pragma unroll
@@ -415,221 +626,55 @@ __device__ __forceinline__ void walk_frames(
             const bool cand = valid && ((I > q.Ahi) || (I < q.Alo));
             if (__ballot(cand)) {
                 ++dg[3];
-                const int tp = k > 0 ? a.toff[k - 1] : 0;
-                const int dt = a.toff[k] - tp;
-                // ---- crossing count: FP32 certainty for one crossing,
-                // FP64 level walk otherwise, FP64 replica if undecided
-                int n = 0;
-                bool up = false;
-                bool f64 = false;
-                bool slow = false;
-                if (cand) {
-                    up = I > q.Ahi;
-                    const bool one = up ? (I >= q.Bhi && I <= q.Chi)
-                                        : (I <= q.Blo && I >= q.Clo);
-                    if (force64)
-                        f64 = true;
-                    else if (one)
-                        n = 1;
-                    else
-                        slow = true;
-                }
-                if (__ballot(slow)) {
-                    if (slow) {
-                        // walk the levels in FP64 with a tiny guard
-                        const double s = LOGIN ? (double)I : (double)I + eps;
-                        double X = up ? q.Xh : q.Xl;
-                        const double E = up ? q.Ep : q.En;
-                        for (;;) {
-                            const double lo = lvl_below<LOGIN>(X, kG64, 0.0);
-                            const double hi = lvl_above<LOGIN>(X, kG64, 0.0);
-                            const bool crossed = up ? (s >= hi) : (s <= lo);
-                            const bool short_ = up ? (s < lo) : (s > hi);
-                            if (crossed) {
-                                ++n;
-                                if (n >= kFastMaxCross) {
-                                    f64 = true;
-                                    break;
-                                }
-                                X = lvl_step<LOGIN>(X, E);
-                                continue;
-                            }
-                            if (!short_) f64 = true;
-                            break;
-                        }
-                        if (f64) n = 0;
-                    }
-                }
-                double L0d = 0.0, L1d = 0.0;
-                bool have_d = false;
-                if (__ballot(f64)) {
-                    ++dg[4];
-                    if (f64) {
-                        const LogPair lp = log_pair64<LOGIN>(q.prev, I, eps);
-                        L0d = lp.L0;
-                        L1d = lp.L1;
-                        have_d = true;
-                        ++f64count;
-                        ++dg[0];
-                        const Count64 c =
-                            count64(q.L_init, q.nup, q.ndn, q.cp, q.cn, L1d);
-                        n = c.n;
-                        up = c.up != 0;
-                    }
-                }
-                // ---- (frame, pixel, k) slots within the wave
+                int n;
+                bool up, f64;
+                count_frame<LOGIN>(q, I, cand, force64, eps, n, up, f64, dg);
                 const int incl = wave_incl_scan(n);
                 const int total = wave_last(incl);
-                const int excl = incl - n;
                 if (total > 0) {
-                    ++dg[7];
-                    // interpolation fraction of crossing j: N_j / D with
-                    // N_j = ln(X_j / x0), D = ln(x1 / x0) (log input: plain
-                    // differences), N_j = N_1 + j * step
-                    float D = 1.f, invD = 1.f, relD = 0.f;
-                    float N1 = 0.f, relN1 = 0.f, absN = 0.f, cstep = 0.f;
-                    if (n > 0 && !f64) {
-                        const double X1 = up ? q.Xh : q.Xl;
-                        cstep = up ? q.cp : -q.cn;
-                        if (LOGIN) {
-                            D = (float)((double)I - (double)q.prev);
-                            relD = 0x1p-24f;
-                            N1 = (float)(X1 - (double)q.prev);
-                            relN1 = 0x1p-24f;
-                            absN = (float)(0x1p-36 * (1.0 + fabs(X1)));
-                        } else {
-                            const LnRatio d =
-                                ln_ratio(I - q.prev, (I + q.prev) + 2.0f * eps_f,
-                                         I + eps_f, q.prev + eps_f);
-                            D = d.v;
-                            relD = d.rel;
-                            const double x0d = (double)q.prev + eps;
-                            const LnRatio nn = ln_ratio(
-                                (float)(X1 - x0d), (float)(X1 + x0d), (float)X1,
-                                q.prev + eps_f);
-                            N1 = nn.v;
-                            relN1 = nn.rel;
-                            absN = 0x1p-35f;
-                        }
-                        invD = fast_rcp(D);
-                    }
-                    const float dtf = (float)dt;
-                    // |error of tau_j| <= alpha + beta * phi_j (safety 1.25)
-                    const float alpha =
-                        1.25f * dtf * (relN1 * fabsf(N1) + absN) * fabsf(invD) +
-                        a.eT;
-                    const float beta = 1.25f * dtf * (relD + 0x1p-21f + 0x1p-23f);
-                    const int tl0 = q.tlast;
-                    int win_lo = 0;
-                    int win_cap;  // writable entries in this window
-                    bool write;
-                    if (!RERUN) {
-                        write = !over && (cursor + total <= S);
-                        if (!write) over = true;
-                        win_cap = total;
-                    } else {
-                        if (cursor + total > S) {
-                            gpos = flush_wave(buf, cursor, pix0, key_hi,
-                                              a.out_key, a.out_val, gpos,
-                                              a.out_cap);
-                            cursor = 0;
-                        }
-                        write = true;
-                        win_cap = total < S ? total : S;
-                    }
-                    for (;;) {
-                        q.tlast = tl0;
-                        int em = 0;
-                        for (int j = 0; __ballot(j < n); ++j) {
-                            ++dg[5];
-                            int tt = 0;
-                            bool need = false;
-                            if (j < n) {
-                                need = f64;
-                                if (!need) {
-                                    const float Nj = fmaf((float)j, cstep, N1);
-                                    const float phi = Nj * invD;
-                                    const float tau = dtf * phi;
-                                    const float et = fmaf(beta, phi, alpha);
-                                    const float c1 = ceilf(tau - et);
-                                    const float c2 = ceilf(tau + et);
-                                    if (c1 == c2 && et < 0.25f)
-                                        tt = tp + (int)c2;
-                                    else
-                                        need = true;
-                                }
-                            }
-                            if (__ballot(need)) {
-                                ++dg[6];
-                                if (need) {
-                                    ++dg[1];
-                                    if (!have_d) {
-                                        const LogPair lp =
-                                            log_pair64<LOGIN>(q.prev, I, eps);
-                                        L0d = lp.L0;
-                                        L1d = lp.L1;
-                                        have_d = true;
-                                    }
-                                    ++f64count;
-                                    tt = time64(q.L_init, q.nup, q.ndn, q.cp,
-                                                q.cn, up ? 1 : 0, j, L0d, L1d,
-                                                a.T0, tp, dt);
-                                }
-                            }
-                            if (j < n) {
-                                const bool emit = (tt - q.tlast) >= tref;
-                                if (emit) q.tlast = tt;
-                                em += emit ? 1 : 0;
-                                const int idx = excl + j - win_lo;
-                                if (write && idx >= 0 && idx < win_cap) {
-                                    buf[cursor + idx] =
-                                        emit ? (((uint32_t)tt << 7) | lane_bits |
-                                                (up ? 1u : 0u))
-                                             : kEntryHole;
-                                }
-                            }
-                        }
-                        if (!RERUN) {
-                            emitted += em;
-                            if (write) cursor += total;
-                            break;
-                        } else {
-                            const int used = (total - win_lo) < win_cap
-                                                 ? (total - win_lo)
-                                                 : win_cap;
-                            cursor += used;
-                            win_lo += win_cap;
-                            if (win_lo >= total) break;
-                            gpos = flush_wave(buf, cursor, pix0, key_hi,
-                                              a.out_key, a.out_val, gpos,
-                                              a.out_cap);
-                            cursor = 0;
-                        }
-                    }
-                }
-                // ---- move the reference by the n crossings
-                if (n > 0) {
-                    if (up)
-                        q.nup += n;
+                    uint32_t slot = kNoSlot;
+                    if (!over && slots + total <= cap)
+                        slot = (uint32_t)(slots + incl - n);
                     else
-                        q.ndn += n;
-                    if (f64) {
-                        exact_levels<LOGIN>(q, eps);
-                    } else {
-                        const double E = up ? q.Ep : q.En;
-                        q.Xh = lvl_step<LOGIN>(q.Xh, E);
-                        q.Xl = lvl_step<LOGIN>(q.Xl, E);
-                        for (int i = 1; i < n; ++i) {
-                            q.Xh = lvl_step<LOGIN>(q.Xh, E);
-                            q.Xl = lvl_step<LOGIN>(q.Xl, E);
+                        over = true;
+                    slots += total;
+                    if (n > 0) {
+                        Rec rc;
+                        rc.slot = slot;
+                        rc.meta = (uint32_t)n | ((uint32_t)k << 21) |
+                                  (up ? (1u << 29) : 0u) | (f64 ? (1u << 30) : 0u);
+                        rc.I = I;
+                        rc.prev = q.prev;
+                        recs[rcount * kWave + lane] = rc;
+                        ++rcount;
+                        // move the reference by the n crossings
+                        if (up)
+                            q.nup += n;
+                        else
+                            q.ndn += n;
+                        if (f64) {
+                            exact_levels<LOGIN>(q, eps);
+                        } else {
+                            const double E = up ? q.Ep : q.En;
+                            for (int i = 0; i < n; ++i) {
+                                q.Xh = lvl_step<LOGIN>(q.Xh, E);
+                                q.Xl = lvl_step<LOGIN>(q.Xl, E);
+                            }
+                            refresh_thresholds<LOGIN>(q, eps);
                         }
-                        refresh_thresholds<LOGIN>(q, eps);
+                    }
+                    if (__ballot(rcount == kRecMax)) {
+                        drain_records<LOGIN>(a, q, b, recs, rcount, s_toff, out,
+                                             cap, emitted, f64count, dg);
+                        rcount = 0;
                     }
                 }
             }
             q.prev = I;
         }
     }
+    drain_records<LOGIN>(a, q, b, recs, rcount, s_toff, out, cap, emitted,
+                         f64count, dg);
 }
 
 #ifdef NSIM_TILE_TRACE
@@ -647,13 +692,16 @@ __device__ uint64_t g_tile_trace[1 << 17][8];
 #endif
 
 // One tile = one wave of 64 consecutive pixels of one environment, fully
-// independent of every other tile: the wave walks the launch's frames,
-// stages its events in LDS in (frame, pixel, k) order and writes them to the
-// tile's own staging segment (or one from the overflow pool).  The scan and
-// gather kernels restore pixel-block order afterwards.
+// independent of every other tile: the wave walks the launch's frames and
+// writes its staged entries to its own staging segment (wave * stage_entries,
+// or, when that overflows, a segment of the exact size from the pool behind
+// the fixed segments, filled by walking the frames again from the launch's
+// starting state).  The scan and gather kernels restore pixel-block order
+// afterwards.
 template <bool LOGIN, bool MAP>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
-                                          uint32_t* buf, float* fslab) {
+                                          Rec* recs, float* fslab,
+                                          const int* s_toff) {
     Header* hdr = a.hdr;
     const int lane = lane_id();
     TILE_STAMP(0);
@@ -661,23 +709,24 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
     const EnvRec er = a.envs[env];
     const int local = (wid - er.wave0) * kWave + lane;
     const int pix = wid * kWave + lane;
-    const uint32_t pix0 = (uint32_t)(wid * kWave);
     const bool valid = local < er.npix;
     const float* fr = a.frames + er.frame_off + local;
-    const uint32_t key_hi = (uint32_t)env << a.key_tbits;
 
     Px q;
     load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
                       MAP ? a.c_pos_map : nullptr, MAP ? a.c_neg_map : nullptr,
                       a.c_pos, a.c_neg, pix, valid, a.log_eps);
+    Bst b{q.Xh, q.Xl, q.nup, q.ndn, q.tlast};
 
     TILE_STAMP(1);
-    int cursor = 0, emitted = 0, f64count = 0;
+    int emitted = 0, f64count = 0;
+    int64_t slots = 0;
     bool over = false;
-    int64_t gdummy = 0;
     int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    walk_frames<LOGIN, false>(a, q, valid, fr, pix0, key_hi, buf, fslab,
-                              cursor, over, emitted, f64count, gdummy, dg);
+    const int64_t S = a.stage_entries;
+    walk_split<LOGIN>(a, q, b, valid, fr, recs, fslab, s_toff,
+                      a.out_key + (int64_t)wid * S, S, slots, over, emitted,
+                      f64count, dg);
     dg[2] = over ? 1 : 0;
     TILE_STAMP(2);
 
@@ -686,15 +735,15 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
         const int nxt = cur ^ 1;
         a.nud[nxt][pix] = make_int2(q.nup, q.ndn);
         a.prev[nxt][pix] = q.prev;
-        const int last = a.toff[a.K - 1];
+        const int last = s_toff[a.K - 1];
         int tl = kTlastNone;
-        if (q.tlast != kTlastNone && q.tlast - last >= -a.tref)
-            tl = q.tlast - last;
+        if (b.tlast != kTlastNone && b.tlast - last >= -a.tref)
+            tl = b.tlast - last;
         a.tlast[nxt][pix] = tl;
     }
 
     // (64-bit: pathological inputs may exceed 2^31 crossings per wave; the
-    // count saturates and the step then reports an overflow)
+    // counts saturate and the step then reports an overflow)
     const int64_t wemit = wave_sum64(emitted);
     const int wf64 = wave_sum(f64count);
 #ifdef NSIM_STEP_DIAG
@@ -710,42 +759,42 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
         }
     }
 #endif
-    // this wave's staging segment: its fixed one, or one from the pool
-    int64_t base = (int64_t)wid * a.stage_entries;
+    int64_t base = (int64_t)wid * S;
     if (over) {
-        uint64_t b = 0;
+        uint64_t bb = 0;
         if (lane == 0)
-            b = atomicAdd((unsigned long long*)&hdr->alloc,
-                          (unsigned long long)wemit);
-        base = (int64_t)a.nwaves * a.stage_entries + (int64_t)__shfl(b, 0, kWave);
+            bb = atomicAdd((unsigned long long*)&hdr->alloc,
+                           (unsigned long long)slots);
+        base = (int64_t)a.nwaves * S + (int64_t)__shfl(bb, 0, kWave);
     }
     if (lane == 0) {
         a.seg_base[wid] = base;
         a.seg_count[wid] = (uint32_t)(wemit < 0xFFFFFFFFll ? wemit : 0xFFFFFFFFll);
+        a.seg_slots[wid] = (uint32_t)(slots < 0xFFFFFFFFll ? slots : 0xFFFFFFFFll);
         if (wf64)
             atomicAdd((unsigned long long*)&hdr->fp64_evals,
                       (unsigned long long)wf64);
     }
     TILE_STAMP(3);
-    if (base + wemit > a.out_cap) return;  // the step overflows anyway
-    int64_t g = base;
-    if (!over) {
-        flush_wave(buf, cursor, pix0, key_hi, a.out_key, a.out_val, g,
-                   a.out_cap);
-    } else {
+    if (over) {
+        if (slots >= 0xFFFFFFFFll || base + slots > a.out_cap) {
+            // the pool is exhausted: the step cannot be committed
+            if (lane == 0) atomicOr(&hdr->stage_full, 1);
+            return;
+        }
         // regenerate this wave's events from the launch's starting state
+        // into the pool segment, which fits them exactly
         load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
                           MAP ? a.c_pos_map : nullptr,
                           MAP ? a.c_neg_map : nullptr, a.c_pos, a.c_neg, pix,
                           valid, a.log_eps);
-        cursor = 0;
-        over = false;
+        b = Bst{q.Xh, q.Xl, q.nup, q.ndn, q.tlast};
         int e2 = 0, f2 = 0;
+        int64_t s2 = 0;
+        bool o2 = false;
         int dg2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        walk_frames<LOGIN, true>(a, q, valid, fr, pix0, key_hi, buf, fslab,
-                                 cursor, over, e2, f2, g, dg2);
-        flush_wave(buf, cursor, pix0, key_hi, a.out_key, a.out_val, g,
-                   a.out_cap);
+        walk_split<LOGIN>(a, q, b, valid, fr, recs, fslab, s_toff,
+                          a.out_key + base, slots, s2, o2, e2, f2, dg2);
     }
     TILE_STAMP(4);
 #ifdef NSIM_TILE_TRACE
@@ -758,20 +807,29 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
 
 // The step launch: a grid-stride loop of waves over the tiles of the padded
 // pixel space of all environments, so the same kernel runs as one wave per
-// tile or as a persistent grid sized to the chip.  LDS per wave (dynamic):
-// stage_entries 4-byte entries, then the kChunk x 64 frame slab.
+// tile or as a persistent grid sized to the chip.  LDS: the launch's frame
+// times per workgroup (static); per wave (dynamic, kStepLdsPerWave bytes)
+// the record queue (kRecMax x 64 records of 16 B) and the kChunk x 64
+// frame slab.
+constexpr int kStepLdsPerWave = kRecMax * kWave * (int)sizeof(Rec) +
+                                kChunk * kWave * (int)sizeof(float);
+
 template <bool LOGIN, bool MAP>
 __global__ __launch_bounds__(kStepMaxThreads) void step_kernel(const StepArgs a) {
-    extern __shared__ uint32_t s_dyn[];
+    extern __shared__ char s_dyn[];
+    __shared__ int s_toff[kMaxFramesPerLaunch];
     const int wpb = blockDim.x / kWave;
     const int w = threadIdx.x / kWave;
     if (a.hdr->status != 0) return;
+    for (int i = threadIdx.x; i < a.K; i += blockDim.x) s_toff[i] = a.toff[i];
+    __syncthreads();
     const int cur = a.hdr->cur;
-    uint32_t* buf = s_dyn + w * (a.stage_entries + kChunk * kWave);
-    float* fslab = reinterpret_cast<float*>(buf + a.stage_entries);
+    Rec* recs = reinterpret_cast<Rec*>(s_dyn + w * kStepLdsPerWave);
+    float* slab = reinterpret_cast<float*>(s_dyn + w * kStepLdsPerWave +
+                                           kRecMax * kWave * sizeof(Rec));
     const int stride = gridDim.x * wpb;
     for (int wid = blockIdx.x * wpb + w; wid < a.nwaves; wid += stride)
-        step_tile<LOGIN, MAP>(a, wid, cur, buf, fslab);
+        step_tile<LOGIN, MAP>(a, wid, cur, recs, slab, s_toff);
 }
 
 // Exclusive scan of the per-wave counts in wave (= pixel) order, two
@@ -845,8 +903,8 @@ __device__ __forceinline__ bool step_fits(const Header* hdr, int64_t scap,
                                           int64_t qcap, int64_t* n_out) {
     const int64_t n = hdr->n_step;
     *n_out = n;
-    return hdr->status == 0 && hdr->internal_err == 0 && n <= scap &&
-           (hdr->tail - hdr->head) + n <= qcap;
+    return hdr->status == 0 && hdr->internal_err == 0 && hdr->stage_full == 0 &&
+           n <= scap && (hdr->tail - hdr->head) + n <= qcap;
 }
 
 // Copy every wave's segment to its pixel-order position and count the
@@ -867,19 +925,30 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherArgs a) {
     for (int i = threadIdx.x; i < kMaxPasses * kDigits; i += blockDim.x) s_h[i] = 0u;
     __syncthreads();
     const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
     const int64_t wstride = (int64_t)gridDim.x * (blockDim.x / kWave);
     for (int64_t wv = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
          wv < a.nwaves; wv += wstride) {
         const int64_t sb = a.seg_base[wv];
-        const uint32_t sc = a.seg_count[wv];
-        const int64_t dst = a.pref[wv];
-        for (uint32_t j = lane; j < sc; j += kWave) {
-            const uint32_t k = a.skey[sb + j];
-            a.dkey[dst + j] = k;
-            a.dval[dst + j] = a.sval[sb + j];
-            for (int p = 0; p < a.npass; ++p)
-                atomicAdd(&s_h[p * kDigits + ((k >> (kDigitBits * p)) & (kDigits - 1))],
-                          1u);
+        const uint32_t ns = a.seg_slots[wv];
+        int64_t dst = a.pref[wv];
+        const uint32_t key_hi = (uint32_t)a.wave_env[wv] << a.key_tbits;
+        const uint32_t pix0 = (uint32_t)(wv * kWave);
+        for (uint32_t j0 = 0; j0 < ns; j0 += kWave) {
+            const uint32_t j = j0 + lane;
+            const uint32_t e = j < ns ? a.skey[sb + j] : kEntryHole;
+            const bool v = e != kEntryHole;
+            const uint64_t m = __ballot(v);
+            if (v) {
+                const int64_t pos = dst + __popcll(m & lt);
+                const uint32_t k = key_hi | (e >> 7);
+                a.dkey[pos] = k;
+                a.dval[pos] = ((pix0 + ((e >> 1) & 63u)) << 1) | (e & 1u);
+                for (int p = 0; p < a.npass; ++p)
+                    atomicAdd(&s_h[p * kDigits + ((k >> (kDigitBits * p)) & (kDigits - 1))],
+                              1u);
+            }
+            dst += __popcll(m);
         }
     }
     __syncthreads();
@@ -1070,6 +1139,7 @@ __global__ void commit_kernel(const CommitArgs a) {
         s_n = n;
         h->n_step = 0;
         h->alloc = 0;
+        h->stage_full = 0;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kMaxPasses * kDigits; i += blockDim.x) a.hist[i] = 0u;
@@ -1093,6 +1163,7 @@ __global__ void reset_kernel(Header* h, uint32_t* hist) {
         h->dropped_t = 0;
         h->internal_err = 0;
         h->alloc = 0;
+        h->stage_full = 0;
     }
     for (int i = threadIdx.x; i < kMaxPasses * kDigits; i += blockDim.x) hist[i] = 0u;
 }
@@ -1150,15 +1221,14 @@ hipError_t launch_init(const InitArgs& a, hipStream_t s) {
 hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
                        int waves_per_block, int max_blocks, hipStream_t s) {
     if (waves_per_block < 1 || waves_per_block * kWave > kStepMaxThreads ||
-        a.stage_entries < kWave || a.stage_entries > kStepMaxLdsEntries ||
+        a.stage_entries < 1 || a.stage_entries > kStepMaxLdsEntries ||
         max_blocks < 0)
         return hipErrorInvalidValue;
     int blocks = (a.nwaves + waves_per_block - 1) / waves_per_block;
     if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
     const dim3 grid(blocks);
     const dim3 block(waves_per_block * kWave);
-    const size_t lds = (size_t)waves_per_block *
-                       (a.stage_entries + kChunk * kWave) * sizeof(uint32_t);
+    const size_t lds = (size_t)waves_per_block * kStepLdsPerWave;
     if (log_input) {
         if (has_map)
             hipLaunchKernelGGL((step_kernel<true, true>), grid, block, lds, s, a);

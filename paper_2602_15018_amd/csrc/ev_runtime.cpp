@@ -75,10 +75,10 @@ struct nsim_ev {
     float* cneg_map = nullptr;
     uint32_t* skey[2] = {nullptr, nullptr};   // dense, radix ping-pong
     uint32_t* sval[2] = {nullptr, nullptr};
-    uint32_t* stage_key = nullptr;            // per-wave segments
-    uint32_t* stage_val = nullptr;
+    uint32_t* stage_key = nullptr;            // per-wave segments (packed)
     int64_t* seg_base = nullptr;
     uint32_t* seg_count = nullptr;
+    uint32_t* seg_slots = nullptr;
     uint32_t* pref = nullptr;
     uint64_t* tile_sum = nullptr;
     int64_t stage_cap = 0;                    // fixed segments + pool
@@ -165,7 +165,7 @@ void free_all(nsim_ev* h) {
                     h->nud[1], h->prev[0], h->prev[1], h->tlast[0],
                     h->tlast[1], h->cpos_map, h->cneg_map, h->skey[0],
                     h->skey[1], h->sval[0], h->sval[1], h->q_t, h->q_x,
-                    h->q_y, h->q_p, h->stage_key, h->stage_val, h->seg_base,
+                    h->q_y, h->q_p, h->stage_key, h->seg_slots, h->seg_base,
                     h->seg_count, h->pref, h->tile_sum, h->hist,
                     h->pass_status, h->pass_ctr, h->env_off};
     for (void* p : ptrs)
@@ -289,10 +289,10 @@ void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
     const double amax = std::max(std::fabs((double)T0), std::fabs((double)tmax));
     a.eT = (float)std::max(0x1p-12, amax * 0x1p-51);
     a.out_key = h->stage_key;
-    a.out_val = h->stage_val;
     a.out_cap = h->stage_cap;
     a.seg_base = h->seg_base;
     a.seg_count = h->seg_count;
+    a.seg_slots = h->seg_slots;
     a.hdr = h->hdr;
     a.flags = h->flags;
     for (int32_t i = 0; i < kl; ++i) a.toff[i] = (int32_t)(t_us[i] - T0);
@@ -312,11 +312,13 @@ void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
     nsim::GatherArgs& ga = L.gather;
     ga.seg_base = h->seg_base;
     ga.seg_count = h->seg_count;
+    ga.seg_slots = h->seg_slots;
     ga.pref = h->pref;
     ga.nwaves = h->nwaves;
     ga.npass = L.npass;
     ga.skey = h->stage_key;
-    ga.sval = h->stage_val;
+    ga.wave_env = h->wave_env;
+    ga.key_tbits = tbits;
     ga.dkey = h->skey[0];
     ga.dval = h->sval[0];
     ga.hdr = h->hdr;
@@ -563,7 +565,7 @@ int autotune(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t kl,
     std::vector<int32_t> stages, wpbs;
     if (h->want_stage) stages.push_back(h->want_stage);
     else
-        for (int32_t st : {128, 512, 2000})
+        for (int32_t st : {128, 512, 2048})
             if (st <= h->stage_alloc) stages.push_back(st);
     if (h->want_wpb) wpbs.push_back(h->want_wpb);
     else wpbs = {1, 2, 4};
@@ -831,7 +833,7 @@ int create_core(nsim_ev* h, const std::vector<EnvDesc>& envs, double log_eps,
     chk(dmalloc(&h->q_p, h->qcap));
     h->stage_cap = (int64_t)h->nwaves * h->stage_alloc + h->scap;
     chk(dmalloc(&h->stage_key, h->stage_cap));
-    chk(dmalloc(&h->stage_val, h->stage_cap));
+    chk(dmalloc(&h->seg_slots, h->nwaves));
     chk(dmalloc(&h->seg_base, h->nwaves));
     chk(dmalloc(&h->seg_count, h->nwaves));
     chk(dmalloc(&h->pref, h->nwaves));
@@ -1106,7 +1108,7 @@ int nsim_ev_get_stats(nsim_ev_t* h, nsim_ev_stats* out) {
     if (rc) return rc;
     h->stats.events = h->hdr_host->events_total;
     h->stats.fp64_evaluations = h->hdr_host->fp64_evals - h->fp64_trial;
-    h->stats.packed_event_bytes = 8 * h->hdr_host->events_total;
+    h->stats.packed_event_bytes = 4 * h->hdr_host->events_total;
     for (int i = 0; i < 8; ++i) h->stats.diag[i] = h->hdr_host->diag[i];
     *out = h->stats;
     return NSIM_OK;
@@ -1157,8 +1159,8 @@ int nsim_evb_create(const nsim_evb_env* envs, int32_t n_env,
     int32_t stage_alloc = cfg->stage_entries;
     if (stage_alloc == 0) {
         stage_alloc = 128;
-        for (int32_t s : {512, 2000})
-            if (nwaves * s * 8 <= (int64_t(1) << 31)) stage_alloc = s;
+        for (int32_t s : {512, 2048})
+            if (nwaves * s * 4 <= (int64_t(1) << 31)) stage_alloc = s;
     }
 
     nsim_evb* b = new (std::nothrow) nsim_evb();

@@ -135,6 +135,59 @@ def upsampler_sequence(seed: int, crop=None, t0_frame: int = 0, n: int = 9,
     return render(p, t, device=device, crop=crop)
 
 
+def render_many(ps, t_us, crops, device="cpu"):
+    """Frames [S][T][h][w] of S scenes with the same element counts, each
+    through its own crop window (y0, x0, h, w) of equal size; the same
+    arithmetic as ``render``, vectorised over the scenes."""
+    import torch
+
+    S, T = len(ps), len(t_us)
+    h, w = crops[0][2], crops[0][3]
+    H, W = ps[0].height, ps[0].width
+    t_s = np.asarray(t_us, dtype=np.float64) * 1e-6
+
+    def col(vals):
+        return torch.as_tensor(np.asarray(vals, np.float64), dtype=torch.float32
+                               ).to(device).view(S, 1, 1, 1)
+
+    y0 = col([c[0] for c in crops])
+    x0 = col([c[1] for c in crops])
+    ys = torch.arange(h, dtype=torch.float32, device=device).view(1, 1, h, 1) + y0
+    xs = torch.arange(w, dtype=torch.float32, device=device).view(1, 1, 1, w) + x0
+    acc = torch.zeros((S, T, h, w), dtype=torch.float32, device=device)
+
+    def per_frame(vals):  # [S][T] float64 -> [S,T,1,1] float32
+        return torch.as_tensor(vals, dtype=torch.float32).to(device).view(S, T, 1, 1)
+
+    two_pi = 2.0 * math.pi
+    g = lambda name: np.stack([getattr(p, name) for p in ps])   # [S][n]
+    g_amp, g_freq, g_theta, g_phase = g("g_amp"), g("g_freq"), g("g_theta"), g("g_phase")
+    g_cx, g_cy, g_vx, g_vy, g_om = g("g_cx"), g("g_cy"), g("g_vx"), g("g_vy"), g("g_omega")
+    for i in range(g_amp.shape[1]):
+        cx = per_frame(np.mod(g_cx[:, i, None] + g_vx[:, i, None] * t_s[None], W))
+        cy = per_frame(np.mod(g_cy[:, i, None] + g_vy[:, i, None] * t_s[None], H))
+        th = g_theta[:, i, None] + g_om[:, i, None] * t_s[None]
+        c, sn = per_frame(np.cos(th)), per_frame(np.sin(th))
+        u = (xs - cx) * c + (ys - cy) * sn
+        acc += col(g_amp[:, i].astype(np.float32)) * torch.sin(
+            u * col((two_pi * g_freq[:, i] / W)) + col(g_phase[:, i]))
+    b_amp, b_sx, b_sy, b_theta = g("b_amp"), g("b_sx"), g("b_sy"), g("b_theta")
+    b_cx, b_cy, b_vx, b_vy, b_om = g("b_cx"), g("b_cy"), g("b_vx"), g("b_vy"), g("b_omega")
+    for j in range(b_amp.shape[1]):
+        cx = per_frame(np.mod(b_cx[:, j, None] + b_vx[:, j, None] * t_s[None], W))
+        cy = per_frame(np.mod(b_cy[:, j, None] + b_vy[:, j, None] * t_s[None], H))
+        th = b_theta[:, j, None] + b_om[:, j, None] * t_s[None]
+        c, sn = per_frame(np.cos(th)), per_frame(np.sin(th))
+        dx = torch.remainder(xs - cx + 0.5 * W, float(W)) - 0.5 * W
+        dy = torch.remainder(ys - cy + 0.5 * H, float(H)) - 0.5 * H
+        u = (dx * c + dy * sn) / col(b_sx[:, j])
+        v = (dy * c - dx * sn) / col(b_sy[:, j])
+        acc += col(b_amp[:, j]) * torch.exp(-0.5 * (u * u + v * v))
+    n = g_amp.shape[1] + b_amp.shape[1]
+    gain = ps[0].gain
+    return (0.5 + (gain / math.sqrt(max(n, 1))) * acc).clamp_(0.01, 1.0)
+
+
 def frame_times(w: Workload, first: int = 0, count: int | None = None):
     """Integer microsecond timestamps t_f = t0 + f * dt of frames
     first .. first + count - 1."""
