@@ -155,8 +155,10 @@ __device__ __forceinline__ LnRatio ln_ratio(float diff, float sum, float xa,
         // conditioned; each log2 carries at most 2^-21 (1 + |log2 x|).
         const float la = fast_log2(xa), lb = fast_log2(xb);
         r.v = (la - lb) * kLn2f;
-        r.rel = 0x1p-21f * (2.0f + fabsf(la) + fabsf(lb)) * kLn2f /
-                    fabsf(r.v) +
+        // (v_rcp_f32 is within 1 ulp; the 1.25 safety factor of the
+        // timestamp bound covers that and the rounding of this bound)
+        r.rel = 0x1p-21f * (2.0f + fabsf(la) + fabsf(lb)) * kLn2f *
+                    fast_rcp(fabsf(r.v)) +
                 0x1p-22f;
     }
     return r;
@@ -257,6 +259,11 @@ __device__ __forceinline__ void load_pixel(Px& q, const double* L_init,
     q.Ep2 = q.Ep * (1.0 - kG32);
     q.En2 = q.En * (1.0 + kG32);
     exact_levels<LOGIN>(q, eps);
+    if (!valid) {
+        // padding lanes never become candidates
+        q.Ahi = __builtin_inff();
+        q.Alo = -__builtin_inff();
+    }
 }
 
 // ---- rare paths, kept out of line so the frame loop stays small.  They
@@ -346,13 +353,14 @@ __device__ __forceinline__ void exact_levels(Px& q, double eps) {
 //
 // Phase A walks the frames in lockstep: the per-frame test against the
 // FP32 thresholds, the crossing count of candidate lanes, the staging slots
-// of the frame's crossings ((frame, pixel, k) order: a wave scan of the
-// counts) and the move of the levels.  Each frame with crossings leaves a
-// record in the lane's LDS queue.  Phase B drains the queues in rounds,
-// round r taking every lane's r-th record: timestamps, the refractory
-// filter and the staged entry (or hole) of each crossing.  Only lanes with
-// records work in a round, instead of every lane on every frame that has a
-// crossing somewhere in the wave.
+// of the frame's crossings ((frame, pixel, k) order), and the move of the
+// levels.  Each frame with crossings leaves a record in the lane's LDS
+// queue with everything its timestamps need.  Phase B drains the queues:
+// first the timestamps of the records with a single crossing, in compacted
+// rounds of 64 records whatever lanes they belong to; then, per lane and in
+// record order, the refractory filter and the staged entry (or hole) of
+// each crossing, with the full evaluation for the rare records that have
+// several crossings, need FP64, or whose bound did not decide.
 //
 // Staged entry: (time offset << 7) | (lane << 1) | (p > 0), written straight
 // to the wave's staging segment in global memory; a suppressed crossing
@@ -360,22 +368,24 @@ __device__ __forceinline__ void exact_levels(Px& q, double eps) {
 
 constexpr int kRecMax = 4;                 // records per lane between drains
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // crossings past the segment
+constexpr uint32_t kRecF64 = 1u << 30;     // meta: count decided in FP64
+constexpr uint32_t kRecReady = 1u << 31;   // meta: timestamp in `tt`
 
+// Six 32-bit words: slot, meta, then either the raw inputs (the frame's
+// sample I, the previous sample, the first crossed level X1 as FP64 in the
+// sample domain) or, once ready, the FP32 interpolation (N1, 1/D, alpha,
+// beta) that the bound decides for every crossing of the record.
 struct Rec {
     uint32_t slot;   // staging slot of the frame's first crossing
     uint32_t meta;   // n (bits 0..20) | frame (21..28) | up (29) | f64 (30)
-    float I;         // the frame's sample
-    float prev;      // the previous frame's sample
+                     // | interpolation ready (31)
+    uint32_t w0, w1, w2, w3;
 };
-
-// Phase B's copy of the lattice state: the levels and counts replayed
-// record by record (the same operations as phase A, so the same values),
-// and the refractory time.
-struct Bst {
-    double Xh, Xl;
-    int nup, ndn;
-    int tlast;
-};
+__device__ __forceinline__ float rec_I(const Rec& r) { return __uint_as_float(r.w0); }
+__device__ __forceinline__ float rec_prev(const Rec& r) { return __uint_as_float(r.w1); }
+__device__ __forceinline__ double rec_X1(const Rec& r) {
+    return __hiloint2double((int)r.w3, (int)r.w2);
+}
 
 __device__ __forceinline__ int wave_max_small(int v) {
     int m = 0;
@@ -391,31 +401,24 @@ template <bool LOGIN>
 __device__ __forceinline__ void count_frame(const Px& q, float I, bool cand,
                                             bool force64, double eps, int& n,
                                             bool& up, bool& f64, int* dg) {
-    n = 0;
-    up = false;
-    f64 = false;
-    bool slow = false;
-    if (cand) {
-        up = I > q.Ahi;
-        const bool one = up ? (I >= q.Bhi && I <= q.Chi)
-                            : (I <= q.Blo && I >= q.Clo);
-        if (force64)
-            f64 = true;
-        else if (one)
-            n = 1;
-        else
-            slow = true;
-    }
+    // one crossing for sure: up: Bhi <= I <= Chi, down: Clo <= I <= Blo
+    up = I > q.Ahi;
+    const float lo = up ? q.Bhi : q.Clo;
+    const float hi = up ? q.Chi : q.Blo;
+    const bool one = cand & (I >= lo) & (I <= hi) & !force64;
+    n = one ? 1 : 0;
+    f64 = cand & force64;
+    bool slow = cand & !one & !force64;
     if (__ballot(slow)) {
         if (slow) {
             const double s = LOGIN ? (double)I : (double)I + eps;
             double X = up ? q.Xh : q.Xl;
             const double E = up ? q.Ep : q.En;
             for (;;) {
-                const double lo = lvl_below<LOGIN>(X, kG64, 0.0);
-                const double hi = lvl_above<LOGIN>(X, kG64, 0.0);
-                const bool crossed = up ? (s >= hi) : (s <= lo);
-                const bool short_ = up ? (s < lo) : (s > hi);
+                const double lo64 = lvl_below<LOGIN>(X, kG64, 0.0);
+                const double hi64 = lvl_above<LOGIN>(X, kG64, 0.0);
+                const bool crossed = up ? (s >= hi64) : (s <= lo64);
+                const bool short_ = up ? (s < lo64) : (s > hi64);
                 if (crossed) {
                     ++n;
                     if (n >= kFastMaxCross) {
@@ -443,134 +446,222 @@ __device__ __forceinline__ void count_frame(const Px& q, float I, bool cand,
     }
 }
 
-// Phase B: timestamps, refractory filter and staged entries of the queued
-// records, in rounds over the lanes' queues.
+// Interpolation of a record's crossings: crossing j has fraction N_j / D
+// with D = ln(x1 / x0), N_j = ln(X_j / x0) = N_1 + j * step (log input:
+// plain differences), and |error of tau_j| <= alpha + beta * phi_j.
+struct TsSetup {
+    float N1, invD, cstep, alpha, beta, dtf;
+    int tp, dt;
+};
+
+// `cstep` is the threshold of the record's own pixel in the crossing's
+// direction (+C_pos or -C_neg).
 template <bool LOGIN>
-__device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
-                                              Bst& b, const Rec* recs,
-                                              int rcount, const int* s_toff,
-                                              uint32_t* out, int64_t cap,
-                                              int& emitted, int& f64count,
-                                              int* dg) {
-    const int lane = lane_id();
-    const uint32_t lane_bits = ((uint32_t)lane) << 1;
+__device__ __forceinline__ TsSetup ts_setup(const StepArgs& a, const Rec& rc,
+                                            float cstep, const int* s_toff) {
+    TsSetup s;
+    const int k = (int)((rc.meta >> 21) & 0xFFu);
+    s.tp = k > 0 ? s_toff[k - 1] : 0;
+    s.dt = s_toff[k] - s.tp;
     const float eps_f = a.log_eps_f;
     const double eps = a.log_eps;
+    const float I = rec_I(rc), prev = rec_prev(rc);
+    const double X1 = rec_X1(rc);
+    float D, relD, relN1, absN;
+    s.cstep = cstep;
+    if (LOGIN) {
+        D = (float)((double)I - (double)prev);
+        relD = 0x1p-24f;
+        s.N1 = (float)(X1 - (double)prev);
+        relN1 = 0x1p-24f;
+        absN = (float)(0x1p-36 * (1.0 + fabs(X1)));
+    } else {
+        const LnRatio d = ln_ratio(I - prev, (I + prev) + 2.0f * eps_f,
+                                   I + eps_f, prev + eps_f);
+        D = d.v;
+        relD = d.rel;
+        const double x0d = (double)prev + eps;
+        const LnRatio nn = ln_ratio((float)(X1 - x0d), (float)(X1 + x0d),
+                                    (float)X1, prev + eps_f);
+        s.N1 = nn.v;
+        relN1 = nn.rel;
+        absN = 0x1p-35f;
+    }
+    s.invD = fast_rcp(D);
+    s.dtf = (float)s.dt;
+    // (safety factor 1.25)
+    s.alpha = 1.25f * s.dtf * (relN1 * fabsf(s.N1) + absN) * fabsf(s.invD) + a.eT;
+    s.beta = 1.25f * s.dtf * (relD + 0x1p-21f + 0x1p-23f);
+    return s;
+}
+
+// Timestamp of crossing j from FP32 when the bound decides it.
+__device__ __forceinline__ bool ts_fast(const TsSetup& s, int j, int& tt) {
+    const float Nj = fmaf((float)j, s.cstep, s.N1);
+    const float phi = Nj * s.invD;
+    const float tau = s.dtf * phi;
+    const float et = fmaf(s.beta, phi, s.alpha);
+    const float c1 = ceilf(tau - et);
+    const float c2 = ceilf(tau + et);
+    tt = s.tp + (int)c2;
+    return c1 == c2 && et < 0.25f;
+}
+
+// Phase B.  `tlast` is the lane's refractory time; `idx` is the wave's
+// compaction list (kRecMax * 64 bytes); (nup0, ndn0) are the lattice
+// counters before the lane's first queued record.
+template <bool LOGIN>
+__device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
+                                              int& tlast, Rec* recs,
+                                              uint8_t* idx, int rcount,
+                                              uint32_t simple_mask, int nup0,
+                                              int ndn0,
+                                              const int* s_toff, uint32_t* out,
+                                              int64_t cap, int& emitted,
+                                              int& f64count, int* dg) {
+    const int lane = lane_id();
+    const uint32_t lane_bits = ((uint32_t)lane) << 1;
+    const double eps = a.log_eps;
     const int tref = a.tref;
+
+    // 1. FP32 interpolation of the records counted in FP32, compacted over
+    //    the wave; kept when the bound decides every crossing
+    const int ns = __popc(simple_mask);
+    const int incl = wave_incl_scan(ns);
+    const int total = wave_last(incl);
+    {
+        int pos = incl - ns;
+        for (int r = 0; r < kRecMax; ++r)
+            if ((simple_mask >> r) & 1u) idx[pos++] = (uint8_t)(r * kWave + lane);
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int c0 = 0; c0 < total; c0 += kWave) {
+        ++dg[7];
+        const int i = c0 + lane;
+        const bool act = i < total;
+        const int e = act ? (int)idx[i] : lane;
+        // the record belongs to lane e % 64: its pixel's thresholds
+        const int owner = e & (kWave - 1);
+        const float cp_o = __shfl(q.cp, owner, kWave);
+        const float cn_o = __shfl(q.cn, owner, kWave);
+        if (act) {
+            Rec rc = recs[e];
+            const bool up = ((rc.meta >> 29) & 1u) != 0;
+            const int n = (int)(rc.meta & 0x1FFFFFu);
+            const TsSetup s = ts_setup<LOGIN>(a, rc, up ? cp_o : -cn_o, s_toff);
+            bool ok = true;
+            for (int j = 0; j < n; ++j) {
+                int tt;
+                ok = ok && ts_fast(s, j, tt);
+            }
+            if (ok) {
+                Rec w;
+                w.slot = rc.slot;
+                w.meta = rc.meta | kRecReady;
+                w.w0 = __float_as_uint(s.N1);
+                w.w1 = __float_as_uint(s.invD);
+                w.w2 = __float_as_uint(s.alpha);
+                w.w3 = __float_as_uint(s.beta);
+                recs[e] = w;
+            }
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // 2. per lane, in record order: refractory filter and staged entries
     const int rmax = wave_max_small(rcount);
+    int cu = nup0, cd = ndn0;
     for (int r = 0; r < rmax; ++r) {
         const bool act = r < rcount;
-        Rec rc;
-        rc.slot = kNoSlot;
-        rc.meta = 0;
-        rc.I = 1.0f;
-        rc.prev = 1.0f;
+        Rec rc{kNoSlot, 0u, 0u, 0u, 0u, 0u};
         if (act) rc = recs[r * kWave + lane];
-        const int n = (int)(rc.meta & 0x1FFFFFu);
-        const int k = (int)((rc.meta >> 21) & 0xFFu);
+        const bool ready = (rc.meta & kRecReady) != 0;
         const bool up = ((rc.meta >> 29) & 1u) != 0;
-        const bool f64 = ((rc.meta >> 30) & 1u) != 0;
-        const float I = rc.I, prev = rc.prev;
-        const int tp = k > 0 ? s_toff[k - 1] : 0;
-        const int dt = s_toff[k] - tp;
-        ++dg[7];
-        // interpolation fraction of crossing j: N_j / D with N_j =
-        // ln(X_j / x0), D = ln(x1 / x0) (log input: plain differences),
-        // N_j = N_1 + j * step
-        float D = 1.f, invD = 1.f, relD = 0.f;
-        float N1 = 0.f, relN1 = 0.f, absN = 0.f, cstep = 0.f;
-        if (n > 0 && !f64) {
-            const double X1 = up ? b.Xh : b.Xl;
-            cstep = up ? q.cp : -q.cn;
-            if (LOGIN) {
-                D = (float)((double)I - (double)prev);
-                relD = 0x1p-24f;
-                N1 = (float)(X1 - (double)prev);
-                relN1 = 0x1p-24f;
-                absN = (float)(0x1p-36 * (1.0 + fabs(X1)));
-            } else {
-                const LnRatio d = ln_ratio(I - prev, (I + prev) + 2.0f * eps_f,
-                                           I + eps_f, prev + eps_f);
-                D = d.v;
-                relD = d.rel;
-                const double x0d = (double)prev + eps;
-                const LnRatio nn = ln_ratio((float)(X1 - x0d), (float)(X1 + x0d),
-                                            (float)X1, prev + eps_f);
-                N1 = nn.v;
-                relN1 = nn.rel;
-                absN = 0x1p-35f;
+        const int nrec = (int)(rc.meta & 0x1FFFFFu);
+        const int cu_r = cu, cd_r = cd;
+        if (up)
+            cu += nrec;
+        else
+            cd += nrec;
+        if (__ballot(ready)) {
+            TsSetup s{};
+            int n = 0;
+            if (ready) {
+                n = nrec;
+                const int k = (int)((rc.meta >> 21) & 0xFFu);
+                s.tp = k > 0 ? s_toff[k - 1] : 0;
+                s.dt = s_toff[k] - s.tp;
+                s.dtf = (float)s.dt;
+                s.cstep = up ? q.cp : -q.cn;
+                s.N1 = __uint_as_float(rc.w0);
+                s.invD = __uint_as_float(rc.w1);
+                s.alpha = __uint_as_float(rc.w2);
+                s.beta = __uint_as_float(rc.w3);
             }
-            invD = fast_rcp(D);
-        }
-        const float dtf = (float)dt;
-        // |error of tau_j| <= alpha + beta * phi_j (safety 1.25)
-        const float alpha =
-            1.25f * dtf * (relN1 * fabsf(N1) + absN) * fabsf(invD) + a.eT;
-        const float beta = 1.25f * dtf * (relD + 0x1p-21f + 0x1p-23f);
-        double L0d = 0.0, L1d = 0.0;
-        bool have_d = false;
-        for (int j = 0; __ballot(j < n); ++j) {
-            ++dg[5];
-            int tt = 0;
-            bool need = false;
-            if (j < n) {
-                need = f64;
-                if (!need) {
-                    const float Nj = fmaf((float)j, cstep, N1);
-                    const float phi = Nj * invD;
-                    const float tau = dtf * phi;
-                    const float et = fmaf(beta, phi, alpha);
-                    const float c1 = ceilf(tau - et);
-                    const float c2 = ceilf(tau + et);
-                    if (c1 == c2 && et < 0.25f)
-                        tt = tp + (int)c2;
-                    else
-                        need = true;
-                }
-            }
-            if (__ballot(need)) {
-                ++dg[6];
-                if (need) {
-                    ++dg[1];
-                    if (!have_d) {
-                        const LogPair lp = log_pair64<LOGIN>(prev, I, eps);
-                        L0d = lp.L0;
-                        L1d = lp.L1;
-                        have_d = true;
-                    }
-                    ++f64count;
-                    tt = time64(q.L_init, b.nup, b.ndn, q.cp, q.cn, up ? 1 : 0, j,
-                                L0d, L1d, a.T0, tp, dt);
-                }
-            }
-            if (j < n) {
-                const bool emit = (tt - b.tlast) >= tref;
-                if (emit) b.tlast = tt;
+            for (int j = 0; j < n; ++j) {
+                int tt;
+                ts_fast(s, j, tt);
+                const bool emit = (tt - tlast) >= tref;
+                if (emit) tlast = tt;
                 emitted += emit ? 1 : 0;
                 if (rc.slot != kNoSlot) {
-                    const int64_t s = (int64_t)rc.slot + j;
-                    if (s < cap)
-                        out[s] = emit ? (((uint32_t)tt << 7) | lane_bits |
-                                         (up ? 1u : 0u))
-                                      : kEntryHole;
+                    const int64_t sl = (int64_t)rc.slot + j;
+                    if (sl < cap)
+                        out[sl] = emit ? (((uint32_t)tt << 7) | lane_bits |
+                                          (up ? 1u : 0u))
+                                       : kEntryHole;
                 }
             }
         }
-        // replay the record's move of the levels
-        if (n > 0) {
-            if (up)
-                b.nup += n;
-            else
-                b.ndn += n;
-            if (f64) {
-                const Levels l = levels64<LOGIN>(q.L_init, b.nup, b.ndn, q.cp, q.cn);
-                b.Xh = l.Xh;
-                b.Xl = l.Xl;
-            } else {
-                const double E = up ? q.Ep : q.En;
-                for (int i = 0; i < n; ++i) {
-                    b.Xh = lvl_step<LOGIN>(b.Xh, E);
-                    b.Xl = lvl_step<LOGIN>(b.Xl, E);
+        const bool full = act && !ready;
+        if (__ballot(full)) {
+            ++dg[6];
+            int n = 0;
+            bool f64 = false;
+            TsSetup s{};
+            if (full) {
+                n = (int)(rc.meta & 0x1FFFFFu);
+                f64 = (rc.meta & kRecF64) != 0;
+                if (!f64) s = ts_setup<LOGIN>(a, rc, up ? q.cp : -q.cn, s_toff);
+                else {
+                    const int k = (int)((rc.meta >> 21) & 0xFFu);
+                    s.tp = k > 0 ? s_toff[k - 1] : 0;
+                    s.dt = s_toff[k] - s.tp;
+                }
+            }
+            double L0d = 0.0, L1d = 0.0;
+            bool have_d = false;
+            for (int j = 0; __ballot(j < n); ++j) {
+                ++dg[5];
+                int tt = 0;
+                bool need = false;
+                if (j < n) need = f64 || !ts_fast(s, j, tt);
+                if (__ballot(need)) {
+                    if (need) {
+                        ++dg[1];
+                        if (!have_d) {
+                            const LogPair lp =
+                                log_pair64<LOGIN>(rec_prev(rc), rec_I(rc), eps);
+                            L0d = lp.L0;
+                            L1d = lp.L1;
+                            have_d = true;
+                        }
+                        ++f64count;
+                        tt = time64(q.L_init, cu_r, cd_r, q.cp, q.cn,
+                                    up ? 1 : 0, j, L0d, L1d, a.T0, s.tp, s.dt);
+                    }
+                }
+                if (j < n) {
+                    const bool emit = (tt - tlast) >= tref;
+                    if (emit) tlast = tt;
+                    emitted += emit ? 1 : 0;
+                    if (rc.slot != kNoSlot) {
+                        const int64_t sl = (int64_t)rc.slot + j;
+                        if (sl < cap)
+                            out[sl] = emit ? (((uint32_t)tt << 7) | lane_bits |
+                                              (up ? 1u : 0u))
+                                           : kEntryHole;
+                    }
                 }
             }
         }
@@ -583,9 +674,9 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
 // segment is marked overflowed and later crossings are only counted.
 // `slots` returns the slots the launch needs (holes included).
 template <bool LOGIN>
-__device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, Bst& b,
+__device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
                                            bool valid, const float* fr,
-                                           Rec* recs, float* fslab,
+                                           Rec* recs, uint8_t* idx, float* fslab,
                                            const int* s_toff, uint32_t* out,
                                            int64_t cap, int64_t& slots,
                                            bool& over, int& emitted,
@@ -596,6 +687,8 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, Bst& b,
     const int K = a.K;
     const int lane = lane_id();
     int rcount = 0;
+    uint32_t simple_mask = 0;
+    int nup0 = q.nup, ndn0 = q.ndn;
 
     // Frames are prefetched a chunk of kChunk frames ahead into registers;
     // at the start of each chunk the registers (loaded one chunk earlier)
@@ -623,29 +716,47 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, Bst& b,
         for (int u = 0; u < cnt; ++u) {
             const int k = kc + u;
             const float I = fslab[u * kWave + lane];
-            const bool cand = valid && ((I > q.Ahi) || (I < q.Alo));
+            const bool cand = (I > q.Ahi) | (I < q.Alo);
             if (__ballot(cand)) {
                 ++dg[3];
                 int n;
                 bool up, f64;
                 count_frame<LOGIN>(q, I, cand, force64, eps, n, up, f64, dg);
-                const int incl = wave_incl_scan(n);
-                const int total = wave_last(incl);
+                // staging slots in (frame, pixel, k) order: a popcount when
+                // every count is 0 or 1, a wave scan otherwise
+                int excl, total;
+                if (__ballot(n > 1) == 0) {
+                    const uint64_t m = __ballot(n > 0);
+                    excl = __popcll(m & lanemask_lt());
+                    total = __popcll(m);
+                } else {
+                    const int incl = wave_incl_scan(n);
+                    total = wave_last(incl);
+                    excl = incl - n;
+                }
                 if (total > 0) {
                     uint32_t slot = kNoSlot;
                     if (!over && slots + total <= cap)
-                        slot = (uint32_t)(slots + incl - n);
+                        slot = (uint32_t)(slots + excl);
                     else
                         over = true;
                     slots += total;
                     if (n > 0) {
+                        if (rcount == 0) {
+                            nup0 = q.nup;
+                            ndn0 = q.ndn;
+                        }
                         Rec rc;
                         rc.slot = slot;
                         rc.meta = (uint32_t)n | ((uint32_t)k << 21) |
-                                  (up ? (1u << 29) : 0u) | (f64 ? (1u << 30) : 0u);
-                        rc.I = I;
-                        rc.prev = q.prev;
+                                  (up ? (1u << 29) : 0u) | (f64 ? kRecF64 : 0u);
+                        const double X1 = up ? q.Xh : q.Xl;
+                        rc.w0 = __float_as_uint(I);
+                        rc.w1 = __float_as_uint(q.prev);
+                        rc.w2 = (uint32_t)__double2loint(X1);
+                        rc.w3 = (uint32_t)__double2hiint(X1);
                         recs[rcount * kWave + lane] = rc;
+                        if (!f64) simple_mask |= 1u << rcount;
                         ++rcount;
                         // move the reference by the n crossings
                         if (up)
@@ -656,7 +767,9 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, Bst& b,
                             exact_levels<LOGIN>(q, eps);
                         } else {
                             const double E = up ? q.Ep : q.En;
-                            for (int i = 0; i < n; ++i) {
+                            q.Xh = lvl_step<LOGIN>(q.Xh, E);
+                            q.Xl = lvl_step<LOGIN>(q.Xl, E);
+                            for (int i = 1; i < n; ++i) {
                                 q.Xh = lvl_step<LOGIN>(q.Xh, E);
                                 q.Xl = lvl_step<LOGIN>(q.Xl, E);
                             }
@@ -664,17 +777,19 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, Bst& b,
                         }
                     }
                     if (__ballot(rcount == kRecMax)) {
-                        drain_records<LOGIN>(a, q, b, recs, rcount, s_toff, out,
-                                             cap, emitted, f64count, dg);
+                        drain_records<LOGIN>(a, q, tlast, recs, idx, rcount,
+                                             simple_mask, nup0, ndn0, s_toff,
+                                             out, cap, emitted, f64count, dg);
                         rcount = 0;
+                        simple_mask = 0;
                     }
                 }
             }
             q.prev = I;
         }
     }
-    drain_records<LOGIN>(a, q, b, recs, rcount, s_toff, out, cap, emitted,
-                         f64count, dg);
+    drain_records<LOGIN>(a, q, tlast, recs, idx, rcount, simple_mask, nup0,
+                         ndn0, s_toff, out, cap, emitted, f64count, dg);
 }
 
 #ifdef NSIM_TILE_TRACE
@@ -700,7 +815,7 @@ __device__ uint64_t g_tile_trace[1 << 17][8];
 // afterwards.
 template <bool LOGIN, bool MAP>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
-                                          Rec* recs, float* fslab,
+                                          Rec* recs, uint8_t* idx, float* fslab,
                                           const int* s_toff) {
     Header* hdr = a.hdr;
     const int lane = lane_id();
@@ -716,7 +831,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
     load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
                       MAP ? a.c_pos_map : nullptr, MAP ? a.c_neg_map : nullptr,
                       a.c_pos, a.c_neg, pix, valid, a.log_eps);
-    Bst b{q.Xh, q.Xl, q.nup, q.ndn, q.tlast};
+    int tlast = q.tlast;
 
     TILE_STAMP(1);
     int emitted = 0, f64count = 0;
@@ -724,7 +839,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
     bool over = false;
     int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t S = a.stage_entries;
-    walk_split<LOGIN>(a, q, b, valid, fr, recs, fslab, s_toff,
+    walk_split<LOGIN>(a, q, tlast, valid, fr, recs, idx, fslab, s_toff,
                       a.out_key + (int64_t)wid * S, S, slots, over, emitted,
                       f64count, dg);
     dg[2] = over ? 1 : 0;
@@ -737,8 +852,8 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
         a.prev[nxt][pix] = q.prev;
         const int last = s_toff[a.K - 1];
         int tl = kTlastNone;
-        if (b.tlast != kTlastNone && b.tlast - last >= -a.tref)
-            tl = b.tlast - last;
+        if (tlast != kTlastNone && tlast - last >= -a.tref)
+            tl = tlast - last;
         a.tlast[nxt][pix] = tl;
     }
 
@@ -788,12 +903,12 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
                           MAP ? a.c_pos_map : nullptr,
                           MAP ? a.c_neg_map : nullptr, a.c_pos, a.c_neg, pix,
                           valid, a.log_eps);
-        b = Bst{q.Xh, q.Xl, q.nup, q.ndn, q.tlast};
+        tlast = q.tlast;
         int e2 = 0, f2 = 0;
         int64_t s2 = 0;
         bool o2 = false;
         int dg2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        walk_split<LOGIN>(a, q, b, valid, fr, recs, fslab, s_toff,
+        walk_split<LOGIN>(a, q, tlast, valid, fr, recs, idx, fslab, s_toff,
                           a.out_key + base, slots, s2, o2, e2, f2, dg2);
     }
     TILE_STAMP(4);
@@ -809,13 +924,15 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
 // pixel space of all environments, so the same kernel runs as one wave per
 // tile or as a persistent grid sized to the chip.  LDS: the launch's frame
 // times per workgroup (static); per wave (dynamic, kStepLdsPerWave bytes)
-// the record queue (kRecMax x 64 records of 16 B) and the kChunk x 64
-// frame slab.
+// the record queue (kRecMax x 64 records of 24 B), the kChunk x 64 frame
+// slab and the compaction list (kRecMax x 64 bytes).
 constexpr int kStepLdsPerWave = kRecMax * kWave * (int)sizeof(Rec) +
-                                kChunk * kWave * (int)sizeof(float);
+                                kChunk * kWave * (int)sizeof(float) +
+                                kRecMax * kWave;
 
 template <bool LOGIN, bool MAP>
-__global__ __launch_bounds__(kStepMaxThreads) void step_kernel(const StepArgs a) {
+__global__ __launch_bounds__(kStepMaxThreads)
+__attribute__((amdgpu_waves_per_eu(4))) void step_kernel(const StepArgs a) {
     extern __shared__ char s_dyn[];
     __shared__ int s_toff[kMaxFramesPerLaunch];
     const int wpb = blockDim.x / kWave;
@@ -824,12 +941,14 @@ __global__ __launch_bounds__(kStepMaxThreads) void step_kernel(const StepArgs a)
     for (int i = threadIdx.x; i < a.K; i += blockDim.x) s_toff[i] = a.toff[i];
     __syncthreads();
     const int cur = a.hdr->cur;
-    Rec* recs = reinterpret_cast<Rec*>(s_dyn + w * kStepLdsPerWave);
-    float* slab = reinterpret_cast<float*>(s_dyn + w * kStepLdsPerWave +
-                                           kRecMax * kWave * sizeof(Rec));
+    char* base = s_dyn + w * kStepLdsPerWave;
+    Rec* recs = reinterpret_cast<Rec*>(base);
+    float* slab = reinterpret_cast<float*>(base + kRecMax * kWave * sizeof(Rec));
+    uint8_t* idx = reinterpret_cast<uint8_t*>(base + kRecMax * kWave * sizeof(Rec) +
+                                              kChunk * kWave * sizeof(float));
     const int stride = gridDim.x * wpb;
     for (int wid = blockIdx.x * wpb + w; wid < a.nwaves; wid += stride)
-        step_tile<LOGIN, MAP>(a, wid, cur, recs, slab, s_toff);
+        step_tile<LOGIN, MAP>(a, wid, cur, recs, idx, slab, s_toff);
 }
 
 // Exclusive scan of the per-wave counts in wave (= pixel) order, two
