@@ -223,7 +223,7 @@ def bench_batch(args):
     offs = np.cumsum([0] + [w.pixels for w in ws])
     sims = [EventSim(w.width, w.height, c_pos_map=e["c_pos_map"],
                      c_neg_map=e["c_neg_map"], refractory_us=100,
-                     capacity_events=max(1 << 16, int(0.2 * w.pixels) * 4))
+                     capacity_events=2 * w.pixels + (1 << 16))
             for w, e in zip(ws, envs)]
     views = [flat[:, offs[i]:offs[i + 1]].reshape(F, w.height, w.width)
              for i, w in enumerate(ws)]
@@ -234,8 +234,12 @@ def bench_batch(args):
         for k in range(F):
             for i, s_ in enumerate(sims):
                 s_.step(views[i][k:k + 1], t[k:k + 1])
-                if k % 16 == 15:
+            for i, s_ in enumerate(sims):
+                try:
                     s_.drain()
+                except Exception as ex:
+                    raise RuntimeError("environment %d (%dx%d) frame %d: %s" % (
+                        i, ws[i].width, ws[i].height, k, ex))
 
     run_plain()
     torch.cuda.synchronize()
