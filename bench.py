@@ -67,6 +67,8 @@ def parse():
                          "-> upsampler -> events against the 1000-FPS path")
     ap.add_argument("--train-sequences", type=int, default=10_000)
     ap.add_argument("--eval-pairs", type=int, default=16)
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batch64: leave out the separate-stream comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (the reference "
                          "dispatch that scales profiler byte counters)")
@@ -241,14 +243,16 @@ def bench_batch(args):
                     raise RuntimeError("environment %d (%dx%d) frame %d: %s" % (
                         i, ws[i].width, ws[i].height, k, ex))
 
-    run_plain()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    run_plain()
-    for s_ in sims:
-        s_.sync()
-    torch.cuda.synchronize()
-    el_plain = time.perf_counter() - t1
+    el_plain = None
+    if not args.no_plain:
+        run_plain()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        run_plain()
+        for s_ in sims:
+            s_.sync()
+        torch.cuda.synchronize()
+        el_plain = time.perf_counter() - t1
     for s_ in sims:
         s_.close()
 
@@ -276,7 +280,7 @@ def bench_batch(args):
         "us_per_call": ms_batch * 1e3 / F,
         "tuning": {k: tun[k] for k in ("stage_entries", "waves_per_block",
                                        "step_blocks", "use_graph")},
-        "plain_separate_streams": {
+        "plain_separate_streams": None if el_plain is None else {
             "ms_per_step": el_plain * 1e3,
             "value": pu / el_plain / 1e9,
             "speedup_of_batch": el_plain * 1e3 / ms_batch,

@@ -30,6 +30,7 @@
 // with a guard band larger than its proven error; every lane whose result
 // the bound cannot decide is re-evaluated with the FP64 arithmetic of the
 // definition (same operations, same order, no contraction).
+#include <algorithm>
 #include <math.h>
 #include <stdint.h>
 
@@ -1028,7 +1029,15 @@ __device__ __forceinline__ bool step_fits(const Header* hdr, int64_t scap,
 
 // Copy every wave's segment to its pixel-order position and count the
 // radix digits of all passes; also clears the passes' look-back words.
-__global__ __launch_bounds__(256) void gather_kernel(const GatherArgs a) {
+// Each 16-lane group of a wave walks its own segments (a segment of a one-
+// frame call holds a handful of entries), four slots per lane per round so
+// that the loads of a round are in flight together.
+constexpr int kGatherGroup = 16;
+constexpr int kGatherUnroll = 4;
+constexpr int kGatherThreads = 256;
+constexpr int kGatherMaxBlocks = 2048;
+
+__global__ __launch_bounds__(kGatherThreads) void gather_kernel(const GatherArgs a) {
     __shared__ uint32_t s_h[kMaxPasses * kDigits];
     int64_t n;
     const bool ok = step_fits(a.hdr, a.scratch_cap, a.qcap, &n);
@@ -1044,30 +1053,40 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherArgs a) {
     for (int i = threadIdx.x; i < kMaxPasses * kDigits; i += blockDim.x) s_h[i] = 0u;
     __syncthreads();
     const int lane = lane_id();
-    const uint64_t lt = lanemask_lt();
-    const int64_t wstride = (int64_t)gridDim.x * (blockDim.x / kWave);
-    for (int64_t wv = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-         wv < a.nwaves; wv += wstride) {
+    const int gl = lane % kGatherGroup;
+    const uint64_t gmask = 0xFFFFull << (lane - gl);
+    const uint64_t lt = lanemask_lt() & gmask;
+    constexpr int kGroupsPerBlock = kGatherThreads / kGatherGroup;
+    const int64_t gstride = (int64_t)gridDim.x * kGroupsPerBlock;
+    for (int64_t wv = (int64_t)blockIdx.x * kGroupsPerBlock + threadIdx.x / kGatherGroup;
+         wv < a.nwaves; wv += gstride) {
         const int64_t sb = a.seg_base[wv];
         const uint32_t ns = a.seg_slots[wv];
         int64_t dst = a.pref[wv];
         const uint32_t key_hi = (uint32_t)a.wave_env[wv] << a.key_tbits;
         const uint32_t pix0 = (uint32_t)(wv * kWave);
-        for (uint32_t j0 = 0; j0 < ns; j0 += kWave) {
-            const uint32_t j = j0 + lane;
-            const uint32_t e = j < ns ? a.skey[sb + j] : kEntryHole;
-            const bool v = e != kEntryHole;
-            const uint64_t m = __ballot(v);
-            if (v) {
-                const int64_t pos = dst + __popcll(m & lt);
-                const uint32_t k = key_hi | (e >> 7);
-                a.dkey[pos] = k;
-                a.dval[pos] = ((pix0 + ((e >> 1) & 63u)) << 1) | (e & 1u);
-                for (int p = 0; p < a.npass; ++p)
-                    atomicAdd(&s_h[p * kDigits + ((k >> (kDigitBits * p)) & (kDigits - 1))],
-                              1u);
+        for (uint32_t j0 = 0; j0 < ns; j0 += kGatherUnroll * kGatherGroup) {
+            uint32_t e[kGatherUnroll];
+#pragma unroll
+            for (int u = 0; u < kGatherUnroll; ++u) {
+                const uint32_t j = j0 + u * kGatherGroup + gl;
+                e[u] = j < ns ? a.skey[sb + j] : kEntryHole;
             }
-            dst += __popcll(m);
+#pragma unroll
+            for (int u = 0; u < kGatherUnroll; ++u) {
+                const bool v = e[u] != kEntryHole;
+                const uint64_t m = __ballot(v) & gmask;
+                if (v) {
+                    const int64_t pos = dst + __popcll(m & lt);
+                    const uint32_t k = key_hi | (e[u] >> 7);
+                    a.dkey[pos] = k;
+                    a.dval[pos] = ((pix0 + ((e[u] >> 1) & 63u)) << 1) | (e[u] & 1u);
+                    for (int p = 0; p < a.npass; ++p)
+                        atomicAdd(&s_h[p * kDigits + ((k >> (kDigitBits * p)) & (kDigits - 1))],
+                                  1u);
+                }
+                dst += __popcll(m);
+            }
         }
     }
     __syncthreads();
@@ -1372,7 +1391,10 @@ hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(gather_kernel, dim3(512), dim3(256), 0, s, a);
+    constexpr int64_t kGroups = kGatherThreads / kGatherGroup;
+    const int64_t want = (a.nwaves + kGroups - 1) / kGroups;
+    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kGatherMaxBlocks, want));
+    hipLaunchKernelGGL(gather_kernel, dim3(blocks), dim3(kGatherThreads), 0, s, a);
     return hipGetLastError();
 }
 
