@@ -44,6 +44,7 @@ constexpr int kFastMaxCross = 32;        // longer runs per frame: FP64 replica
 constexpr int kMaxCross = 1 << 20;       // termination bound (finite input)
 constexpr uint32_t kSpinLimit = 1u << 24;
 constexpr uint32_t kAgg = 1u, kInc = 2u;
+constexpr int kLookBack = 8;   // predecessor tiles read per look-back step
 constexpr double kG32 = 0x1p-22;         // guard of the FP32 sample tests
 constexpr double kG64 = 0x1p-36;         // guard of the FP64 level tests
 constexpr float kLn2f = 0.693147180559945309f;
@@ -1153,11 +1154,15 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
             const int64_t e = base + w * (kWave * kSortItems) + i * kWave + lane;
             const bool v = e < n;
             const uint32_t d = (key[i] >> shift) & dmask;
+            // lanes holding the same digit: all kDigitBits bits are matched
+            // (a pass over fewer key bits sees zeros above them)
             uint64_t peers = __ballot(v);
-            for (int b = 0; b < a.bits; ++b) {
-                const bool bit = (d >> b) & 1u;
-                const uint64_t bb = __ballot(bit);
-                peers &= bit ? bb : ~bb;
+#pragma unroll
+            for (int b = 0; b < kDigitBits; ++b) {
+                // all ones where bit b of the digit is set
+                const uint32_t m = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
+                const uint64_t bb = __ballot(m != 0u);
+                peers &= ~(bb ^ (((uint64_t)m << 32) | m));
             }
             uint32_t prior = 0;
             if (v) prior = s_wcnt[w][d];
@@ -1191,22 +1196,45 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
             // look back over earlier tiles for digit d
             uint32_t excl = 0;
             if (tile > 0) {
+                // a window of kLookBack predecessors is read at once and
+                // walked newest first; tile 0 always publishes an inclusive
+                // prefix, so every walk ends there at the latest
                 int64_t j = tile - 1;
                 uint32_t spins = 0;
                 for (;;) {
-                    const uint32_t s = atomic_load_u32(a.status + j * kDigits + d);
-                    const uint32_t flag = s >> 30;
-                    if (flag == 0u) {
+                    uint32_t sw[kLookBack];
+#pragma unroll
+                    for (int i = 0; i < kLookBack; ++i)
+                        sw[i] = (j - i >= 0)
+                                    ? atomic_load_u32(a.status + (j - i) * kDigits + d)
+                                    : (kInc << 30);
+                    bool live = true, done = false;
+                    int adv = kLookBack;
+#pragma unroll
+                    for (int i = 0; i < kLookBack; ++i) {
+                        if (live) {
+                            const uint32_t flag = sw[i] >> 30;
+                            if (flag == 0u) {
+                                adv = i;
+                                live = false;
+                            } else {
+                                excl += sw[i] & 0x3FFFFFFFu;
+                                if (flag == kInc) {
+                                    done = true;
+                                    live = false;
+                                }
+                            }
+                        }
+                    }
+                    if (done) break;
+                    j -= adv;
+                    if (adv < kLookBack) {   // predecessor j not published yet
                         if (++spins > kSpinLimit) {
                             atomicExch(&a.hdr->internal_err, 1);
                             break;
                         }
                         __builtin_amdgcn_s_sleep(1);
-                        continue;
                     }
-                    excl += s & 0x3FFFFFFFu;
-                    if (flag == kInc || j == 0) break;
-                    --j;
                 }
                 atomic_store_u32(st, (kInc << 30) | (excl + tot));
             }
@@ -1227,26 +1255,55 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
         }
         __syncthreads();
         const int cnt = (int)((n - base) < kSortTile ? (n - base) : kSortTile);
-        for (int j = tid; j < cnt; j += kSortThreads) {
-            const uint32_t k = s_key[j];
-            const uint32_t v = s_val[j];
-            const uint32_t d = (k >> shift) & dmask;
-            const int64_t gpos = (int64_t)s_gbase[d] + (j - (int)s_lstart[d]);
-            if (gpos < 0 || gpos >= n) continue;  // only a corrupt histogram
-            if (a.final_pass) {
+        // every item of the thread is read first (and, in the last pass, its
+        // environment's record), so that the loads overlap; stores follow
+        uint32_t sk[kSortItems], sv[kSortItems];
+#pragma unroll
+        for (int i = 0; i < kSortItems; ++i) {
+            const int j = tid + i * kSortThreads;
+            sk[i] = j < cnt ? s_key[j] : 0u;
+            sv[i] = j < cnt ? s_val[j] : 0u;
+        }
+        // destination of item i (-1 past the tile's end)
+        auto dest = [&](int i) -> int64_t {
+            const int j = tid + i * kSortThreads;
+            const uint32_t d = (sk[i] >> shift) & dmask;
+            return j < cnt ? (int64_t)s_gbase[d] + (j - (int)s_lstart[d]) : -1;
+        };
+        if (a.final_pass) {
+            uint32_t ew0[kSortItems], ewd[kSortItems];
+#pragma unroll
+            for (int i = 0; i < kSortItems; ++i) {
+                const bool v = tid + i * kSortThreads < cnt;
+                const uint32_t env = sk[i] >> a.key_tbits;
+                ew0[i] = v ? (uint32_t)a.envs[env].wave0 : 0u;
+                ewd[i] = v ? (uint32_t)a.envs[env].width : 1u;
+            }
+#pragma unroll
+            for (int i = 0; i < kSortItems; ++i) {
+                const int64_t gpos = dest(i);
+                if (gpos < 0 || gpos >= n) continue;  // tail, or a corrupt histogram
                 int64_t r = tailm + gpos;
                 if (r >= a.qcap) r -= a.qcap;
-                const uint32_t env = k >> a.key_tbits;
-                const uint32_t toff = k & ((1u << a.key_tbits) - 1u);
-                const EnvRec er = a.envs[env];
-                const uint32_t px = (v >> 1) - (uint32_t)er.wave0 * kWave;
+                const uint32_t toff = sk[i] & ((1u << a.key_tbits) - 1u);
+                const uint32_t px = (sv[i] >> 1) - ew0[i] * kWave;
+                // px < 2^32 and width <= 65535: the FP64 quotient's floor is
+                // the integer quotient (its distance to the next integer,
+                // >= 1/width, exceeds the rounding error)
+                const uint32_t y = (uint32_t)((double)px / (double)ewd[i]);
+                const uint32_t x = px - y * ewd[i];
                 a.t_out[r] = a.T0 + (int64_t)toff;
-                a.x_out[r] = (uint16_t)(px % (uint32_t)er.width);
-                a.y_out[r] = (uint16_t)(px / (uint32_t)er.width);
-                a.p_out[r] = (v & 1u) ? (int8_t)1 : (int8_t)-1;
-            } else {
-                a.kout[gpos] = k;
-                a.vout[gpos] = v;
+                a.x_out[r] = (uint16_t)x;
+                a.y_out[r] = (uint16_t)y;
+                a.p_out[r] = (sv[i] & 1u) ? (int8_t)1 : (int8_t)-1;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < kSortItems; ++i) {
+                const int64_t gpos = dest(i);
+                if (gpos < 0 || gpos >= n) continue;
+                a.kout[gpos] = sk[i];
+                a.vout[gpos] = sv[i];
             }
         }
         __syncthreads();
