@@ -353,11 +353,15 @@ __device__ __forceinline__ void exact_levels(Px& q, double eps) {
 
 // ---- the frame walk, in two phases per wave ----------------------------
 //
-// Phase A walks the frames in lockstep: the per-frame test against the
-// FP32 thresholds, the crossing count of candidate lanes, the staging slots
-// of the frame's crossings ((frame, pixel, k) order), and the move of the
-// levels.  Each frame with crossings leaves a record in the lane's LDS
-// queue with everything its timestamps need.  Phase B drains the queues:
+// Phase A walks a chunk of frames per lane: each lane tests the chunk's
+// samples against its FP32 thresholds at once, then visits only its
+// candidate frames, so that one pass of the crossing path serves lanes at
+// different frames.  A visit counts the crossings and moves the levels;
+// the lane then re-tests the rest of the chunk against the new thresholds.
+// Each frame with crossings leaves a record in the lane's LDS queue with
+// everything its timestamps need.  A lane with a full queue waits; when no
+// lane can go on, the records of the frames before the earliest waiting
+// lane's frame are drained.  Phase B drains the queues:
 // first the timestamps of the records with a single crossing, in compacted
 // rounds of 64 records whatever lanes they belong to; then, per lane and in
 // record order, the refractory filter and the staged entry (or hole) of
@@ -373,12 +377,12 @@ constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // crossings past the segment
 constexpr uint32_t kRecF64 = 1u << 30;     // meta: count decided in FP64
 constexpr uint32_t kRecReady = 1u << 31;   // meta: timestamp in `tt`
 
-// Six 32-bit words: slot, meta, then either the raw inputs (the frame's
-// sample I, the previous sample, the first crossed level X1 as FP64 in the
-// sample domain) or, once ready, the FP32 interpolation (N1, 1/D, alpha,
-// beta) that the bound decides for every crossing of the record.
+// Five 32-bit words: meta, then either the raw inputs (the frame's sample
+// I, the previous sample, the first crossed level X1 as FP64 in the sample
+// domain) or, once ready, the FP32 interpolation (N1, 1/D, alpha, beta)
+// that the bound decides for every crossing of the record.  Staging slots
+// are given out when the record is drained.
 struct Rec {
-    uint32_t slot;   // staging slot of the frame's first crossing
     uint32_t meta;   // n (bits 0..20) | frame (21..28) | up (29) | f64 (30)
                      // | interpolation ready (31)
     uint32_t w0, w1, w2, w3;
@@ -387,6 +391,11 @@ __device__ __forceinline__ float rec_I(const Rec& r) { return __uint_as_float(r.
 __device__ __forceinline__ float rec_prev(const Rec& r) { return __uint_as_float(r.w1); }
 __device__ __forceinline__ double rec_X1(const Rec& r) {
     return __hiloint2double((int)r.w3, (int)r.w2);
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
+    return v;
 }
 
 __device__ __forceinline__ int wave_max_small(int v) {
@@ -400,9 +409,9 @@ __device__ __forceinline__ int wave_max_small(int v) {
 // exactly one crossing, an FP64 level walk with a small guard otherwise, the
 // FP64 replica of the definition when even that cannot decide.
 template <bool LOGIN>
-__device__ __forceinline__ void count_frame(const Px& q, float I, bool cand,
-                                            bool force64, double eps, int& n,
-                                            bool& up, bool& f64, int* dg) {
+__device__ __forceinline__ void count_frame(const Px& q, float I, float Ip,
+                                            bool cand, bool force64, double eps,
+                                            int& n, bool& up, bool& f64, int* dg) {
     // one crossing for sure: up: Bhi <= I <= Chi, down: Clo <= I <= Blo
     up = I > q.Ahi;
     const float lo = up ? q.Bhi : q.Clo;
@@ -440,7 +449,7 @@ __device__ __forceinline__ void count_frame(const Px& q, float I, bool cand,
         ++dg[4];
         if (f64) {
             ++dg[0];
-            const LogPair lp = log_pair64<LOGIN>(q.prev, I, eps);
+            const LogPair lp = log_pair64<LOGIN>(Ip, I, eps);
             const Count64 c = count64(q.L_init, q.nup, q.ndn, q.cp, q.cn, lp.L1);
             n = c.n;
             up = c.up != 0;
@@ -509,32 +518,62 @@ __device__ __forceinline__ bool ts_fast(const TsSetup& s, int j, int& tt) {
     return c1 == c2 && et < 0.25f;
 }
 
-// Phase B.  `tlast` is the lane's refractory time; `idx` is the wave's
-// compaction list (kRecMax * 64 bytes); (nup0, ndn0) are the lattice
-// counters before the lane's first queued record.
+// Phase B for the queued records of frames <= kcut, which are a prefix of
+// each lane's queue (a lane queues its records in frame order).  Every lane
+// has passed frame kcut, so the drained records are all of the wave's
+// crossings in those frames; their staging slots are given out here, lane
+// by lane, so that entries of one frame (and so of one microsecond) keep
+// pixel order.  The undrained records move to the front of the queue.
+// `idx` is the compaction list (kRecMax * 64 bytes); (nup0, ndn0) are the
+// lattice counters before the lane's first queued record.
 template <bool LOGIN>
 __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
                                               int& tlast, Rec* recs,
-                                              uint8_t* idx, int rcount,
-                                              uint32_t simple_mask, int nup0,
-                                              int ndn0,
+                                              uint8_t* idx, int& rcount,
+                                              uint32_t& simple_mask, int& nup0,
+                                              int& ndn0, int kcut,
                                               const int* s_toff, uint32_t* out,
-                                              int64_t cap, int& emitted,
+                                              int64_t cap, int64_t& slots,
+                                              bool& over, int& emitted,
                                               int& f64count, int* dg) {
     const int lane = lane_id();
     const uint32_t lane_bits = ((uint32_t)lane) << 1;
     const double eps = a.log_eps;
     const int tref = a.tref;
 
-    // 1. FP32 interpolation of the records counted in FP32, compacted over
-    //    the wave; kept when the bound decides every crossing
-    const int ns = __popc(simple_mask);
+    // 0. the drained prefix, its crossings and the lane's first slot
+    int rd = 0, ent = 0;
+#pragma unroll
+    for (int r = 0; r < kRecMax; ++r) {
+        if (r < rcount && rd == r) {
+            const uint32_t m = recs[r * kWave + lane].meta;
+            if ((int)((m >> 21) & 0xFFu) <= kcut) {
+                rd = r + 1;
+                ent += (int)(m & 0x1FFFFFu);
+            }
+        }
+    }
+    const int eincl = wave_incl_scan(ent);
+    const int etot = wave_last(eincl);
+    uint32_t lslot = kNoSlot;
+    if (etot > 0) {
+        if (!over && slots + etot <= cap)
+            lslot = (uint32_t)(slots + (eincl - ent));
+        else
+            over = true;
+        slots += etot;
+    }
+
+    // 1. FP32 interpolation of the drained records counted in FP32,
+    //    compacted over the wave; kept when the bound decides every crossing
+    const uint32_t smask = simple_mask & ((1u << rd) - 1u);
+    const int ns = __popc(smask);
     const int incl = wave_incl_scan(ns);
     const int total = wave_last(incl);
     {
         int pos = incl - ns;
         for (int r = 0; r < kRecMax; ++r)
-            if ((simple_mask >> r) & 1u) idx[pos++] = (uint8_t)(r * kWave + lane);
+            if ((smask >> r) & 1u) idx[pos++] = (uint8_t)(r * kWave + lane);
     }
     __builtin_amdgcn_wave_barrier();
     for (int c0 = 0; c0 < total; c0 += kWave) {
@@ -558,7 +597,6 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
             }
             if (ok) {
                 Rec w;
-                w.slot = rc.slot;
                 w.meta = rc.meta | kRecReady;
                 w.w0 = __float_as_uint(s.N1);
                 w.w1 = __float_as_uint(s.invD);
@@ -571,16 +609,19 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
     __builtin_amdgcn_wave_barrier();
 
     // 2. per lane, in record order: refractory filter and staged entries
-    const int rmax = wave_max_small(rcount);
+    const int rmax = wave_max_small(rd);
     int cu = nup0, cd = ndn0;
+    uint32_t run = 0;
     for (int r = 0; r < rmax; ++r) {
-        const bool act = r < rcount;
-        Rec rc{kNoSlot, 0u, 0u, 0u, 0u, 0u};
+        const bool act = r < rd;
+        Rec rc{0u, 0u, 0u, 0u, 0u};
         if (act) rc = recs[r * kWave + lane];
         const bool ready = (rc.meta & kRecReady) != 0;
         const bool up = ((rc.meta >> 29) & 1u) != 0;
         const int nrec = (int)(rc.meta & 0x1FFFFFu);
         const int cu_r = cu, cd_r = cd;
+        const uint32_t rslot = lslot == kNoSlot ? kNoSlot : lslot + run;
+        run += (uint32_t)nrec;
         if (up)
             cu += nrec;
         else
@@ -606,8 +647,8 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
                 const bool emit = (tt - tlast) >= tref;
                 if (emit) tlast = tt;
                 emitted += emit ? 1 : 0;
-                if (rc.slot != kNoSlot) {
-                    const int64_t sl = (int64_t)rc.slot + j;
+                if (rslot != kNoSlot) {
+                    const int64_t sl = (int64_t)rslot + j;
                     if (sl < cap)
                         out[sl] = emit ? (((uint32_t)tt << 7) | lane_bits |
                                           (up ? 1u : 0u))
@@ -622,7 +663,7 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
             bool f64 = false;
             TsSetup s{};
             if (full) {
-                n = (int)(rc.meta & 0x1FFFFFu);
+                n = nrec;
                 f64 = (rc.meta & kRecF64) != 0;
                 if (!f64) s = ts_setup<LOGIN>(a, rc, up ? q.cp : -q.cn, s_toff);
                 else {
@@ -657,8 +698,8 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
                     const bool emit = (tt - tlast) >= tref;
                     if (emit) tlast = tt;
                     emitted += emit ? 1 : 0;
-                    if (rc.slot != kNoSlot) {
-                        const int64_t sl = (int64_t)rc.slot + j;
+                    if (rslot != kNoSlot) {
+                        const int64_t sl = (int64_t)rslot + j;
                         if (sl < cap)
                             out[sl] = emit ? (((uint32_t)tt << 7) | lane_bits |
                                               (up ? 1u : 0u))
@@ -668,13 +709,22 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
             }
         }
     }
+
+    // 3. the undrained records move to the front of the queue
+#pragma unroll
+    for (int r = 0; r + 1 < kRecMax; ++r)
+        if (rd > 0 && r + rd < rcount) recs[r * kWave + lane] = recs[(r + rd) * kWave + lane];
+    rcount -= rd;
+    simple_mask >>= rd;
+    nup0 = cu;
+    ndn0 = cd;
 }
 
 // Walk the launch's frames for one lane's pixel (phase A), draining the
-// record queues (phase B) whenever one fills and at the end.  Crossings get
-// staging slots [0, cap) of `out`; once a frame's crossings do not fit, the
-// segment is marked overflowed and later crossings are only counted.
-// `slots` returns the slots the launch needs (holes included).
+// record queues (phase B) when lanes wait on full queues and at the end.
+// Crossings get staging slots [0, cap) of `out`; once a drain's crossings
+// do not fit, the segment is marked overflowed and later crossings are only
+// counted.  `slots` returns the slots the launch needs (holes included).
 template <bool LOGIN>
 __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
                                            bool valid, const float* fr,
@@ -695,7 +745,7 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
     // Frames are prefetched a chunk of kChunk frames ahead into registers;
     // at the start of each chunk the registers (loaded one chunk earlier)
     // are parked in the wave's LDS slab and the next chunk's loads are
-    // issued, so the frame walk reads LDS and never waits on a fresh load.
+    // issued, so the walk reads LDS and never waits on a fresh load.
     constexpr int U = kChunk;
     float r[U];
 #pragma unroll
@@ -704,8 +754,14 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
                                 : 1.0f;
 
     for (int kc = 0; kc < K; kc += U) {
+        const int cnt = (K - kc) < U ? (K - kc) : U;
+        // candidate frames of the chunk under the current thresholds
+        uint32_t cm = 0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) fslab[u * kWave + lane] = r[u];
+        for (int u = 0; u < U; ++u) {
+            fslab[u * kWave + lane] = r[u];
+            if (u < cnt && ((r[u] > q.Ahi) | (r[u] < q.Alo))) cm |= 1u << u;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int kk = kc + U + u;
@@ -713,85 +769,80 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
                        ? __builtin_nontemporal_load(fr + (int64_t)kk * P)
                        : 1.0f;
         }
-        const int cnt = (K - kc) < U ? (K - kc) : U;
-#pragma clang loop unroll(disable)
-        for (int u = 0; u < cnt; ++u) {
-            const int k = kc + u;
-            const float I = fslab[u * kWave + lane];
-            const bool cand = (I > q.Ahi) | (I < q.Alo);
-            if (__ballot(cand)) {
-                ++dg[3];
-                int n;
-                bool up, f64;
-                count_frame<LOGIN>(q, I, cand, force64, eps, n, up, f64, dg);
-                // staging slots in (frame, pixel, k) order: a popcount when
-                // every count is 0 or 1, a wave scan otherwise
-                int excl, total;
-                if (__ballot(n > 1) == 0) {
-                    const uint64_t m = __ballot(n > 0);
-                    excl = __popcll(m & lanemask_lt());
-                    total = __popcll(m);
-                } else {
-                    const int incl = wave_incl_scan(n);
-                    total = wave_last(incl);
-                    excl = incl - n;
-                }
-                if (total > 0) {
-                    uint32_t slot = kNoSlot;
-                    if (!over && slots + total <= cap)
-                        slot = (uint32_t)(slots + excl);
-                    else
-                        over = true;
-                    slots += total;
-                    if (n > 0) {
-                        if (rcount == 0) {
-                            nup0 = q.nup;
-                            ndn0 = q.ndn;
-                        }
-                        Rec rc;
-                        rc.slot = slot;
-                        rc.meta = (uint32_t)n | ((uint32_t)k << 21) |
-                                  (up ? (1u << 29) : 0u) | (f64 ? kRecF64 : 0u);
-                        const double X1 = up ? q.Xh : q.Xl;
-                        rc.w0 = __float_as_uint(I);
-                        rc.w1 = __float_as_uint(q.prev);
-                        rc.w2 = (uint32_t)__double2loint(X1);
-                        rc.w3 = (uint32_t)__double2hiint(X1);
-                        recs[rcount * kWave + lane] = rc;
-                        if (!f64) simple_mask |= 1u << rcount;
-                        ++rcount;
-                        // move the reference by the n crossings
-                        if (up)
-                            q.nup += n;
-                        else
-                            q.ndn += n;
-                        if (f64) {
-                            exact_levels<LOGIN>(q, eps);
-                        } else {
-                            const double E = up ? q.Ep : q.En;
-                            q.Xh = lvl_step<LOGIN>(q.Xh, E);
-                            q.Xl = lvl_step<LOGIN>(q.Xl, E);
-                            for (int i = 1; i < n; ++i) {
-                                q.Xh = lvl_step<LOGIN>(q.Xh, E);
-                                q.Xl = lvl_step<LOGIN>(q.Xl, E);
-                            }
-                            refresh_thresholds<LOGIN>(q, eps);
-                        }
-                    }
-                    if (__ballot(rcount == kRecMax)) {
-                        drain_records<LOGIN>(a, q, tlast, recs, idx, rcount,
-                                             simple_mask, nup0, ndn0, s_toff,
-                                             out, cap, emitted, f64count, dg);
-                        rcount = 0;
-                        simple_mask = 0;
-                    }
-                }
+        const float prev0 = q.prev;
+        for (;;) {
+            const bool has = cm != 0u;
+            const bool wait = has && rcount == kRecMax;
+            const bool go = has && !wait;
+            if (!__ballot(go)) {
+                if (!__ballot(wait)) break;
+                // every lane has passed the frames before the earliest
+                // waiting lane's frame: drain their records
+                const int fw = wait ? kc + __builtin_ctz(cm) : 0x7FFFFFFF;
+                drain_records<LOGIN>(a, q, tlast, recs, idx, rcount, simple_mask,
+                                     nup0, ndn0, wave_min(fw) - 1, s_toff, out,
+                                     cap, slots, over, emitted, f64count, dg);
+                continue;
             }
-            q.prev = I;
+            ++dg[3];
+            const int u = go ? __builtin_ctz(cm) : 0;
+            const float I = fslab[u * kWave + lane];
+            const float Ip = u > 0 ? fslab[(u - 1) * kWave + lane] : prev0;
+            int n;
+            bool up, f64;
+            count_frame<LOGIN>(q, I, Ip, go, force64, eps, n, up, f64, dg);
+            if (go) cm &= ~((2u << u) - 1u);
+            if (n > 0) {
+                if (rcount == 0) {
+                    nup0 = q.nup;
+                    ndn0 = q.ndn;
+                }
+                Rec rc;
+                rc.meta = (uint32_t)n | ((uint32_t)(kc + u) << 21) |
+                          (up ? (1u << 29) : 0u) | (f64 ? kRecF64 : 0u);
+                const double X1 = up ? q.Xh : q.Xl;
+                rc.w0 = __float_as_uint(I);
+                rc.w1 = __float_as_uint(Ip);
+                rc.w2 = (uint32_t)__double2loint(X1);
+                rc.w3 = (uint32_t)__double2hiint(X1);
+                recs[rcount * kWave + lane] = rc;
+                if (!f64) simple_mask |= 1u << rcount;
+                ++rcount;
+                // move the reference by the n crossings
+                if (up)
+                    q.nup += n;
+                else
+                    q.ndn += n;
+                if (f64) {
+                    exact_levels<LOGIN>(q, eps);
+                } else {
+                    const double E = up ? q.Ep : q.En;
+                    q.Xh = lvl_step<LOGIN>(q.Xh, E);
+                    q.Xl = lvl_step<LOGIN>(q.Xl, E);
+                    for (int i = 1; i < n; ++i) {
+                        q.Xh = lvl_step<LOGIN>(q.Xh, E);
+                        q.Xl = lvl_step<LOGIN>(q.Xl, E);
+                    }
+                    refresh_thresholds<LOGIN>(q, eps);
+                }
+                // the rest of the chunk against the new thresholds (every
+                // slab entry is read and tested; positions up to u and past
+                // the chunk's end are masked off afterwards)
+                uint32_t nm = 0;
+#pragma unroll
+                for (int v = 0; v < U; ++v) {
+                    const float J = fslab[v * kWave + lane];
+                    nm |= ((J > q.Ahi) | (J < q.Alo)) ? (1u << v) : 0u;
+                }
+                cm = nm & ~((2u << u) - 1u) & ((1u << cnt) - 1u);
+            }
         }
+        q.prev = fslab[(cnt - 1) * kWave + lane];
     }
-    drain_records<LOGIN>(a, q, tlast, recs, idx, rcount, simple_mask, nup0,
-                         ndn0, s_toff, out, cap, emitted, f64count, dg);
+    if (__ballot(rcount > 0))
+        drain_records<LOGIN>(a, q, tlast, recs, idx, rcount, simple_mask, nup0,
+                             ndn0, K - 1, s_toff, out, cap, slots, over,
+                             emitted, f64count, dg);
 }
 
 #ifdef NSIM_TILE_TRACE
@@ -926,7 +977,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
 // pixel space of all environments, so the same kernel runs as one wave per
 // tile or as a persistent grid sized to the chip.  LDS: the launch's frame
 // times per workgroup (static); per wave (dynamic, kStepLdsPerWave bytes)
-// the record queue (kRecMax x 64 records of 24 B), the kChunk x 64 frame
+// the record queue (kRecMax x 64 records of 20 B), the kChunk x 64 frame
 // slab and the compaction list (kRecMax x 64 bytes).
 constexpr int kStepLdsPerWave = kRecMax * kWave * (int)sizeof(Rec) +
                                 kChunk * kWave * (int)sizeof(float) +
