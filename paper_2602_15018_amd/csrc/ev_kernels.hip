@@ -829,10 +829,12 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
                 // slab entry is read and tested; positions up to u and past
                 // the chunk's end are masked off afterwards)
                 uint32_t nm = 0;
+                if (u + 1 < cnt) {
 #pragma unroll
-                for (int v = 0; v < U; ++v) {
-                    const float J = fslab[v * kWave + lane];
-                    nm |= ((J > q.Ahi) | (J < q.Alo)) ? (1u << v) : 0u;
+                    for (int v = 0; v < U; ++v) {
+                        const float J = fslab[v * kWave + lane];
+                        nm |= ((J > q.Ahi) | (J < q.Alo)) ? (1u << v) : 0u;
+                    }
                 }
                 cm = nm & ~((2u << u) - 1u) & ((1u << cnt) - 1u);
             }
