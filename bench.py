@@ -86,14 +86,17 @@ def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(frames_per_launch):
     """HBM bytes per step-kernel launch from the committed counter profile,
-    or None when it was taken on a different kernel source."""
+    or None when it was taken on a different kernel source or launch
+    length."""
     try:
         rec = json.load(open(TRAFFIC_FILE))
     except (OSError, ValueError):
         return None
     if rec.get("kernel_hash") != kernel_hash():
+        return None
+    if abs(rec.get("frames_per_launch", -1) - frames_per_launch) > 1e-9:
         return None
     return rec.get("bytes_per_launch")
 
@@ -564,7 +567,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(),
+            "traffic": measured_traffic(round((F - 1) / launches_per_step, 1)),
             "avg_launch_ms": k1_ms,
             "alg_bytes_per_launch": alg_bytes_launch,
             "launches_per_step": launches_per_step,

@@ -67,14 +67,17 @@ typedef struct nsim_ev_config {
     int64_t capacity_events; /* events the queue holds until drained; also
                                 the most one internal launch may produce */
     uint32_t flags;          /* NSIM_INPUT_LOG | NSIM_FORCE_FP64 */
-    int32_t max_frames_per_launch; /* 0 = automatic; else 1 .. 256 */
+    int32_t max_frames_per_launch; /* 0 = automatic (up to 128 frames while
+                                      the launch spans at most 65535 us);
+                                      else 1 .. 256 */
 } nsim_ev_config;
 
 typedef struct nsim_ev nsim_ev_t;
 
 /* Create a stream.  Allocates state (about 40 B per pixel with threshold
- * maps), per-wave staging (8 KB per 64 pixels), and per event of capacity
- * 13 B of queue plus 20 B of staging and sort scratch.
+ * maps), per-wave staging (128 B per frame of a launch per 64 pixels, at
+ * least 8 KB: 16 KB in automatic mode), and per event of capacity 13 B of
+ * queue plus 20 B of staging and sort scratch.
  * Returns NSIM_EINVAL for a bad config (out is set to NULL). */
 int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out);
 

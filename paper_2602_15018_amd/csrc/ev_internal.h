@@ -16,7 +16,7 @@ constexpr int kScanTile = 1024;              // per-wave counts per scan block
 constexpr int kMaxEnvs = 4096;
 constexpr int kChunk = 8;                     // frames prefetched per chunk
 constexpr int kMaxFramesPerLaunch = 256;
-constexpr int kAutoFramesPerLaunch = 64;
+constexpr int kAutoFramesPerLaunch = 128;
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 16;               // items per thread per tile
 constexpr int kSortTile = kSortThreads * kSortItems;

@@ -673,9 +673,9 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
     while (k < K) {
         const int64_t T0 = h->t_expect;
         int32_t kl = 0;
-        // automatic mode: 64 frames per launch (amortises the per-pixel
-        // state round trip while keeping the wave's staged events in LDS),
-        // fewer once the time span needs a third radix digit
+        // automatic mode: up to 128 frames per launch (amortises the
+        // per-pixel state round trip and each wave's set-up), fewer once the
+        // time span would need a third radix digit
         const int32_t cap_frames =
             h->max_frames > 0 ? h->max_frames : nsim::kAutoFramesPerLaunch;
         while (k + kl < K && kl < cap_frames) {
@@ -922,15 +922,22 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out) {
 
     nsim_ev* h = new (std::nothrow) nsim_ev();
     if (!h) return NSIM_ENOMEM;
+    // staging slots per wave: 32 per frame of a launch (a wave's events and
+    // holes outgrow that only in the busiest tiles, which then take an
+    // exactly sized pool segment)
+    const int32_t fpl = cfg->max_frames_per_launch > 0
+                            ? cfg->max_frames_per_launch
+                            : nsim::kAutoFramesPerLaunch;
+    const int32_t stage = std::max(nsim::kStepLdsEntries, 32 * fpl);
     const int rc = create_core(h, {d}, cfg->log_eps, cfg->refractory_us,
                                cfg->capacity_events, cfg->flags,
-                               cfg->max_frames_per_launch,
-                               nsim::kStepLdsEntries, stream);
+                               cfg->max_frames_per_launch, stage, stream);
     if (rc) {
         free_all(h);
         delete h;
         return rc;
     }
+    h->stage_entries = stage;
     *out = h;
     return NSIM_OK;
 }
