@@ -375,7 +375,9 @@ __device__ __forceinline__ void exact_levels(Px& q, double eps) {
 constexpr int kRecMax = 4;                 // records per lane between drains
 constexpr uint32_t kNoSlot = 0xFFFFFFFFu;  // crossings past the segment
 constexpr uint32_t kRecF64 = 1u << 30;     // meta: count decided in FP64
-constexpr uint32_t kRecReady = 1u << 31;   // meta: timestamp in `tt`
+constexpr uint32_t kRecReady = 1u << 31;   // meta: interpolation ready
+constexpr uint32_t kTtStored = 0xFFFFFFFFu; // w1 of a ready single-crossing
+                                            // record: w0 holds its time
 
 // Five 32-bit words: meta, then either the raw inputs (the frame's sample
 // I, the previous sample, the first crossed level X1 as FP64 in the sample
@@ -591,17 +593,27 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
             const int n = (int)(rc.meta & 0x1FFFFFu);
             const TsSetup s = ts_setup<LOGIN>(a, rc, up ? cp_o : -cn_o, s_toff);
             bool ok = true;
+            int tt0 = 0;
             for (int j = 0; j < n; ++j) {
-                int tt;
+                int tt = 0;
                 ok = ok && ts_fast(s, j, tt);
+                if (j == 0) tt0 = tt;
             }
             if (ok) {
                 Rec w;
                 w.meta = rc.meta | kRecReady;
-                w.w0 = __float_as_uint(s.N1);
-                w.w1 = __float_as_uint(s.invD);
-                w.w2 = __float_as_uint(s.alpha);
-                w.w3 = __float_as_uint(s.beta);
+                if (n == 1) {
+                    // the time itself (1/D is never a NaN pattern)
+                    w.w0 = (uint32_t)tt0;
+                    w.w1 = kTtStored;
+                    w.w2 = 0u;
+                    w.w3 = 0u;
+                } else {
+                    w.w0 = __float_as_uint(s.N1);
+                    w.w1 = __float_as_uint(s.invD);
+                    w.w2 = __float_as_uint(s.alpha);
+                    w.w3 = __float_as_uint(s.beta);
+                }
                 recs[e] = w;
             }
         }
@@ -626,10 +638,21 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
             cu += nrec;
         else
             cd += nrec;
-        if (__ballot(ready)) {
+        const bool direct = ready && rc.w1 == kTtStored;
+        if (direct) {
+            const int tt = (int)rc.w0;
+            const bool emit = (tt - tlast) >= tref;
+            if (emit) tlast = tt;
+            emitted += emit ? 1 : 0;
+            if (rslot != kNoSlot && (int64_t)rslot < cap)
+                out[rslot] = emit ? (((uint32_t)tt << 7) | lane_bits | (up ? 1u : 0u))
+                                  : kEntryHole;
+        }
+        const bool general = ready && !direct;
+        if (__ballot(general)) {
             TsSetup s{};
             int n = 0;
-            if (ready) {
+            if (general) {
                 n = nrec;
                 const int k = (int)((rc.meta >> 21) & 0xFFu);
                 s.tp = k > 0 ? s_toff[k - 1] : 0;
