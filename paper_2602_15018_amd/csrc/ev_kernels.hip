@@ -179,7 +179,7 @@ struct Px {
     int tlast;       // relative to T0 of the launch
     float prev;      // previous sample (I, or L for log input)
     float cp, cn;    // thresholds (FP32 values of the definition)
-    double Ep2, En2; // level-2 factors with the guard folded in (intensity)
+    float Ep2f, En2f; // level-2 factors with the guard folded in (intensity)
     float Ahi, Bhi, Chi;  // I > Ahi: maybe up; I >= Bhi: surely >= 1 up;
                           // I <= Chi: surely < 2 up
     float Alo, Blo, Clo;  // mirrored for down crossings
@@ -202,8 +202,12 @@ __device__ __forceinline__ double lvl_above(double X, double g, double eps) {
 }
 
 // The six FP32 sample thresholds of the current levels.  For intensity
-// input each is one FMA: X (1 -/+ g) - eps (1 +/- g), with the level-2
-// factors Ep (1 - g), En (1 + g) precomputed per pixel.
+// input each is one FP32 FMA on the level rounded once to FP32:
+// x (1 -/+ g) - eps (1 +/- g), with the level-2 factors Ep (1 - g),
+// En (1 + g) precomputed per pixel in FP32.  The three roundings (level,
+// factor or constant, FMA) move a threshold by at most 3 * 2^-24 (X + eps),
+// inside the guard g (X + eps) = 2^-22 (X + eps), with room left for the
+// FP64 level's own error (~1e-11 relative); 1 -/+ g are exact in FP32.
 template <bool LOGIN>
 __device__ __forceinline__ void refresh_thresholds(Px& q, double eps) {
     if (LOGIN) {
@@ -214,13 +218,16 @@ __device__ __forceinline__ void refresh_thresholds(Px& q, double eps) {
         q.Blo = (float)lvl_below<LOGIN>(q.Xl, kG32, eps);
         q.Clo = (float)lvl_above<LOGIN>(lvl_step<LOGIN>(q.Xl, q.En), kG32, eps);
     } else {
-        const double eb = -eps * (1.0 + kG32), ea = -eps * (1.0 - kG32);
-        q.Ahi = (float)fma(q.Xh, 1.0 - kG32, eb);
-        q.Bhi = (float)fma(q.Xh, 1.0 + kG32, ea);
-        q.Chi = (float)fma(q.Xh, q.Ep2, eb);
-        q.Alo = (float)fma(q.Xl, 1.0 + kG32, ea);
-        q.Blo = (float)fma(q.Xl, 1.0 - kG32, eb);
-        q.Clo = (float)fma(q.Xl, q.En2, ea);
+        const float eb = (float)(-eps * (1.0 + kG32));
+        const float ea = (float)(-eps * (1.0 - kG32));
+        const float gm = (float)(1.0 - kG32), gp = (float)(1.0 + kG32);
+        const float xh = (float)q.Xh, xl = (float)q.Xl;
+        q.Ahi = fmaf(xh, gm, eb);
+        q.Bhi = fmaf(xh, gp, ea);
+        q.Chi = fmaf(xh, q.Ep2f, eb);
+        q.Alo = fmaf(xl, gp, ea);
+        q.Blo = fmaf(xl, gm, eb);
+        q.Clo = fmaf(xl, q.En2f, ea);
     }
 }
 
@@ -258,8 +265,8 @@ __device__ __forceinline__ void load_pixel(Px& q, const double* L_init,
         q.Ep = exp((double)q.cp);
         q.En = exp(-(double)q.cn);
     }
-    q.Ep2 = q.Ep * (1.0 - kG32);
-    q.En2 = q.En * (1.0 + kG32);
+    q.Ep2f = (float)(q.Ep * (1.0 - kG32));
+    q.En2f = (float)(q.En * (1.0 + kG32));
     exact_levels<LOGIN>(q, eps);
     if (!valid) {
         // padding lanes never become candidates
