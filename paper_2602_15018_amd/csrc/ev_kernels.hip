@@ -801,73 +801,74 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
         }
         const float prev0 = q.prev;
         for (;;) {
-            const bool has = cm != 0u;
-            const bool wait = has && rcount == kRecMax;
-            const bool go = has && !wait;
-            if (!__ballot(go)) {
-                if (!__ballot(wait)) break;
-                // every lane has passed the frames before the earliest
-                // waiting lane's frame: drain their records
-                const int fw = wait ? kc + __builtin_ctz(cm) : 0x7FFFFFFF;
-                drain_records<LOGIN>(a, q, tlast, recs, idx, rcount, simple_mask,
-                                     nup0, ndn0, wave_min(fw) - 1, s_toff, out,
-                                     cap, slots, over, emitted, f64count, dg);
-                continue;
-            }
-            ++dg[3];
-            const int u = go ? __builtin_ctz(cm) : 0;
-            const float I = fslab[u * kWave + lane];
-            const float Ip = u > 0 ? fslab[(u - 1) * kWave + lane] : prev0;
-            int n;
-            bool up, f64;
-            count_frame<LOGIN>(q, I, Ip, go, force64, eps, n, up, f64, dg);
-            if (go) cm &= ~((2u << u) - 1u);
-            if (n > 0) {
-                if (rcount == 0) {
-                    nup0 = q.nup;
-                    ndn0 = q.ndn;
-                }
-                Rec rc;
-                rc.meta = (uint32_t)n | ((uint32_t)(kc + u) << 21) |
-                          (up ? (1u << 29) : 0u) | (f64 ? kRecF64 : 0u);
-                const double X1 = up ? q.Xh : q.Xl;
-                rc.w0 = __float_as_uint(I);
-                rc.w1 = __float_as_uint(Ip);
-                rc.w2 = (uint32_t)__double2loint(X1);
-                rc.w3 = (uint32_t)__double2hiint(X1);
-                recs[rcount * kWave + lane] = rc;
-                if (!f64) simple_mask |= 1u << rcount;
-                ++rcount;
-                // move the reference by the n crossings
-                if (up)
-                    q.nup += n;
-                else
-                    q.ndn += n;
-                if (f64) {
-                    exact_levels<LOGIN>(q, eps);
-                } else {
-                    const double E = up ? q.Ep : q.En;
-                    q.Xh = lvl_step<LOGIN>(q.Xh, E);
-                    q.Xl = lvl_step<LOGIN>(q.Xl, E);
-                    for (int i = 1; i < n; ++i) {
+            // passes while some lane can go on
+            for (;;) {
+                const bool go = cm != 0u && rcount < kRecMax;
+                if (!__ballot(go)) break;
+                ++dg[3];
+                const int u = go ? __builtin_ctz(cm) : 0;
+                const float I = fslab[u * kWave + lane];
+                const float Ip = u > 0 ? fslab[(u - 1) * kWave + lane] : prev0;
+                int n;
+                bool up, f64;
+                count_frame<LOGIN>(q, I, Ip, go, force64, eps, n, up, f64, dg);
+                if (go) cm &= ~((2u << u) - 1u);
+                if (n > 0) {
+                    if (rcount == 0) {
+                        nup0 = q.nup;
+                        ndn0 = q.ndn;
+                    }
+                    Rec rc;
+                    rc.meta = (uint32_t)n | ((uint32_t)(kc + u) << 21) |
+                              (up ? (1u << 29) : 0u) | (f64 ? kRecF64 : 0u);
+                    const double X1 = up ? q.Xh : q.Xl;
+                    rc.w0 = __float_as_uint(I);
+                    rc.w1 = __float_as_uint(Ip);
+                    rc.w2 = (uint32_t)__double2loint(X1);
+                    rc.w3 = (uint32_t)__double2hiint(X1);
+                    recs[rcount * kWave + lane] = rc;
+                    if (!f64) simple_mask |= 1u << rcount;
+                    ++rcount;
+                    // move the reference by the n crossings
+                    if (up)
+                        q.nup += n;
+                    else
+                        q.ndn += n;
+                    if (f64) {
+                        exact_levels<LOGIN>(q, eps);
+                    } else {
+                        const double E = up ? q.Ep : q.En;
                         q.Xh = lvl_step<LOGIN>(q.Xh, E);
                         q.Xl = lvl_step<LOGIN>(q.Xl, E);
+                        for (int i = 1; i < n; ++i) {
+                            q.Xh = lvl_step<LOGIN>(q.Xh, E);
+                            q.Xl = lvl_step<LOGIN>(q.Xl, E);
+                        }
+                        refresh_thresholds<LOGIN>(q, eps);
                     }
-                    refresh_thresholds<LOGIN>(q, eps);
-                }
-                // the rest of the chunk against the new thresholds (every
-                // slab entry is read and tested; positions up to u and past
-                // the chunk's end are masked off afterwards)
-                uint32_t nm = 0;
-                if (u + 1 < cnt) {
+                    // the rest of the chunk against the new thresholds (every
+                    // slab entry is read and tested; positions up to u and past
+                    // the chunk's end are masked off afterwards)
+                    uint32_t nm = 0;
+                    if (u + 1 < cnt) {
 #pragma unroll
-                    for (int v = 0; v < U; ++v) {
-                        const float J = fslab[v * kWave + lane];
-                        nm |= ((J > q.Ahi) | (J < q.Alo)) ? (1u << v) : 0u;
+                        for (int v = 0; v < U; ++v) {
+                            const float J = fslab[v * kWave + lane];
+                            nm |= ((J > q.Ahi) | (J < q.Alo)) ? (1u << v) : 0u;
+                        }
                     }
+                    cm = nm & ~((2u << u) - 1u) & ((1u << cnt) - 1u);
                 }
-                cm = nm & ~((2u << u) - 1u) & ((1u << cnt) - 1u);
             }
+            // the lanes left with candidates wait on full queues: every lane
+            // has passed the frames before the earliest waiting lane's frame,
+            // so their records drain
+            const bool wait = cm != 0u;
+            if (!__ballot(wait)) break;
+            const int fw = wait ? kc + __builtin_ctz(cm) : 0x7FFFFFFF;
+            drain_records<LOGIN>(a, q, tlast, recs, idx, rcount, simple_mask,
+                                 nup0, ndn0, wave_min(fw) - 1, s_toff, out, cap,
+                                 slots, over, emitted, f64count, dg);
         }
         q.prev = fslab[(cnt - 1) * kWave + lane];
     }
