@@ -171,6 +171,8 @@ struct PassArgs {
     int32_t shift;
     int32_t bits;
     int32_t key_tbits;
+    int32_t n_env;           // entries of envs (keys naming others are refused)
+    int32_t pad;
     const EnvRec* envs;
     int64_t T0;
     const uint32_t* hist;    // this pass's digit counts

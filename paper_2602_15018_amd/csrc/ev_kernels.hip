@@ -1184,6 +1184,9 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
     __shared__ uint32_t s_wcnt[kSortThreads / kWave][kDigits];
+    // per wave and digit: the lanes holding that digit in the current item
+    // (OR-ed in, read back, cleared; a wave's LDS operations run in order)
+    __shared__ unsigned long long s_peer[kSortThreads / kWave][kDigits];
     __shared__ uint32_t s_lstart[kDigits];
     __shared__ uint32_t s_gbase[kDigits];
     __shared__ uint32_t s_doff[kDigits];
@@ -1200,6 +1203,7 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
     const uint32_t shift = (uint32_t)a.shift;
     const uint32_t dmask = kDigits - 1;
     const int64_t tailm = a.hdr->tail % a.qcap;
+    for (int i = lane; i < kDigits; i += kWave) s_peer[w][i] = 0ull;
 
     // exclusive scan of the global digit counts: each digit's first slot
     {
@@ -1238,16 +1242,12 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
             const int64_t e = base + w * (kWave * kSortItems) + i * kWave + lane;
             const bool v = e < n;
             const uint32_t d = (key[i] >> shift) & dmask;
-            // lanes holding the same digit: all kDigitBits bits are matched
-            // (a pass over fewer key bits sees zeros above them)
-            uint64_t peers = __ballot(v);
-#pragma unroll
-            for (int b = 0; b < kDigitBits; ++b) {
-                // all ones where bit b of the digit is set
-                const uint32_t m = (uint32_t)((int32_t)(d << (31 - b)) >> 31);
-                const uint64_t bb = __ballot(m != 0u);
-                peers &= ~(bb ^ (((uint64_t)m << 32) | m));
-            }
+            // lanes holding the same digit
+            if (v) atomicOr(&s_peer[w][d], 1ull << lane);
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t peers = v ? s_peer[w][d] : 0ull;
+            __builtin_amdgcn_wave_barrier();
+            if (v) s_peer[w][d] = 0ull;
             uint32_t prior = 0;
             if (v) prior = s_wcnt[w][d];
             __builtin_amdgcn_wave_barrier();
@@ -1355,18 +1355,25 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
             return j < cnt ? (int64_t)s_gbase[d] + (j - (int)s_lstart[d]) : -1;
         };
         if (a.final_pass) {
+            // an environment index outside the table can only come from a
+            // corrupt key: the item is dropped and the step fails
             uint32_t ew0[kSortItems], ewd[kSortItems];
+            bool bad = false;
 #pragma unroll
             for (int i = 0; i < kSortItems; ++i) {
-                const bool v = tid + i * kSortThreads < cnt;
                 const uint32_t env = sk[i] >> a.key_tbits;
-                ew0[i] = v ? (uint32_t)a.envs[env].wave0 : 0u;
-                ewd[i] = v ? (uint32_t)a.envs[env].width : 1u;
+                const bool v = tid + i * kSortThreads < cnt;
+                const bool ok = env < (uint32_t)a.n_env;
+                bad = bad || (v && !ok);
+                ew0[i] = (v && ok) ? (uint32_t)a.envs[env].wave0 : 0xFFFFFFFFu;
+                ewd[i] = (v && ok) ? (uint32_t)a.envs[env].width : 1u;
             }
+            if (bad) atomicExch(&a.hdr->internal_err, 1);
 #pragma unroll
             for (int i = 0; i < kSortItems; ++i) {
                 const int64_t gpos = dest(i);
                 if (gpos < 0 || gpos >= n) continue;  // tail, or a corrupt histogram
+                if (ew0[i] == 0xFFFFFFFFu) continue;  // corrupt key
                 int64_t r = tailm + gpos;
                 if (r >= a.qcap) r -= a.qcap;
                 const uint32_t toff = sk[i] & ((1u << a.key_tbits) - 1u);

@@ -345,6 +345,7 @@ void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
         pa.bits = std::min(nsim::kDigitBits, L.nbits - nsim::kDigitBits * p);
         pa.key_tbits = tbits;
         pa.envs = h->envs;
+        pa.n_env = h->n_env;
         pa.T0 = T0;
         pa.hist = h->hist + p * nsim::kDigits;
         pa.status = h->pass_status + (int64_t)p * h->max_sort_tiles * nsim::kDigits;
