@@ -138,6 +138,34 @@ def test_parity_random_8x8(seed, F, dt, tref, mismatch):
     assert rep["exact"], rep
 
 
+@pytest.mark.parametrize("max_frames", [0, 8, 5])
+def test_busy_lanes_partial_drains(max_frames):
+    """Pixels crossing several levels in every frame beside nearly quiet
+    ones (with bursts): busy lanes fill their record queues in the middle of
+    a frame chunk and wait while the others walk on, so drains cut chunks at
+    different frames and staging slots are given out drain by drain.  Run
+    with automatic launches, with launches of one chunk, and with launches
+    ragged against the chunk."""
+    rng = np.random.default_rng(31)
+    H, W, F = 3, 200, 130
+    n = np.arange(H * W).reshape(H, W)
+    k = np.arange(F)[:, None, None]
+    base = rng.uniform(0.2, 0.8, size=(H, W))[None]
+    busy = (n % 7 == 0)[None]
+    burst = (n % 11 == 3)[None] & ((k % 40) >= 17) & ((k % 40) < 23)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=(H, W))[None]
+    logI = np.log(base) + np.where(busy, 0.9, 0.02) * np.sin(2.1 * k + ph)
+    logI = logI + np.where(burst, 0.7 * (2 * (k % 2) - 1), 0.0)
+    fr = np.exp(logI).astype(np.float32)
+    cp = rng.uniform(0.1, 0.3, size=(H, W)).astype(np.float32)
+    cn = rng.uniform(0.1, 0.3, size=(H, W)).astype(np.float32)
+    t = 5 + 500 * np.arange(F)
+    rep, got, ref, st = check_parity(fr, t, W, c_pos=cp, c_neg=cn,
+                                     refractory_us=40, max_frames=max_frames)
+    assert rep["n_oracle"] > 5000
+    assert rep["exact"], rep
+
+
 def test_parity_log_input_large_jumps():
     """Log input with jumps of tens of thresholds per frame: exercises the
     FP64 count path, multi-crossing frames and the staging overflow rerun."""
