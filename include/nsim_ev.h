@@ -145,14 +145,16 @@ typedef struct nsim_ev_stats {
     int64_t fp64_evaluations;  /* candidate crossings re-evaluated in FP64 */
     int64_t sort_passes;       /* radix passes launched */
     int64_t packed_event_bytes;/* bytes of packed events written by the step kernel */
-    int64_t diag[8];           /* diagnostic counters of the step kernel:
-                                  0 FP64 count evaluations, 1 FP64 timestamp
-                                  evaluations, 2 waves regenerated after a
-                                  staging overflow, 3 wave-frames with a
-                                  candidate, 4 wave-frames with an FP64
-                                  count, 5 wave-level event-loop iterations,
-                                  6 wave-level FP64 timestamp branches,
-                                  7 wave-frames with a crossing */
+    int64_t diag[8];           /* diagnostic counters of the step kernel,
+                                  zero unless the library was built with
+                                  NSIM_STEP_DIAG: 0 FP64 count evaluations,
+                                  1 FP64 timestamp evaluations, 2 waves
+                                  regenerated after a staging overflow,
+                                  3 crossing passes of the walk, 4 passes
+                                  with an FP64 count, 5 crossing iterations
+                                  of the full timestamp path, 6 full-path
+                                  record rounds, 7 compacted interpolation
+                                  rounds (3..7 per wave) */
 } nsim_ev_stats;
 
 int nsim_ev_set_profiling(nsim_ev_t* h, int on);

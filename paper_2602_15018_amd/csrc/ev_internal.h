@@ -54,12 +54,13 @@ struct alignas(64) Header {
     int32_t internal_err; // 1: a bounded wait gave up
     int32_t stage_full;   // 1: the staging pool could not hold a launch
     int64_t alloc;        // packed-event slots handed out in this launch
-    // diagnostic counters (summed over launches):
-    // 0 FP64 count evaluations (lanes), 1 FP64 timestamp evaluations
-    // (events), 2 waves regenerated after staging overflow, 3 wave-frames
-    // with a candidate crossing, 4 wave-frames running the FP64 count,
-    // 5 event-loop iterations (wave level), 6 wave-level FP64 timestamp
-    // branches, 7 wave-frames with at least one crossing
+    // diagnostic counters (summed over launches; filled only in builds with
+    // NSIM_STEP_DIAG): 0 FP64 count evaluations (lanes), 1 FP64 timestamp
+    // evaluations (events), 2 waves regenerated after staging overflow,
+    // 3 crossing passes of the walk (wave level), 4 passes running the FP64
+    // count (wave level), 5 crossing iterations of the full timestamp path
+    // (wave level), 6 full-path record rounds (wave level), 7 compacted
+    // interpolation rounds (wave level)
     int64_t diag[8];
 };
 

@@ -10,17 +10,20 @@
 //
 // Pipeline per launch of up to 256 frames:
 //   step_kernel  one lane per pixel walks the frames with its state in
-//                registers; crossings are staged per wave in LDS in
-//                (frame, pixel, k) order; each wave (64 pixels) is
-//                independent and writes its events to a segment it reserves
-//                with one atomic;
-//   scan_kernel  exclusive scan of the per-wave counts (pixel order);
-//   gather       segments copied into (pixel block, frame, pixel, k) order,
-//                digit histograms of the time-offset keys built on the way;
+//                registers: per chunk of 8 frames each lane visits only its
+//                candidate frames, queueing a record per frame with
+//                crossings in LDS; frame-closed drains turn records into
+//                packed entries, lane by lane, in the wave's own staging
+//                segment (a wave that outgrows it takes an exactly sized
+//                pool segment with one atomic and walks again);
+//   scan kernels exclusive scan of the per-wave counts (pixel order);
+//   gather       segments compacted (holes dropped) in wave order, digit
+//                histograms of the time-offset keys built on the way;
 //   pass_kernel  stable LSD radix passes on the time offset (onesweep:
 //                single pass per digit with per-digit look-back); the last
 //                pass expands to SoA (t, x, y, p) in the queue ring.  Equal
-//                times share a frame, so sorting on time alone yields the
+//                times share a frame, and a wave's entries of one frame are
+//                in pixel order, so sorting on time alone yields the
 //                (t, y, x, k) order;
 //   commit       all-or-nothing: append to the queue and flip the state
 //                buffers only when every event fitted.
