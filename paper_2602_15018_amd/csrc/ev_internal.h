@@ -19,7 +19,7 @@ constexpr int kChunk = 8;                     // frames prefetched per chunk
 constexpr int kMaxFramesPerLaunch = 256;
 constexpr int kAutoFramesPerLaunch = 128;
 constexpr int kSortThreads = 256;
-constexpr int kSortItems = 16;               // items per thread per tile
+constexpr int kSortItems = 24;               // items per thread per tile
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kDigitBits = 8;
 constexpr int kDigits = 1 << kDigitBits;
