@@ -239,6 +239,9 @@ template <bool LOGIN>
 __device__ __forceinline__ void exact_levels(Px& q, double eps);
 
 template <bool LOGIN>
+__device__ __forceinline__ void pixel_levels(Px& q, bool valid, double eps);
+
+template <bool LOGIN>
 __device__ __forceinline__ void load_pixel(Px& q, const double* L_init,
                                            const int2* nud, const float* prev,
                                            const int32_t* tlast,
@@ -261,6 +264,62 @@ __device__ __forceinline__ void load_pixel(Px& q, const double* L_init,
         q.tlast = kTlastNone;
         q.cp = q.cn = 1.0f;
     }
+    pixel_levels<LOGIN>(q, valid, eps);
+}
+
+// The inputs of one wave tile of a one-frame launch, loaded a tile ahead in
+// a persistent loop so that their latency overlaps the previous tile.
+struct TileIn {
+    double L_init;
+    int2 nud;
+    float prev;
+    int32_t tlast;
+    float cp, cn;
+    float I0;       // the launch's only frame
+    int32_t valid;
+};
+
+template <bool MAP>
+__device__ __forceinline__ void tile_in(const StepArgs& a, int wid, int cur,
+                                        TileIn& t) {
+    const int lane = lane_id();
+    const EnvRec er = a.envs[a.wave_env[wid]];
+    const int local = (wid - er.wave0) * kWave + lane;
+    const int pix = wid * kWave + lane;
+    t.valid = local < er.npix;
+    if (t.valid) {
+        t.L_init = a.L_init[pix];
+        t.nud = a.nud[cur][pix];
+        t.prev = a.prev[cur][pix];
+        t.tlast = a.tlast[cur][pix];
+        t.cp = MAP ? a.c_pos_map[pix] : a.c_pos;
+        t.cn = MAP ? a.c_neg_map[pix] : a.c_neg;
+        t.I0 = __builtin_nontemporal_load(a.frames + er.frame_off + local);
+    } else {
+        t.L_init = 0.0;
+        t.nud = make_int2(0, 0);
+        t.prev = 1.0f;
+        t.tlast = kTlastNone;
+        t.cp = t.cn = 1.0f;
+        t.I0 = 1.0f;
+    }
+}
+
+template <bool LOGIN>
+__device__ __forceinline__ void pixel_from(Px& q, const TileIn& t, double eps) {
+    q.L_init = t.L_init;
+    q.nup = t.nud.x;
+    q.ndn = t.nud.y;
+    q.prev = t.prev;
+    q.tlast = t.tlast;
+    q.cp = t.cp;
+    q.cn = t.cn;
+    pixel_levels<LOGIN>(q, t.valid != 0, eps);
+}
+
+// Level steps, current levels and thresholds of a loaded pixel.
+template <bool LOGIN>
+__device__ __forceinline__ void pixel_levels(Px& q, bool valid, double eps) {
     if (LOGIN) {
         q.Ep = (double)q.cp;
         q.En = -(double)q.cn;
@@ -758,9 +817,9 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
 // Crossings get staging slots [0, cap) of `out`; once a drain's crossings
 // do not fit, the segment is marked overflowed and later crossings are only
 // counted.  `slots` returns the slots the launch needs (holes included).
-template <bool LOGIN>
+template <bool LOGIN, bool ONE>
 __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
-                                           bool valid, const float* fr,
+                                           bool valid, const float* fr, float I0,
                                            Rec* recs, uint8_t* idx, float* fslab,
                                            const int* s_toff, uint32_t* out,
                                            int64_t cap, int64_t& slots,
@@ -779,12 +838,14 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
     // at the start of each chunk the registers (loaded one chunk earlier)
     // are parked in the wave's LDS slab and the next chunk's loads are
     // issued, so the walk reads LDS and never waits on a fresh load.
-    constexpr int U = kChunk;
+    // (one-frame launches: a chunk of one frame, the sample loaded ahead)
+    constexpr int U = ONE ? 1 : kChunk;
     float r[U];
 #pragma unroll
     for (int u = 0; u < U; ++u)
-        r[u] = (valid && u < K) ? __builtin_nontemporal_load(fr + (int64_t)u * P)
-                                : 1.0f;
+        r[u] = ONE ? (valid ? I0 : 1.0f)
+                   : ((valid && u < K) ? __builtin_nontemporal_load(fr + (int64_t)u * P)
+                                       : 1.0f);
 
     for (int kc = 0; kc < K; kc += U) {
         const int cnt = (K - kc) < U ? (K - kc) : U;
@@ -798,7 +859,7 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int kk = kc + U + u;
-            r[u] = (valid && kk < K)
+            r[u] = (!ONE && valid && kk < K)
                        ? __builtin_nontemporal_load(fr + (int64_t)kk * P)
                        : 1.0f;
         }
@@ -902,24 +963,30 @@ __device__ uint64_t g_tile_trace[1 << 17][8];
 // the fixed segments, filled by walking the frames again from the launch's
 // starting state).  The scan and gather kernels restore pixel-block order
 // afterwards.
-template <bool LOGIN, bool MAP>
+// ONE: a one-frame launch whose tile inputs `tin` were loaded ahead.
+template <bool LOGIN, bool MAP, bool ONE>
 __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
                                           Rec* recs, uint8_t* idx, float* fslab,
-                                          const int* s_toff) {
+                                          const int* s_toff, const TileIn& tin) {
     Header* hdr = a.hdr;
     const int lane = lane_id();
     TILE_STAMP(0);
-    const int env = a.wave_env[wid];
-    const EnvRec er = a.envs[env];
-    const int local = (wid - er.wave0) * kWave + lane;
     const int pix = wid * kWave + lane;
-    const bool valid = local < er.npix;
-    const float* fr = a.frames + er.frame_off + local;
-
+    bool valid;
+    const float* fr = nullptr;
     Px q;
-    load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
-                      MAP ? a.c_pos_map : nullptr, MAP ? a.c_neg_map : nullptr,
-                      a.c_pos, a.c_neg, pix, valid, a.log_eps);
+    if (ONE) {
+        valid = tin.valid != 0;
+        pixel_from<LOGIN>(q, tin, a.log_eps);
+    } else {
+        const EnvRec er = a.envs[a.wave_env[wid]];
+        const int local = (wid - er.wave0) * kWave + lane;
+        valid = local < er.npix;
+        fr = a.frames + er.frame_off + local;
+        load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
+                          MAP ? a.c_pos_map : nullptr, MAP ? a.c_neg_map : nullptr,
+                          a.c_pos, a.c_neg, pix, valid, a.log_eps);
+    }
     int tlast = q.tlast;
 
     TILE_STAMP(1);
@@ -928,9 +995,9 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
     bool over = false;
     int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t S = a.stage_entries;
-    walk_split<LOGIN>(a, q, tlast, valid, fr, recs, idx, fslab, s_toff,
-                      a.out_key + (int64_t)wid * S, S, slots, over, emitted,
-                      f64count, dg);
+    walk_split<LOGIN, ONE>(a, q, tlast, valid, fr, tin.I0, recs, idx, fslab,
+                           s_toff, a.out_key + (int64_t)wid * S, S, slots, over,
+                           emitted, f64count, dg);
     dg[2] = over ? 1 : 0;
     TILE_STAMP(2);
 
@@ -988,17 +1055,21 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
         }
         // regenerate this wave's events from the launch's starting state
         // into the pool segment, which fits them exactly
-        load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
-                          MAP ? a.c_pos_map : nullptr,
-                          MAP ? a.c_neg_map : nullptr, a.c_pos, a.c_neg, pix,
-                          valid, a.log_eps);
+        if (ONE)
+            pixel_from<LOGIN>(q, tin, a.log_eps);
+        else
+            load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
+                              MAP ? a.c_pos_map : nullptr,
+                              MAP ? a.c_neg_map : nullptr, a.c_pos, a.c_neg, pix,
+                              valid, a.log_eps);
         tlast = q.tlast;
         int e2 = 0, f2 = 0;
         int64_t s2 = 0;
         bool o2 = false;
         int dg2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        walk_split<LOGIN>(a, q, tlast, valid, fr, recs, idx, fslab, s_toff,
-                          a.out_key + base, slots, s2, o2, e2, f2, dg2);
+        walk_split<LOGIN, ONE>(a, q, tlast, valid, fr, tin.I0, recs, idx, fslab,
+                               s_toff, a.out_key + base, slots, s2, o2, e2, f2,
+                               dg2);
     }
     TILE_STAMP(4);
 #ifdef NSIM_TILE_TRACE
@@ -1019,7 +1090,10 @@ constexpr int kStepLdsPerWave = kRecMax * kWave * (int)sizeof(Rec) +
                                 kChunk * kWave * (int)sizeof(float) +
                                 kRecMax * kWave;
 
-template <bool LOGIN, bool MAP>
+// ONE (launches of one frame): each wave loads its next tile's inputs before
+// it works on the current one, so that in a persistent grid the loads of a
+// tile overlap the work of the one before.
+template <bool LOGIN, bool MAP, bool ONE>
 __global__ __launch_bounds__(kStepMaxThreads)
 __attribute__((amdgpu_waves_per_eu(4))) void step_kernel(const StepArgs a) {
     extern __shared__ char s_dyn[];
@@ -1036,8 +1110,20 @@ __attribute__((amdgpu_waves_per_eu(4))) void step_kernel(const StepArgs a) {
     uint8_t* idx = reinterpret_cast<uint8_t*>(base + kRecMax * kWave * sizeof(Rec) +
                                               kChunk * kWave * sizeof(float));
     const int stride = gridDim.x * wpb;
-    for (int wid = blockIdx.x * wpb + w; wid < a.nwaves; wid += stride)
-        step_tile<LOGIN, MAP>(a, wid, cur, recs, idx, slab, s_toff);
+    int wid = blockIdx.x * wpb + w;
+    if (ONE) {
+        TileIn nx;
+        if (wid < a.nwaves) tile_in<MAP>(a, wid, cur, nx);
+        for (; wid < a.nwaves; wid += stride) {
+            const TileIn t = nx;
+            if (wid + stride < a.nwaves) tile_in<MAP>(a, wid + stride, cur, nx);
+            step_tile<LOGIN, MAP, true>(a, wid, cur, recs, idx, slab, s_toff, t);
+        }
+    } else {
+        const TileIn none{};
+        for (; wid < a.nwaves; wid += stride)
+            step_tile<LOGIN, MAP, false>(a, wid, cur, recs, idx, slab, s_toff, none);
+    }
 }
 
 // Exclusive scan of the per-wave counts in wave (= pixel) order, two
@@ -1518,17 +1604,26 @@ hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
     const dim3 grid(blocks);
     const dim3 block(waves_per_block * kWave);
     const size_t lds = (size_t)waves_per_block * kStepLdsPerWave;
+    // launches of one frame take the variant that loads tiles ahead
+#define NSIM_STEP(L, M)                                                          \
+    do {                                                                        \
+        if (a.K == 1)                                                           \
+            hipLaunchKernelGGL((step_kernel<L, M, true>), grid, block, lds, s, a);  \
+        else                                                                    \
+            hipLaunchKernelGGL((step_kernel<L, M, false>), grid, block, lds, s, a); \
+    } while (0)
     if (log_input) {
         if (has_map)
-            hipLaunchKernelGGL((step_kernel<true, true>), grid, block, lds, s, a);
+            NSIM_STEP(true, true);
         else
-            hipLaunchKernelGGL((step_kernel<true, false>), grid, block, lds, s, a);
+            NSIM_STEP(true, false);
     } else {
         if (has_map)
-            hipLaunchKernelGGL((step_kernel<false, true>), grid, block, lds, s, a);
+            NSIM_STEP(false, true);
         else
-            hipLaunchKernelGGL((step_kernel<false, false>), grid, block, lds, s, a);
+            NSIM_STEP(false, false);
     }
+#undef NSIM_STEP
     return hipGetLastError();
 }
 
