@@ -1206,11 +1206,16 @@ __device__ __forceinline__ bool step_fits(const Header* hdr, int64_t scap,
 // Each 16-lane group of a wave walks its own segments (a segment of a one-
 // frame call holds a handful of entries), four slots per lane per round so
 // that the loads of a round are in flight together.
+// Every workgroup adds its digit counts to the global histogram with
+// atomics on the same few hundred words; when segments are many and short
+// (one-frame batches) wide workgroups keep those flushes few, otherwise
+// 256-thread workgroups keep the chip full.
 constexpr int kGatherGroup = 16;
 constexpr int kGatherUnroll = 4;
-constexpr int kGatherThreads = 256;
-constexpr int kGatherMaxBlocks = 2048;
+constexpr int kGatherMaxBlocks = 2048;    // 256-thread workgroups
+constexpr int kGatherWideBlocks = 512;    // 1024-thread workgroups
 
+template <int kGatherThreads>
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const GatherArgs a) {
     __shared__ uint32_t s_h[kMaxPasses * kDigits];
     int64_t n;
@@ -1637,10 +1642,16 @@ hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
-    constexpr int64_t kGroups = kGatherThreads / kGatherGroup;
+    constexpr int64_t kGroups = 256 / kGatherGroup;
     const int64_t want = (a.nwaves + kGroups - 1) / kGroups;
-    const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kGatherMaxBlocks, want));
-    hipLaunchKernelGGL(gather_kernel, dim3(blocks), dim3(kGatherThreads), 0, s, a);
+    if (want > kGatherMaxBlocks) {
+        const int64_t wide = (a.nwaves + 4 * kGroups - 1) / (4 * kGroups);
+        const int blocks = (int)std::min<int64_t>(kGatherWideBlocks, wide);
+        hipLaunchKernelGGL(gather_kernel<1024>, dim3(blocks), dim3(1024), 0, s, a);
+    } else {
+        const int blocks = (int)std::max<int64_t>(1, want);
+        hipLaunchKernelGGL(gather_kernel<256>, dim3(blocks), dim3(256), 0, s, a);
+    }
     return hipGetLastError();
 }
 
