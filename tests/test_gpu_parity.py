@@ -259,6 +259,23 @@ def test_ragged_sizes(H, W):
     assert rep["exact"], rep
 
 
+def test_one_frame_calls_ragged():
+    """A stream stepped one frame per call (the variant that loads each
+    tile's inputs ahead) on a size that leaves padding lanes, with per-pixel
+    thresholds and a refractory period: identical to the oracle."""
+    H, W, F = 37, 29, 40
+    fr = scene.random_frames(41, F, H, W)
+    rng = np.random.default_rng(41)
+    cp = rng.uniform(0.05, 0.4, size=(H, W)).astype(np.float32)
+    cn = rng.uniform(0.05, 0.4, size=(H, W)).astype(np.float32)
+    t = 3 + 700 * np.arange(F)
+    rep, got, ref, st = check_parity(fr, t, W, c_pos=cp, c_neg=cn, refractory_us=150,
+                                     chunks=list(range(F + 1)))
+    assert rep["n_oracle"] > 500
+    assert rep["exact"], rep
+    assert st["step_launches"] == F - 1
+
+
 def test_static_scene_gpu():
     f0 = np.random.default_rng(1).uniform(0.01, 1, size=(31, 45)).astype(np.float32)
     fr = np.repeat(f0[None], 12, axis=0)
