@@ -11,7 +11,8 @@ constexpr int kWave = 64;
 constexpr int kStepMaxThreads = 256;         // at most 4 waves per workgroup
 constexpr int kStepWaves = 1;                // default waves per workgroup: a workgroup
                                               // holds its LDS until its slowest wave ends
-constexpr int kStepLdsEntries = 2048;        // default staging slots per wave
+constexpr int kStepLdsEntries = 2048;        // staging slots per wave: single streams
+                                              // take 32 per frame of a launch, at least this
 constexpr int kStepMaxLdsEntries = 1 << 20;  // (4 B each, global memory)
 constexpr int kScanTile = 1024;              // per-wave counts per scan block
 constexpr int kMaxEnvs = 4096;
