@@ -533,7 +533,7 @@ int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
     const int64_t M = (int64_t)a.N * a.H * a.W;
-    if (a.Cin % 4 || a.Ca % 4 || a.Cb % 4 || a.Kpad % 16 || a.K > a.Kpad ||
+    if (a.Cin <= 0 || a.Cin % 4 || a.Ca % 4 || a.Cb % 4 || a.Kpad % 16 || a.K > a.Kpad ||
         a.Cout % 16 || a.CoA > a.Cout || a.CoA < 0 || M <= 0 ||
         (a.b_half && (a.H % 2 || a.W % 2)))
         return hipErrorInvalidValue;
