@@ -206,20 +206,24 @@ __global__ __launch_bounds__(kWgradThreads) void wgrad_kernel(const WgradArgs a)
 #pragma unroll
     for (int i = 0; i < MT; ++i) bsum[i] = 0.f;
 
+    // (n, y, x) of the 4 pixels m0 + 4 g4 + e of this lane's k-group: one
+    // division at the start, then each step of 64 pixels moves them on by
+    // (64 / W rows, 64 % W columns) with carries (only pixels below p1 are
+    // read, and those coordinates are exact).
+    int pn[4], py[4], px[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t m = p0 + 16 * wv + 4 * g4 + e;
+        pn[e] = (int)(m / HW);
+        const int rem = (int)(m - (int64_t)pn[e] * HW);
+        py[e] = rem / a.W;
+        px[e] = rem - py[e] * a.W;
+    }
+    const int sy = 64 / a.W, sx = 64 - sy * a.W;
     for (int64_t m0 = p0 + 16 * wv; m0 < p1; m0 += 64) {
-        // the 4 pixels of this lane's k-group
-        int pn[4], py[4], px[4];
         bool pv[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int64_t m = m0 + 4 * g4 + e;
-            pv[e] = m < p1;
-            const int64_t mm = pv[e] ? m : 0;
-            pn[e] = (int)(mm / HW);
-            const int rem = (int)(mm - (int64_t)pn[e] * HW);
-            py[e] = rem / a.W;
-            px[e] = rem - py[e] * a.W;
-        }
+        for (int e = 0; e < 4; ++e) pv[e] = m0 + 4 * g4 + e < p1;
         s4 af[MT];
 #pragma unroll
         for (int i = 0; i < MT; ++i) {
@@ -247,6 +251,20 @@ __global__ __launch_bounds__(kWgradThreads) void wgrad_kernel(const WgradArgs a)
             }
 #pragma unroll
             for (int i = 0; i < MT; ++i) acc[i][j] = mfma(af[i], bf, acc[i][j]);
+        }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            px[e] += sx;
+            py[e] += sy;
+            if (px[e] >= a.W) {
+                px[e] -= a.W;
+                ++py[e];
+            }
+            if (py[e] >= a.H) {
+                const int q = py[e] / a.H;
+                pn[e] += q;
+                py[e] -= q * a.H;
+            }
         }
     }
     // sum the four waves' tiles in LDS (fixed order), then write
