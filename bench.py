@@ -467,15 +467,7 @@ def main():
         print("bench.py runs on one GPU only; this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    if args.workload == "batch64":
-        bench_batch(args)
-        return
-    if args.workload == "learned":
-        bench_learned(args)
-        return
     import torch
-
-    from paper_2602_15018_amd import scene
 
     dev = torch.device("cuda", 0)
     if args.calib_copy:
@@ -485,6 +477,14 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("calibration copy: 1 GiB read + 1 GiB written")
+    if args.workload == "batch64":
+        bench_batch(args)
+        return
+    if args.workload == "learned":
+        bench_learned(args)
+        return
+
+    from paper_2602_15018_amd import scene
     w = scene.WORKLOADS[WORKLOAD]
     F = args.frames or w.frames
     t = scene.frame_times(w, 0, F)
