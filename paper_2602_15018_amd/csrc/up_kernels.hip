@@ -39,39 +39,14 @@ __device__ __forceinline__ bool bf_positive(short b) {
     return b > 0;  // sign bit clear and not +0
 }
 
-// Four consecutive input channels [c, c + 4) of pixel (n, yy, xx) of the
-// concatenated input (zero outside the image), as MFMA operand elements.
+// The concatenated input of a convolution: channels [0, Ca) from A, the
+// next Cb from B (at half resolution with b_half), NHWC bfloat16.
 struct Src {
     const uint16_t* A;
     const uint16_t* B;
     const uint16_t* maskA;
     int Ca, Cb, H, W, b_half;
 };
-
-__device__ __forceinline__ s4 load4(const Src& s, int n, int yy, int xx, int c) {
-    s4 v = {0, 0, 0, 0};
-    if (yy < 0 || yy >= s.H || xx < 0 || xx >= s.W) return v;
-    if (c < s.Ca) {
-        const int64_t off = (((int64_t)n * s.H + yy) * s.W + xx) * s.Ca + c;
-        v = *reinterpret_cast<const s4*>(s.A + off);
-        if (s.maskA) {
-            const s4 m = *reinterpret_cast<const s4*>(s.maskA + off);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = bf_positive(m[e]) ? v[e] : (short)0;
-        }
-    } else {
-        const int cb = c - s.Ca;
-        int64_t off;
-        if (s.b_half) {
-            const int Hh = s.H >> 1, Wh = s.W >> 1;
-            off = (((int64_t)n * Hh + (yy >> 1)) * Wh + (xx >> 1)) * s.Cb + cb;
-        } else {
-            off = (((int64_t)n * s.H + yy) * s.W + xx) * s.Cb + cb;
-        }
-        v = *reinterpret_cast<const s4*>(s.B + off);
-    }
-    return v;
-}
 
 // One element (channel c) of the concatenated input at (n, yy, xx).
 __device__ __forceinline__ short load1(const Src& s, int n, int yy, int xx, int c) {
@@ -101,19 +76,32 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const ConvArgs a) {
     const int64_t base = ((int64_t)blockIdx.x * (kConvThreads / kWave) + wv) * 64;
     if (base >= M) return;
     const int r16 = lane & 15, g4 = lane >> 4;
-    const Src src{a.inA, a.inB, a.maskA, a.Ca, a.Cb, a.H, a.W, a.b_half};
 
+    // Per pixel i (index m, coordinates n, y, x): the set of taps (ky, kx)
+    // whose source pixel (y + ky - 1, x + kx - 1) lies in the image, as bit
+    // 3 ky + kx of tv (empty past the last pixel), and m Ca.  Tap (ky, kx),
+    // channel c < Ca of pixel i is then element m Ca + ((ky - 1) W + kx - 1)
+    // Ca + c of inA: one add per operand load, the rest once per K step.
     int pn[4], py[4], px[4];
-    bool pv[4];
+    uint32_t tv[4];
+    int64_t mA[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const int64_t m = base + 16 * i + r16;
-        pv[i] = m < M;
-        const int64_t mm = pv[i] ? m : 0;
+        const bool pv = m < M;
+        const int64_t mm = pv ? m : 0;
         pn[i] = (int)(mm / HW);
         const int rem = (int)(mm - (int64_t)pn[i] * HW);
         py[i] = rem / a.W;
         px[i] = rem - py[i] * a.W;
+        mA[i] = mm * a.Ca;
+        const uint32_t rows = (py[i] > 0 ? 1u : 0u) | 2u | (py[i] + 1 < a.H ? 4u : 0u);
+        const uint32_t cols = (px[i] > 0 ? 1u : 0u) | 2u | (px[i] + 1 < a.W ? 4u : 0u);
+        uint32_t bits = 0;
+#pragma unroll
+        for (int ky = 0; ky < 3; ++ky)
+            if ((rows >> ky) & 1u) bits |= cols << (3 * ky);
+        tv[i] = pv ? bits : 0u;
     }
     f4 acc[4][NT];
 #pragma unroll
@@ -121,18 +109,48 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const ConvArgs a) {
 #pragma unroll
         for (int j = 0; j < NT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
 
+    // Column k0 = 16 ks + 4 g4 of the im2col operand is channel c of tap
+    // (ky, kx): one division at the start, then each K step of 16 moves
+    // (tap, c) on by (16 / Cin, 16 % Cin) with one carry.
     const int ksteps = a.Kpad / 16;
+    const int dtap = 16 / a.Cin, dc = 16 - dtap * a.Cin;
+    const int Hh = a.H >> 1, Wh = a.W >> 1;
+    int k0 = g4 * 4;
+    int tap = k0 / a.Cin;
+    int c = k0 - tap * a.Cin;
     for (int ks = 0; ks < ksteps; ++ks) {
-        const int k0 = ks * 16 + g4 * 4;
-        const int tap = k0 / a.Cin;
-        const int c = k0 - tap * a.Cin;
-        const int ky = tap / 3, kx = tap - 3 * (tap / 3);
-        const bool kv = k0 < a.K;
+        const int ky = tap / 3, kx = tap - 3 * ky;
+        const uint32_t tbit = k0 < a.K ? 1u << (tap & 31) : 0u;
         s4 af[4];
+        if (c < a.Ca) {
+            const int d = ((ky - 1) * a.W + (kx - 1)) * a.Ca + c;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            af[i] = s4{0, 0, 0, 0};
-            if (kv && pv[i]) af[i] = load4(src, pn[i], py[i] + ky - 1, px[i] + kx - 1, c);
+            for (int i = 0; i < 4; ++i) {
+                af[i] = s4{0, 0, 0, 0};
+                if (tv[i] & tbit) {
+                    const int64_t off = mA[i] + d;
+                    af[i] = *reinterpret_cast<const s4*>(a.inA + off);
+                    if (a.maskA) {
+                        const s4 mk = *reinterpret_cast<const s4*>(a.maskA + off);
+#pragma unroll
+                        for (int e = 0; e < 4; ++e)
+                            af[i][e] = bf_positive(mk[e]) ? af[i][e] : (short)0;
+                    }
+                }
+            }
+        } else {
+            const int cb = c - a.Ca;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                af[i] = s4{0, 0, 0, 0};
+                if (tv[i] & tbit) {
+                    const int yy = py[i] + ky - 1, xx = px[i] + kx - 1;
+                    const int64_t pix =
+                        a.b_half ? ((int64_t)pn[i] * Hh + (yy >> 1)) * Wh + (xx >> 1)
+                                 : ((int64_t)pn[i] * a.H + yy) * a.W + xx;
+                    af[i] = *reinterpret_cast<const s4*>(a.inB + pix * a.Cb + cb);
+                }
+            }
         }
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
@@ -140,6 +158,13 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const ConvArgs a) {
                 a.wt + (int64_t)(16 * j + r16) * a.Kpad + ks * 16 + g4 * 4);
 #pragma unroll
             for (int i = 0; i < 4; ++i) acc[i][j] = mfma(af[i], bf, acc[i][j]);
+        }
+        k0 += 16;
+        tap += dtap;
+        c += dc;
+        if (c >= a.Cin) {
+            c -= a.Cin;
+            ++tap;
         }
     }
     const int CoB = a.Cout - a.CoA;
