@@ -25,7 +25,10 @@ constexpr int kHeadOut = 7;
 // resolution: nearest 2x upsampling folded into the read).  With maskA set,
 // inA elements whose mask element is not positive read as zero (the ReLU
 // derivative of a backward pass).  Output channels [0, CoA) go to outA
-// (optionally added to its contents), the rest to outB.
+// (optionally added to its contents), the rest to outB.  At most
+// kConvMaxPixels output pixels (N H W) per call: the kernel indexes pixels
+// in 32 bits, with headroom for the last workgroup's lanes.
+constexpr int64_t kConvMaxPixels = ((int64_t)1 << 31) - 1024;
 struct ConvArgs {
     const uint16_t* inA;
     const uint16_t* inB;

@@ -71,9 +71,11 @@ template <int NT>
 __global__ __launch_bounds__(kConvThreads) void conv_kernel(const ConvArgs a) {
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
-    const int64_t HW = (int64_t)a.H * a.W;
-    const int64_t M = (int64_t)a.N * HW;
-    const int64_t base = ((int64_t)blockIdx.x * (kConvThreads / kWave) + wv) * 64;
+    // Pixel indices fit in 32 bits (the launcher rejects 2^31 pixels or
+    // more); element offsets are formed in 64 bits.
+    const int HW = a.H * a.W;
+    const int M = a.N * HW;
+    const int base = (blockIdx.x * (kConvThreads / kWave) + wv) * 64;
     if (base >= M) return;
     const int r16 = lane & 15, g4 = lane >> 4;
 
@@ -82,19 +84,20 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const ConvArgs a) {
     // 3 ky + kx of tv (empty past the last pixel), and m Ca.  Tap (ky, kx),
     // channel c < Ca of pixel i is then element m Ca + ((ky - 1) W + kx - 1)
     // Ca + c of inA: one add per operand load, the rest once per K step.
-    int pn[4], py[4], px[4];
+    int pm[4], pn[4], py[4], px[4];
     uint32_t tv[4];
     int64_t mA[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-        const int64_t m = base + 16 * i + r16;
+        const int m = base + 16 * i + r16;
         const bool pv = m < M;
-        const int64_t mm = pv ? m : 0;
-        pn[i] = (int)(mm / HW);
-        const int rem = (int)(mm - (int64_t)pn[i] * HW);
+        const int mm = pv ? m : 0;
+        pm[i] = mm;
+        pn[i] = mm / HW;
+        const int rem = mm - pn[i] * HW;
         py[i] = rem / a.W;
         px[i] = rem - py[i] * a.W;
-        mA[i] = mm * a.Ca;
+        mA[i] = (int64_t)mm * a.Ca;
         const uint32_t rows = (py[i] > 0 ? 1u : 0u) | 2u | (py[i] + 1 < a.H ? 4u : 0u);
         const uint32_t cols = (px[i] > 0 ? 1u : 0u) | 2u | (px[i] + 1 < a.W ? 4u : 0u);
         uint32_t bits = 0;
@@ -139,16 +142,18 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const ConvArgs a) {
                 }
             }
         } else {
+            // inB: pixel m + (ky - 1) W + kx - 1 at full resolution, else
+            // (n, (y + ky - 1) / 2, (x + kx - 1) / 2) of the half-size image.
             const int cb = c - a.Ca;
+            const int dpix = (ky - 1) * a.W + (kx - 1);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 af[i] = s4{0, 0, 0, 0};
                 if (tv[i] & tbit) {
-                    const int yy = py[i] + ky - 1, xx = px[i] + kx - 1;
-                    const int64_t pix =
-                        a.b_half ? ((int64_t)pn[i] * Hh + (yy >> 1)) * Wh + (xx >> 1)
-                                 : ((int64_t)pn[i] * a.H + yy) * a.W + xx;
-                    af[i] = *reinterpret_cast<const s4*>(a.inB + pix * a.Cb + cb);
+                    const int pix = a.b_half ? (pn[i] * Hh + ((py[i] + ky - 1) >> 1)) * Wh +
+                                                   ((px[i] + kx - 1) >> 1)
+                                             : pm[i] + dpix;
+                    af[i] = *reinterpret_cast<const s4*>(a.inB + (int64_t)pix * a.Cb + cb);
                 }
             }
         }
@@ -176,16 +181,16 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const ConvArgs a) {
         for (int i = 0; i < 4; ++i) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t m = base + 16 * i + 4 * g4 + r;
+                const int m = base + 16 * i + 4 * g4 + r;
                 if (m >= M) continue;
                 float v = acc[i][j][r] + b;
                 if (a.relu) v = fmaxf(v, 0.f);
                 if (co < a.CoA) {
-                    uint16_t* p = a.outA + m * a.CoA + co;
+                    uint16_t* p = a.outA + (int64_t)m * a.CoA + co;
                     if (a.accumA) v += bf2f(*p);
                     *p = f2bf(v);
                 } else {
-                    a.outB[m * CoB + (co - a.CoA)] = f2bf(v);
+                    a.outB[(int64_t)m * CoB + (co - a.CoA)] = f2bf(v);
                 }
             }
         }
@@ -577,7 +582,7 @@ int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
     const int64_t M = (int64_t)a.N * a.H * a.W;
     if (a.Cin <= 0 || a.Cin % 4 || a.Ca % 4 || a.Cb % 4 || a.Kpad % 16 || a.K > a.Kpad ||
-        a.Cout % 16 || a.CoA > a.Cout || a.CoA < 0 || M <= 0 ||
+        a.Cout % 16 || a.CoA > a.Cout || a.CoA < 0 || M <= 0 || M > kConvMaxPixels ||
         (a.b_half && (a.H % 2 || a.W % 2)))
         return hipErrorInvalidValue;
     const dim3 grid(blocks_for(M, 64 * (kConvThreads / kWave))), block(kConvThreads);
