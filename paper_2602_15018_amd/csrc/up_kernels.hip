@@ -51,13 +51,13 @@ struct Src {
 // One element (channel c) of the concatenated input at (n, yy, xx).
 __device__ __forceinline__ short load1(const Src& s, int n, int yy, int xx, int c) {
     if (yy < 0 || yy >= s.H || xx < 0 || xx >= s.W) return 0;
-    if (c < s.Ca) return (short)s.A[(((int64_t)n * s.H + yy) * s.W + xx) * s.Ca + c];
+    if (c < s.Ca) return (short)s.A[(int64_t)((n * s.H + yy) * s.W + xx) * s.Ca + c];
     const int cb = c - s.Ca;
     if (s.b_half) {
         const int Hh = s.H >> 1, Wh = s.W >> 1;
-        return (short)s.B[(((int64_t)n * Hh + (yy >> 1)) * Wh + (xx >> 1)) * s.Cb + cb];
+        return (short)s.B[(int64_t)((n * Hh + (yy >> 1)) * Wh + (xx >> 1)) * s.Cb + cb];
     }
-    return (short)s.B[(((int64_t)n * s.H + yy) * s.W + xx) * s.Cb + cb];
+    return (short)s.B[(int64_t)((n * s.H + yy) * s.W + xx) * s.Cb + cb];
 }
 
 // MFMA 16x16x16 operand layout (per lane l, 4 elements e):
@@ -208,12 +208,14 @@ __global__ __launch_bounds__(kWgradThreads) void wgrad_kernel(const WgradArgs a)
     const int lane = threadIdx.x & (kWave - 1);
     const int wv = threadIdx.x / kWave;
     const int r16 = lane & 15, g4 = lane >> 4;
-    const int64_t HW = (int64_t)a.H * a.W;
-    const int64_t M = (int64_t)a.N * HW;
+    // Pixel indices fit in 32 bits (the launcher rejects more than
+    // kConvMaxPixels pixels); element offsets are formed in 64 bits.
+    const int HW = a.H * a.W;
+    const int M = a.N * HW;
     const int kt = blockIdx.x;
     const int pb = blockIdx.y;
-    const int64_t p0 = (int64_t)pb * a.pix_per_block;
-    const int64_t p1 = p0 + a.pix_per_block < M ? p0 + a.pix_per_block : M;
+    const int p0 = pb * a.pix_per_block;
+    const int p1 = M - p0 > a.pix_per_block ? p0 + a.pix_per_block : M;
     const Src src{a.inA, a.inB, nullptr, a.Ca, a.Cb, a.H, a.W, a.b_half};
     const bool want_bias = kt == 0;
 
@@ -243,14 +245,14 @@ __global__ __launch_bounds__(kWgradThreads) void wgrad_kernel(const WgradArgs a)
     int pn[4], py[4], px[4];
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
-        const int64_t m = p0 + 16 * wv + 4 * g4 + e;
-        pn[e] = (int)(m / HW);
-        const int rem = (int)(m - (int64_t)pn[e] * HW);
+        const int m = p0 + 16 * wv + 4 * g4 + e;
+        pn[e] = m / HW;
+        const int rem = m - pn[e] * HW;
         py[e] = rem / a.W;
         px[e] = rem - py[e] * a.W;
     }
     const int sy = 64 / a.W, sx = 64 - sy * a.W;
-    for (int64_t m0 = p0 + 16 * wv; m0 < p1; m0 += 64) {
+    for (int m0 = p0 + 16 * wv; m0 < p1; m0 += 64) {
         bool pv[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) pv[e] = m0 + 4 * g4 + e < p1;
@@ -262,9 +264,9 @@ __global__ __launch_bounds__(kWgradThreads) void wgrad_kernel(const WgradArgs a)
             for (int e = 0; e < 4; ++e) {
                 short v = 0;
                 if (pv[e]) {
-                    const int64_t m = m0 + 4 * g4 + e;
-                    v = (short)a.dy[m * a.Cout + co];
-                    if (a.y && !bf_positive((short)a.y[m * a.Cout + co])) v = 0;
+                    const int64_t o = (int64_t)(m0 + 4 * g4 + e) * a.Cout + co;
+                    v = (short)a.dy[o];
+                    if (a.y && !bf_positive((short)a.y[o])) v = 0;
                 }
                 af[i][e] = v;
                 if (want_bias) bsum[i] += bf2f((uint16_t)v);
@@ -598,8 +600,10 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_wgrad(const WgradArgs& a, int n_pix_blocks, hipStream_t s) {
-    if (a.Cout % 16 || a.Cout > 64 || a.Kpad % 16 || a.K > a.Kpad ||
+    if (a.Cout % 16 || a.Cout > 64 || a.Kpad % 16 || a.K > a.Kpad || a.Cin <= 0 ||
         a.pix_per_block <= 0 || n_pix_blocks <= 0 ||
+        (int64_t)a.N * a.H * a.W > kConvMaxPixels ||
+        (int64_t)(n_pix_blocks - 1) * a.pix_per_block >= (int64_t)a.N * a.H * a.W ||
         (a.b_half && (a.H % 2 || a.W % 2)))
         return hipErrorInvalidValue;
     const dim3 grid((a.Kpad + kWgradKTile - 1) / kWgradKTile, n_pix_blocks);
