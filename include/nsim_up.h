@@ -48,7 +48,9 @@ extern "C" {
 typedef struct nsim_up nsim_up_t;
 
 typedef struct nsim_up_config {
-    int64_t max_pixels;   /* largest N*H*W of any call */
+    int64_t max_pixels;   /* largest N*H*W of any call, 16 to 2^30
+                             (else NSIM_UP_EINVAL); a call with more
+                             pixels fails with NSIM_UP_EINVAL */
     uint64_t seed;        /* weight initialisation (He-uniform, zero
                              biases, zero head) */
 } nsim_up_config;
