@@ -250,6 +250,84 @@ def test_fragile_flag_marks_near_level():
     assert (0, 1) in set(zip(pix.tolist(), frame.tolist()))
 
 
+def _exact_tau(t_prev, dt, level, L0, L1):
+    """Crossing time of the definition in exact rational arithmetic, from the
+    float32 samples (interpolation in log intensity between two frames)."""
+    from fractions import Fraction as Fr
+    L0, L1 = Fr(float(np.float32(L0))), Fr(float(np.float32(L1)))
+    return t_prev + (Fr(level) - L0) / (L1 - L0) * dt
+
+
+# Frame 1 (t = 1000) puts a pixel at L = 0.3 from 0: one up crossing of the
+# level 0.25 at tau = 833.33, emitted at 834.  Frame 2 (t = 1201) moves it to
+# L2: the crossing of the level 0.5 lands at tau2.  With L2 three float32
+# steps below 0.6, tau2 lies 6.7e-5 us above the integer 1134 (stamped
+# 1135); two steps above 0.6 it lies 6.7e-5 us below 1134 (stamped 1134);
+# with L2 = 0.55 it lies at 1160.8, far from any integer.
+_L2_NEAR = np.uint32(1058642327).view(np.float32)   # 0.59999984502...
+_L2_BELOW = np.uint32(1058642332).view(np.float32)  # 0.60000014305...
+_L2_FAR = np.float32(0.55)
+
+
+def _refractory_boundary_run(L2, tref):
+    fr = np.array([0.0, 0.3, L2], np.float32).reshape(3, 1, 1)
+    r = oracle.run(fr, [0, 1000, 1201], 0.25, 0.25, input_is_log=True,
+                   refractory_us=tref, want_fragile=True)
+    pix, frame = r["fragile"]
+    return r["events"], set(zip(pix.tolist(), frame.tolist()))
+
+
+@pytest.mark.parametrize("tref,gap", [(299, 2), (300, 1), (301, 0), (302, -1),
+                                      (303, -2)])
+def test_fragile_flag_marks_refractory_boundary(tref, gap):
+    """A crossing whose tau lies within 1e-3 us of an integer flags its frame
+    exactly when its stamp sits within 1 us of the refractory boundary
+    (|t - t_last - t_ref| <= 1); the level band plays no part here (both
+    samples stay >= 0.05 from every level)."""
+    import math
+    tau1 = _exact_tau(0, 1000, 0.25, 0.0, 0.3)
+    tau2 = _exact_tau(1000, 201, 0.5, 0.3, _L2_NEAR)
+    t1, t2 = math.ceil(tau1), math.ceil(tau2)
+    assert (t1, t2) == (834, 1135)
+    assert 0 < tau2 - 1134 < 1e-4          # within the band, above 1134
+    assert t2 - t1 - tref == gap
+    ev, fragile = _refractory_boundary_run(_L2_NEAR, tref)
+    # the refractory decision itself: emitted iff the gap is >= 0
+    want_t = [834, 1135] if gap >= 0 else [834]
+    np.testing.assert_array_equal(ev.t, want_t)
+    assert ((0, 2) in fragile) == (abs(gap) <= 1)
+    assert (0, 1) not in fragile             # first event: no boundary
+
+
+@pytest.mark.parametrize("tref,gap", [(298, 2), (299, 1), (300, 0), (301, -1),
+                                      (302, -2)])
+def test_fragile_flag_refractory_boundary_below_integer(tref, gap):
+    """The same with tau just below an integer: the band is the distance to
+    the nearest integer, on either side."""
+    import math
+    tau2 = _exact_tau(1000, 201, 0.5, 0.3, _L2_BELOW)
+    assert 0 < 1134 - tau2 < 1e-4 and math.ceil(tau2) == 1134
+    assert 1134 - 834 - tref == gap
+    ev, fragile = _refractory_boundary_run(_L2_BELOW, tref)
+    np.testing.assert_array_equal(ev.t, [834, 1134] if gap >= 0 else [834])
+    assert ((0, 2) in fragile) == (abs(gap) <= 1)
+
+
+def test_fragile_flag_ignores_boundary_far_from_integer():
+    """At the refractory boundary (gap 0) but with tau 0.2 us from the next
+    integer, no flag; nor without a refractory period at all."""
+    import math
+    tau2 = _exact_tau(1000, 201, 0.5, 0.3, _L2_FAR)
+    t2 = math.ceil(tau2)
+    assert abs(tau2 - round(tau2)) > 0.1
+    tref = t2 - 834
+    ev, fragile = _refractory_boundary_run(_L2_FAR, tref)
+    np.testing.assert_array_equal(ev.t, [834, t2])
+    assert (0, 2) not in fragile
+    ev, fragile = _refractory_boundary_run(_L2_NEAR, 0)
+    assert len(ev) == 2 and (0, 2) not in fragile
+
+
 # ------------------------------------------------------------------ brute force
 
 BRUTE_CASES = [

@@ -214,6 +214,41 @@ def test_l1_gradient_and_adam_first_step():
     np.testing.assert_allclose(p1["a"], want, rtol=1e-15)
 
 
+def _adam3(grads, lr=0.01):
+    p = {"a": np.array([1.0, 2.0, -3.0])}
+    m = {"a": np.zeros(3)}
+    v = {"a": np.zeros(3)}
+    for step, g in enumerate(grads, start=1):
+        p, m, v = unet.adam_step(p, {"a": g}, m, v, step, lr=lr)
+    return p["a"], m["a"], v["a"]
+
+
+def test_adam_three_steps_constant_gradient():
+    """With the same gradient at every step the bias-corrected moments are
+    exactly g and g^2 at every step (m_t = g (1 - b1^t), v_t = g^2 (1 - b2^t)),
+    so three steps move each parameter by 3 lr g / (|g| + eps).  A wrong decay
+    rate or bias-correction exponent breaks the cancellation from step 2 on."""
+    g = np.array([0.5, -4.0, 1e-3])
+    p3, m3, v3 = _adam3([g, g, g])
+    np.testing.assert_allclose(m3, g * (1 - 0.9 ** 3), rtol=1e-14)
+    np.testing.assert_allclose(v3, g * g * (1 - 0.999 ** 3), rtol=1e-14)
+    want = np.array([1.0, 2.0, -3.0]) - 3 * 0.01 * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(p3, want, rtol=1e-13)
+
+
+def test_adam_three_steps_alternating_gradient():
+    """Gradients g, -g, g worked by hand: m_1 = 0.1 g, m_2 = -0.01 g,
+    m_3 = 0.091 g, so the bias-corrected first moments are g, -g/19 and
+    (91/271) g; v_t = g^2 (1 - b2^t) so every corrected second moment is g^2.
+    The parameter moves by -lr (1 - 1/19 + 91/271) g / (|g| + eps)."""
+    g = np.array([0.5, -4.0, 2.0])
+    p3, m3, v3 = _adam3([g, -g, g])
+    np.testing.assert_allclose(m3, 0.091 * g, rtol=1e-13)
+    steps = 1.0 - 1.0 / 19.0 + 91.0 / 271.0
+    want = np.array([1.0, 2.0, -3.0]) - 0.01 * steps * g / (np.abs(g) + 1e-8)
+    np.testing.assert_allclose(p3, want, rtol=1e-12)
+
+
 def test_bf16_rounding_points():
     vals = np.array([1.0, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -9,
                      -2.5, 3.0e38, 1e-40])
