@@ -47,12 +47,28 @@ extern "C" {
 #define NSIM_ENOMEM (-2)    /* device or host allocation failed */
 #define NSIM_EOVERFLOW (-3) /* a step's events did not fit; see nsim_ev_step */
 #define NSIM_EHIP (-4)      /* a HIP runtime call failed */
-#define NSIM_ESTATE (-5)    /* handle unusable (internal error) */
+#define NSIM_ESTATE (-5)    /* a step was not committed: internal error, or
+                               input outside the supported range */
 
 /* config.flags */
 #define NSIM_INPUT_LOG 0x1u  /* frames hold log intensity L, not I */
 #define NSIM_FORCE_FP64 0x2u /* verification mode: evaluate every candidate
                                 crossing in FP64 (same results, slower) */
+#define NSIM_ATOMIC_EMIT 0x4u /* single streams: the paper's kernel design
+                                (Sec. 2, kernel paragraph) instead of the
+                                ordered path: one launch per frame, one lane
+                                per pixel, one atomic per wave reserving its
+                                events' slots; the same events, then radix
+                                passes over (time, pixel) keys restore the
+                                output order.  Frame gaps must fit
+                                32 - ceil(log2(padded pixels)) bits */
+#define NSIM_ATOMIC_UNSORTED 0x8u /* with NSIM_ATOMIC_EMIT: no sort; the
+                                    queue holds each step's events in the
+                                    order the waves reserved them (not
+                                    deterministic) */
+#define NSIM_DIRECT_LAUNCH 0x10u /* single streams: launch every kernel
+                                    directly; by default launches of one or
+                                    two frames replay a captured HIP graph */
 
 typedef struct nsim_ev_config {
     int32_t width;   /* 1 .. 65535 */
@@ -66,7 +82,9 @@ typedef struct nsim_ev_config {
     int64_t refractory_us;   /* 0 disables; at most 2^30 */
     int64_t capacity_events; /* events the queue holds until drained; also
                                 the most one internal launch may produce */
-    uint32_t flags;          /* NSIM_INPUT_LOG | NSIM_FORCE_FP64 */
+    uint32_t flags;          /* NSIM_INPUT_LOG | NSIM_FORCE_FP64 |
+                                NSIM_DIRECT_LAUNCH | NSIM_ATOMIC_EMIT |
+                                NSIM_ATOMIC_UNSORTED */
     int32_t max_frames_per_launch; /* 0 = automatic (up to 128 frames while
                                       the launch spans at most 65535 us);
                                       else 1 .. 256 */
@@ -90,7 +108,12 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out);
  * All-or-nothing: if a step's events would overflow the queue, its state is
  * not committed, this and every later step become no-ops, and the next
  * nsim_ev_sync / nsim_ev_drain reports NSIM_EOVERFLOW once; the caller then
- * drains and re-issues frames after nsim_ev_committed_time(). */
+ * drains and re-issues frames after nsim_ev_committed_time().
+ * Range: a pixel may cross at most 2^20 - 1 levels in one frame interval,
+ * and its crossing counters (levels crossed up, and down, since the stream
+ * started) may not pass 2^30.  Input beyond either limit is not truncated:
+ * the step is not committed (as above) and the next sync / drain reports
+ * NSIM_ESTATE once, with a message naming the limit. */
 int nsim_ev_step(nsim_ev_t* h, const float* frames, const int64_t* t_us,
                  int32_t K);
 
@@ -276,6 +299,16 @@ int nsim_evb_get_tuning(nsim_evb_t* h, nsim_evb_tuning* out);
  * (graph replay). */
 int nsim_evb_set_profiling(nsim_evb_t* h, int on);
 int nsim_evb_get_stats(nsim_evb_t* h, nsim_ev_stats* out);
+
+/* Diagnostic: stream `bytes` (a multiple of 16; both pointers 16-byte
+ * aligned device memory) through HBM with the non-temporal 16-byte accesses
+ * the step kernel reads frames with.  mode 0 copies src to dst; mode 1 only
+ * reads src (dst may be NULL and is practically never written).  Its
+ * duration is the measured bandwidth ceiling quoted beside the step
+ * kernel's, and its known byte count calibrates profiler traffic counters.
+ * Enqueued on `stream`; returns NSIM_EINVAL for bad sizes or alignment. */
+int nsim_diag_stream(const void* src, void* dst, int64_t bytes, int32_t mode,
+                     void* stream);
 
 /* Diagnostic: out[i] = the step kernel's FP32 base-2 logarithm of x[i]
  * (device arrays of n floats), so its error bound can be checked. */

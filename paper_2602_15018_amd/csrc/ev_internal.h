@@ -15,6 +15,10 @@ constexpr int kStepLdsEntries = 2048;        // staging slots per wave: single s
                                               // take 32 per frame of a launch, at least this
 constexpr int kStepMaxLdsEntries = 1 << 20;  // (4 B each, global memory)
 constexpr int kScanTile = 1024;              // per-wave counts per scan block
+// status words of the scan for n waves: one per tile plus the tile counter
+constexpr int64_t scan_words(int64_t nwaves) {
+    return (nwaves + kScanTile - 1) / kScanTile + 1;
+}
 constexpr int kMaxEnvs = 4096;
 constexpr int kChunk = 8;                     // frames prefetched per chunk
 constexpr int kMaxFramesPerLaunch = 256;
@@ -27,6 +31,8 @@ constexpr int kDigits = 1 << kDigitBits;
 constexpr int kMaxPasses = 4;
 constexpr int32_t kTlastNone = -(1 << 30);   // no emitted event that matters
 constexpr int64_t kMaxLaunchSpan = (int64_t(1) << 25) - 2;  // us per launch
+constexpr int32_t kErrWait = 1;              // Header::internal_err bits
+constexpr int32_t kErrRange = 2;
 
 // One environment of a batch: its pixels occupy waves [wave0, wave0 +
 // ceil(npix / 64)) of the padded pixel space (state arrays are indexed by
@@ -52,7 +58,9 @@ struct alignas(64) Header {
     int64_t dropped_t;    // first frame time of the first dropped step
     int64_t events_total; // committed events
     int64_t fp64_evals;   // candidate crossings evaluated in FP64
-    int32_t internal_err; // 1: a bounded wait gave up
+    int32_t internal_err; // kErrWait: a bounded wait gave up; kErrRange: a
+                          // pixel reached kMaxCross crossings in one frame
+                          // interval or a lattice counter passed 2^30
     int32_t stage_full;   // 1: the staging pool could not hold a launch
     int64_t alloc;        // packed-event slots handed out in this launch
     // diagnostic counters (summed over launches; filled only in builds with
@@ -102,19 +110,24 @@ struct StepArgs {
     uint32_t* seg_slots;   // [nwaves] staging slots used (holes included)
     Header* hdr;
     uint32_t flags;
-    uint32_t pad1;
+    int32_t scan_words;    // status words of the scan (cleared by block 0)
+    uint64_t* scan_status;
     int32_t toff[kMaxFramesPerLaunch];  // frame k time minus T0
 };
 
-// Exclusive scan of the per-wave event counts (wave order = pixel order),
-// in blocks of kScanTile counts: block sums first, then every block adds the
-// sums of the blocks before it.
+// Exclusive scan of the per-wave event counts (wave order = pixel order) in
+// one pass: tiles of kScanTile counts taken in the order workgroups start
+// (dynamic tile ids), each publishing its sum and then its inclusive prefix
+// in a status word that later tiles look back on (decoupled look-back).
+// status: [ceil(nwaves / kScanTile)] words (flag << 62 | value), then one
+// word whose low half counts the tiles handed out; all zero at launch (the
+// step kernel clears them).
 struct ScanArgs {
     const uint32_t* seg_count;
     uint32_t* pref;
     int32_t nwaves;
     int32_t restart_queue; // 1: this step's output starts the queue afresh
-    uint64_t* tile_sum;    // [ceil(nwaves / kScanTile)]
+    uint64_t* status;
     Header* hdr;
 };
 
@@ -175,7 +188,8 @@ struct PassArgs {
     int32_t bits;
     int32_t key_tbits;
     int32_t n_env;           // entries of envs (keys naming others are refused)
-    int32_t pad;
+    int32_t key_pbits;       // 0: key = env << key_tbits | t_off; else (atomic
+                             // path) key = t_off << key_pbits | pixel
     const EnvRec* envs;
     int64_t T0;
     const uint32_t* hist;    // this pass's digit counts
@@ -183,6 +197,42 @@ struct PassArgs {
     uint32_t* tile_ctr;
     Header* hdr;
     int64_t scratch_cap;
+};
+
+// The paper's kernel design (Sec. 2, kernel paragraph), kept as an A/B of
+// the ordered path: one frame per launch, one lane per pixel, each wave
+// reserving its events' slots with one atomic on the step's event count.
+// Sorted: entries (key = t_off << pbits | pixel, value = pixel << 1 | p) go
+// to dense arrays with the digit counts of every radix pass, and the passes
+// restore (t, y, x) order; unsorted: SoA events go straight into the queue
+// ring in whatever order the waves reserved.
+struct AtomicArgs {
+    StepArgs s;            // frames, state, thresholds, times (K = 1)
+    int32_t sorted;
+    int32_t pbits;         // bits of the padded pixel index
+    int32_t npass;         // radix passes over the combined key
+    int32_t width;         // single stream
+    uint32_t* dkey;        // sorted: [scap]
+    uint32_t* dval;
+    uint32_t* hist;        // [kMaxPasses][kDigits]
+    int64_t scap;
+    int64_t* q_t;          // unsorted: the queue ring
+    uint16_t* q_x;
+    uint16_t* q_y;
+    int8_t* q_p;
+    int64_t qcap;
+};
+
+// Sorted atomic path: clears the look-back words of the tiles the step's
+// event count needs and the passes' tile counters.
+struct PrepArgs {
+    Header* hdr;
+    uint32_t* status;      // [kMaxPasses][max_tiles][kDigits]
+    int64_t max_tiles;
+    uint32_t* pass_ctr;
+    int32_t npass;
+    int64_t scratch_cap;
+    int64_t qcap;
 };
 
 struct CommitArgs {
@@ -219,10 +269,15 @@ hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, hipStream_t s);
 hipError_t launch_commit(const CommitArgs& a, hipStream_t s);
+hipError_t launch_atomic_step(const AtomicArgs& a, bool log_input, bool has_map,
+                              hipStream_t s);
+hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
 hipError_t launch_reset_header(Header* hdr, uint32_t* hist, hipStream_t s);
 hipError_t launch_clear_status(Header* hdr, hipStream_t s);
 hipError_t launch_state_copy(const StateCopyArgs& a, hipStream_t s);
 hipError_t launch_fast_log2(const float* x, float* out, int64_t n,
                             hipStream_t s);
+hipError_t launch_stream(const void* src, void* dst, int64_t words, int mode,
+                         int n_cu, hipStream_t s);
 
 }  // namespace nsim

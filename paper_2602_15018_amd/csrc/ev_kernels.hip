@@ -44,7 +44,9 @@ namespace nsim {
 namespace {
 
 constexpr int kFastMaxCross = 32;        // longer runs per frame: FP64 replica
-constexpr int kMaxCross = 1 << 20;       // termination bound (finite input)
+constexpr int kMaxCross = 1 << 20;       // crossings per pixel and frame
+                                         // interval: reaching it is an error
+constexpr int kMaxCounter = 1 << 30;     // lattice counters after a launch
 constexpr uint32_t kSpinLimit = 1u << 24;
 constexpr uint32_t kAgg = 1u, kInc = 2u;
 constexpr int kLookBack = 8;   // predecessor tiles read per look-back step
@@ -482,7 +484,8 @@ __device__ __forceinline__ int wave_max_small(int v) {
 template <bool LOGIN>
 __device__ __forceinline__ void count_frame(const Px& q, float I, float Ip,
                                             bool cand, bool force64, double eps,
-                                            int& n, bool& up, bool& f64, int* dg) {
+                                            int& n, bool& up, bool& f64, int& bad,
+                                            int* dg) {
     // one crossing for sure: up: Bhi <= I <= Chi, down: Clo <= I <= Blo
     up = I > q.Ahi;
     const float lo = up ? q.Bhi : q.Clo;
@@ -524,6 +527,12 @@ __device__ __forceinline__ void count_frame(const Px& q, float I, float Ip,
             const Count64 c = count64(q.L_init, q.nup, q.ndn, q.cp, q.cn, lp.L1);
             n = c.n;
             up = c.up != 0;
+            if (n >= kMaxCross) {
+                // outside the supported range: the launch will not commit,
+                // so this lane emits nothing more (the caller stops it)
+                bad = 1;
+                n = 0;
+            }
         }
     }
 }
@@ -824,7 +833,7 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
                                            const int* s_toff, uint32_t* out,
                                            int64_t cap, int64_t& slots,
                                            bool& over, int& emitted,
-                                           int& f64count, int* dg) {
+                                           int& f64count, int& bad, int* dg) {
     const double eps = a.log_eps;
     const bool force64 = (a.flags & 0x2u) != 0;
     const int64_t P = a.frame_stride;
@@ -875,8 +884,14 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
                 const float Ip = u > 0 ? fslab[(u - 1) * kWave + lane] : prev0;
                 int n;
                 bool up, f64;
-                count_frame<LOGIN>(q, I, Ip, go, force64, eps, n, up, f64, dg);
+                count_frame<LOGIN>(q, I, Ip, go, force64, eps, n, up, f64, bad, dg);
                 if (go) cm &= ~((2u << u) - 1u);
+                if (bad) {
+                    // a lane past the supported range takes no further part
+                    q.Ahi = __builtin_inff();
+                    q.Alo = -__builtin_inff();
+                    cm = 0u;
+                }
                 if (n > 0) {
                     if (rcount == 0) {
                         nup0 = q.nup;
@@ -990,14 +1005,21 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
     int tlast = q.tlast;
 
     TILE_STAMP(1);
-    int emitted = 0, f64count = 0;
+    int emitted = 0, f64count = 0, bad = 0;
     int64_t slots = 0;
     bool over = false;
     int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     const int64_t S = a.stage_entries;
     walk_split<LOGIN, ONE>(a, q, tlast, valid, fr, tin.I0, recs, idx, fslab,
                            s_toff, a.out_key + (int64_t)wid * S, S, slots, over,
-                           emitted, f64count, dg);
+                           emitted, f64count, bad, dg);
+    // A launch adds fewer than 256 * kMaxCross = 2^28 to a counter, so a
+    // counter that starts at most kMaxCounter (2^30) cannot wrap in int32.
+    if (q.nup > kMaxCounter || q.ndn > kMaxCounter) bad = 1;
+    if (__ballot(bad != 0)) {
+        if (lane == 0) atomicOr(&hdr->internal_err, kErrRange);
+        return;
+    }
     dg[2] = over ? 1 : 0;
     TILE_STAMP(2);
 
@@ -1063,13 +1085,13 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int wid, int cur,
                               MAP ? a.c_neg_map : nullptr, a.c_pos, a.c_neg, pix,
                               valid, a.log_eps);
         tlast = q.tlast;
-        int e2 = 0, f2 = 0;
+        int e2 = 0, f2 = 0, b2 = 0;
         int64_t s2 = 0;
         bool o2 = false;
         int dg2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
         walk_split<LOGIN, ONE>(a, q, tlast, valid, fr, tin.I0, recs, idx, fslab,
                                s_toff, a.out_key + base, slots, s2, o2, e2, f2,
-                               dg2);
+                               b2, dg2);
     }
     TILE_STAMP(4);
 #ifdef NSIM_TILE_TRACE
@@ -1100,6 +1122,9 @@ __attribute__((amdgpu_waves_per_eu(4))) void step_kernel(const StepArgs a) {
     __shared__ int s_toff[kMaxFramesPerLaunch];
     const int wpb = blockDim.x / kWave;
     const int w = threadIdx.x / kWave;
+    // the scan that follows starts from cleared status words
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < a.scan_words; i += blockDim.x) a.scan_status[i] = 0ull;
     if (a.hdr->status != 0) return;
     for (int i = threadIdx.x; i < a.K; i += blockDim.x) s_toff[i] = a.toff[i];
     __syncthreads();
@@ -1126,47 +1151,70 @@ __attribute__((amdgpu_waves_per_eu(4))) void step_kernel(const StepArgs a) {
     }
 }
 
-// Exclusive scan of the per-wave counts in wave (= pixel) order, two
-// kernels over blocks of kScanTile counts.  scan_sum_kernel: one block sum
-// per tile.  scan_down_kernel: each block adds up the sums of the tiles
-// before it (a few thousand at most, read from L2), scans its own counts
-// with wave scans, and the last block publishes the step's total.
-__device__ __forceinline__ uint64_t block_sum64(uint64_t v, uint64_t* s_w) {
-    const int lane = lane_id(), w = threadIdx.x / kWave;
-    v = (uint64_t)wave_sum64((int64_t)v);
-    if (lane == 0) s_w[w] = v;
-    __syncthreads();
-    uint64_t t = 0;
-    for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += s_w[i];
-    __syncthreads();
-    return t;
-}
+// Exclusive scan of the per-wave counts in wave (= pixel) order, in one
+// pass (decoupled look-back, Merrill & Garland): each workgroup takes the
+// next tile id, scans its kScanTile counts with wave scans, publishes the
+// tile's sum (flag AGG) -- or, for tile 0, its inclusive prefix (flag INC)
+// -- then its first thread walks back over the predecessors' words, adding
+// sums until it meets an inclusive prefix, and publishes its own.  Tiles
+// are handed out in start order, so every predecessor is already running
+// and each wait ends; a bounded spin turns a lost wait into an error.
+constexpr uint64_t kScanAgg = 1ull << 62, kScanInc = 2ull << 62;
+constexpr uint64_t kScanVal = (1ull << 62) - 1ull;
 
-__global__ __launch_bounds__(kScanTile) void scan_sum_kernel(const ScanArgs a) {
+__global__ __launch_bounds__(kScanTile) void scan_kernel(const ScanArgs a) {
+    __shared__ uint32_t s_tile;
     __shared__ uint64_t s_w[kScanTile / kWave];
-    const int64_t i = (int64_t)blockIdx.x * kScanTile + threadIdx.x;
-    const uint64_t c = i < a.nwaves ? a.seg_count[i] : 0u;
-    const uint64_t t = block_sum64(c, s_w);
-    if (threadIdx.x == 0) a.tile_sum[blockIdx.x] = t;
-}
-
-__global__ __launch_bounds__(kScanTile) void scan_down_kernel(const ScanArgs a) {
-    __shared__ uint64_t s_w[kScanTile / kWave];
-    __shared__ uint64_t s_scan[kScanTile / kWave];
+    __shared__ uint64_t s_excl;
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-    uint64_t before = 0;
-    for (int64_t j = tid; j < blockIdx.x; j += kScanTile) before += a.tile_sum[j];
-    const uint64_t base = block_sum64(before, s_w);
-    const int64_t i = (int64_t)blockIdx.x * kScanTile + tid;
+    const int64_t ntiles = (a.nwaves + kScanTile - 1) / kScanTile;
+    uint32_t* ctr = reinterpret_cast<uint32_t*>(a.status + ntiles);
+    if (tid == 0) s_tile = atomicAdd(ctr, 1u);
+    __syncthreads();
+    const int64_t tile = s_tile;
+    if (tile >= ntiles) return;
+    const int64_t i = tile * kScanTile + tid;
     const uint32_t c = i < a.nwaves ? a.seg_count[i] : 0u;
     const uint64_t incl = wave_incl_scan_u64(c);
-    if (lane == kWave - 1) s_scan[w] = incl;
+    if (lane == kWave - 1) s_w[w] = incl;
     __syncthreads();
-    uint64_t off = base;
-    for (int k = 0; k < w; ++k) off += s_scan[k];
-    const uint64_t ex = off + (incl - c);
+    uint64_t before_w = 0, total = 0;
+    for (int k = 0; k < kScanTile / kWave; ++k) {
+        if (k < w) before_w += s_w[k];
+        total += s_w[k];
+    }
+    if (tid == 0) {
+        uint64_t* st = a.status + tile;
+        uint64_t excl = 0;
+        if (tile == 0) {
+            atomic_store_u64(st, kScanInc | total);
+        } else {
+            atomic_store_u64(st, kScanAgg | total);
+            int64_t j = tile - 1;
+            uint32_t spins = 0;
+            for (;;) {
+                const uint64_t v = atomic_load_u64(a.status + j);
+                const uint64_t flag = v & ~kScanVal;
+                if (flag == 0) {
+                    if (++spins > kSpinLimit) {
+                        atomicOr(&a.hdr->internal_err, kErrWait);
+                        break;
+                    }
+                    __builtin_amdgcn_s_sleep(1);
+                    continue;
+                }
+                excl += v & kScanVal;
+                if (flag == kScanInc) break;
+                --j;
+            }
+            atomic_store_u64(st, kScanInc | (excl + total));
+        }
+        s_excl = excl;
+    }
+    __syncthreads();
+    const uint64_t ex = s_excl + before_w + (incl - c);
     if (i < a.nwaves) a.pref[i] = (uint32_t)(ex < 0xFFFFFFFFull ? ex : 0xFFFFFFFFull);
-    if (blockIdx.x == gridDim.x - 1 && tid == kScanTile - 1) {
+    if (tile == ntiles - 1 && tid == kScanTile - 1) {
         a.hdr->n_step = (int64_t)(ex + c);
         if (a.restart_queue) {
             a.hdr->head = 0;
@@ -1408,7 +1456,7 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
                     j -= adv;
                     if (adv < kLookBack) {   // predecessor j not published yet
                         if (++spins > kSpinLimit) {
-                            atomicExch(&a.hdr->internal_err, 1);
+                            atomicOr(&a.hdr->internal_err, kErrWait);
                             break;
                         }
                         __builtin_amdgcn_s_sleep(1);
@@ -1455,14 +1503,14 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
             bool bad = false;
 #pragma unroll
             for (int i = 0; i < kSortItems; ++i) {
-                const uint32_t env = sk[i] >> a.key_tbits;
+                const uint32_t env = a.key_pbits ? 0u : (sk[i] >> a.key_tbits);
                 const bool v = tid + i * kSortThreads < cnt;
                 const bool ok = env < (uint32_t)a.n_env;
                 bad = bad || (v && !ok);
                 ew0[i] = (v && ok) ? (uint32_t)a.envs[env].wave0 : 0xFFFFFFFFu;
                 ewd[i] = (v && ok) ? (uint32_t)a.envs[env].width : 1u;
             }
-            if (bad) atomicExch(&a.hdr->internal_err, 1);
+            if (bad) atomicOr(&a.hdr->internal_err, kErrWait);
 #pragma unroll
             for (int i = 0; i < kSortItems; ++i) {
                 const int64_t gpos = dest(i);
@@ -1470,7 +1518,8 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
                 if (ew0[i] == 0xFFFFFFFFu) continue;  // corrupt key
                 int64_t r = tailm + gpos;
                 if (r >= a.qcap) r -= a.qcap;
-                const uint32_t toff = sk[i] & ((1u << a.key_tbits) - 1u);
+                const uint32_t toff = a.key_pbits ? (sk[i] >> a.key_pbits)
+                                                  : (sk[i] & ((1u << a.key_tbits) - 1u));
                 const uint32_t px = (sv[i] >> 1) - ew0[i] * kWave;
                 // px < 2^32 and width <= 65535: the FP64 quotient's floor is
                 // the integer quotient (its distance to the next integer,
@@ -1492,6 +1541,175 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
             }
         }
         __syncthreads();
+    }
+}
+
+// ---- the paper's kernel design, as an A/B -------------------------------
+//
+// One launch per frame; every lane takes one pixel: it decides its
+// crossings, their timestamps and the refractory filter with the same
+// arithmetic as the ordered path (so both give the same event set), then
+// the wave reserves a contiguous block for all its events with one atomic
+// on the step's event count: when no lane has more than one event the
+// offsets are the ballot mask's prefix counts (mbcnt), otherwise a wave
+// scan.  The order of the blocks is the order in which waves reach the
+// atomic.
+template <bool LOGIN, bool MAP>
+__global__ __launch_bounds__(256) void atomic_step_kernel(const AtomicArgs aa) {
+    const StepArgs& a = aa.s;
+    __shared__ int s_toff[1];
+    __shared__ uint32_t s_h[kMaxPasses * kDigits];
+    Header* hdr = a.hdr;
+    if (hdr->status != 0) return;
+    if (threadIdx.x == 0) s_toff[0] = a.toff[0];
+    if (aa.sorted)
+        for (int i = threadIdx.x; i < aa.npass * kDigits; i += blockDim.x) s_h[i] = 0u;
+    __syncthreads();
+    const int lane = lane_id();
+    const int wid = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+    const int cur = hdr->cur;
+    const int64_t tail = hdr->tail, head = hdr->head;
+    if (wid < a.nwaves) {
+        const int pix = wid * kWave + lane;
+        const EnvRec er = a.envs[a.wave_env[wid]];
+        const int local = (wid - er.wave0) * kWave + lane;
+        const bool valid = local < er.npix;
+        Px q;
+        load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
+                          MAP ? a.c_pos_map : nullptr, MAP ? a.c_neg_map : nullptr,
+                          a.c_pos, a.c_neg, pix, valid, a.log_eps);
+        const float I = valid ? __builtin_nontemporal_load(a.frames + er.frame_off + local)
+                              : 1.0f;
+        const float Ip = q.prev;
+        const bool force64 = (a.flags & 0x2u) != 0;
+        const bool cand = valid && ((I > q.Ahi) | (I < q.Alo));
+        int n = 0, bad = 0;
+        bool up = false, f64 = false;
+        int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        count_frame<LOGIN>(q, I, Ip, cand, force64, a.log_eps, n, up, f64, bad, dg);
+
+        // timestamps of the crossings (relative to T0) in order, refractory
+        TsSetup ts{};
+        if (n > 0 && !f64) {
+            Rec rc;
+            rc.meta = (uint32_t)n | (up ? (1u << 29) : 0u);
+            const double X1 = up ? q.Xh : q.Xl;
+            rc.w0 = __float_as_uint(I);
+            rc.w1 = __float_as_uint(Ip);
+            rc.w2 = (uint32_t)__double2loint(X1);
+            rc.w3 = (uint32_t)__double2hiint(X1);
+            ts = ts_setup<LOGIN>(a, rc, up ? q.cp : -q.cn, s_toff);
+        } else {
+            ts.tp = 0;
+            ts.dt = s_toff[0];
+        }
+        double L0d = 0.0, L1d = 0.0;
+        bool have_d = false;
+        int f64count = 0;
+        auto time_of = [&](int j) -> int {
+            int tt = 0;
+            if (!f64 && ts_fast(ts, j, tt)) return tt;
+            if (!have_d) {
+                const LogPair lp = log_pair64<LOGIN>(Ip, I, a.log_eps);
+                L0d = lp.L0;
+                L1d = lp.L1;
+                have_d = true;
+            }
+            ++f64count;
+            return time64(q.L_init, q.nup, q.ndn, q.cp, q.cn, up ? 1 : 0, j, L0d,
+                          L1d, a.T0, ts.tp, ts.dt);
+        };
+        // first pass: how many crossings survive the refractory filter
+        int e = 0;
+        int tl = q.tlast;
+        for (int j = 0; j < n; ++j) {
+            const int tt = time_of(j);
+            if (tt - tl >= a.tref) {
+                tl = tt;
+                ++e;
+            }
+        }
+        // one atomic per wave
+        const uint64_t lt = lanemask_lt();
+        int excl, total;
+        if (__ballot(e > 1) == 0ull) {
+            const uint64_t m = __ballot(e == 1);
+            excl = __popcll(m & lt);
+            total = __popcll(m);
+        } else {
+            const int incl = wave_incl_scan(e);
+            excl = incl - e;
+            total = wave_last(incl);
+        }
+        uint64_t base = 0;
+        if (total > 0) {
+            if (lane == 0)
+                base = atomicAdd((unsigned long long*)&hdr->n_step,
+                                 (unsigned long long)total);
+            base = __shfl(base, 0, kWave);
+        }
+        // second pass: the same times again, written out
+        const int64_t room = aa.sorted ? aa.scap : aa.qcap - (tail - head);
+        int64_t pos = (int64_t)base + excl;
+        tl = q.tlast;
+        const uint32_t y = valid ? (uint32_t)(local / aa.width) : 0u;
+        const uint32_t x = valid ? (uint32_t)(local - (int)y * aa.width) : 0u;
+        for (int j = 0; j < n; ++j) {
+            const int tt = time_of(j);
+            if (tt - tl < a.tref) continue;
+            tl = tt;
+            if (pos < room) {
+                if (aa.sorted) {
+                    const uint32_t key = ((uint32_t)tt << aa.pbits) | (uint32_t)pix;
+                    aa.dkey[pos] = key;
+                    aa.dval[pos] = ((uint32_t)pix << 1) | (up ? 1u : 0u);
+                    for (int p = 0; p < aa.npass; ++p)
+                        atomicAdd(&s_h[p * kDigits + ((key >> (kDigitBits * p)) & (kDigits - 1))],
+                                  1u);
+                } else {
+                    int64_t r = (tail + pos) % aa.qcap;
+                    aa.q_t[r] = a.T0 + (int64_t)tt;
+                    aa.q_x[r] = (uint16_t)x;
+                    aa.q_y[r] = (uint16_t)y;
+                    aa.q_p[r] = up ? (int8_t)1 : (int8_t)-1;
+                }
+            }
+            ++pos;
+        }
+        // commit-candidate state
+        if (valid) {
+            const int nxt = cur ^ 1;
+            a.nud[nxt][pix] = make_int2(q.nup + (up ? n : 0), q.ndn + (up ? 0 : n));
+            a.prev[nxt][pix] = I;
+            const int last = s_toff[0];
+            int tln = kTlastNone;
+            if (tl != kTlastNone && tl - last >= -a.tref) tln = tl - last;
+            a.tlast[nxt][pix] = tln;
+        }
+        if (q.nup + n > kMaxCounter || q.ndn + n > kMaxCounter) bad = 1;
+        if (__ballot(bad != 0) && lane == 0) atomicOr(&hdr->internal_err, kErrRange);
+        const int wf64 = wave_sum(f64count + (f64 ? 1 : 0));
+        if (wf64 && lane == 0)
+            atomicAdd((unsigned long long*)&hdr->fp64_evals, (unsigned long long)wf64);
+    }
+    if (aa.sorted) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < aa.npass * kDigits; i += blockDim.x)
+            if (s_h[i]) atomicAdd(&aa.hist[i], s_h[i]);
+    }
+}
+
+__global__ void prep_kernel(const PrepArgs a) {
+    int64_t n;
+    const bool ok = step_fits(a.hdr, a.scratch_cap, a.qcap, &n);
+    if (blockIdx.x == 0 && threadIdx.x < kMaxPasses) a.pass_ctr[threadIdx.x] = 0u;
+    if (!ok || n == 0) return;
+    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (int p = 0; p < a.npass; ++p) {
+        uint32_t* st = a.status + (int64_t)p * a.max_tiles * kDigits;
+        for (int64_t i = gid; i < ntiles * kDigits; i += gsz) st[i] = 0u;
     }
 }
 
@@ -1590,6 +1808,42 @@ __global__ void fast_log2_kernel(const float* x, float* out, int64_t n) {
     if (i < n) out[i] = fast_log2(x[i]);
 }
 
+// Reference streams over HBM: a copy, or a read-only pass, of n 16-byte
+// words with non-temporal accesses (as the step kernel reads its frames),
+// four words in flight per lane.  The read-only pass stores nothing unless
+// the words' XOR equals `never`, which keeps its loads alive.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+constexpr int kStreamUnroll = 4;
+
+template <bool COPY>
+__global__ __launch_bounds__(256) void stream_kernel(const u32x4* src, u32x4* dst,
+                                                     int64_t n, uint32_t never) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    u32x4 acc = {0u, 0u, 0u, 0u};
+    for (; i + (kStreamUnroll - 1) * stride < n; i += kStreamUnroll * stride) {
+        u32x4 v[kStreamUnroll];
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u)
+            v[u] = __builtin_nontemporal_load(src + i + u * stride);
+#pragma unroll
+        for (int u = 0; u < kStreamUnroll; ++u) {
+            if (COPY)
+                __builtin_nontemporal_store(v[u], dst + i + u * stride);
+            else
+                acc ^= v[u];
+        }
+    }
+    for (; i < n; i += stride) {
+        const u32x4 v = __builtin_nontemporal_load(src + i);
+        if (COPY)
+            __builtin_nontemporal_store(v, dst + i);
+        else
+            acc ^= v;
+    }
+    if (!COPY && (acc.x ^ acc.y ^ acc.z ^ acc.w) == never && dst) dst[0] = acc;
+}
+
 }  // namespace
 
 hipError_t launch_init(const InitArgs& a, hipStream_t s) {
@@ -1634,10 +1888,7 @@ hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
 
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
     const int tiles = (a.nwaves + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(scan_sum_kernel, dim3(tiles), dim3(kScanTile), 0, s, a);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(scan_down_kernel, dim3(tiles), dim3(kScanTile), 0, s, a);
+    hipLaunchKernelGGL(scan_kernel, dim3(tiles), dim3(kScanTile), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1660,6 +1911,32 @@ hipError_t launch_pass(const PassArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+hipError_t launch_atomic_step(const AtomicArgs& a, bool log_input, bool has_map,
+                              hipStream_t s) {
+    if (a.s.K != 1 || a.pbits < 1 || a.pbits > 31 || a.npass > kMaxPasses ||
+        a.width < 1)
+        return hipErrorInvalidValue;
+    const int blocks = (a.s.nwaves + 3) / 4;
+    const dim3 grid(blocks > 0 ? blocks : 1), block(256);
+    if (log_input) {
+        if (has_map)
+            hipLaunchKernelGGL((atomic_step_kernel<true, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((atomic_step_kernel<true, false>), grid, block, 0, s, a);
+    } else {
+        if (has_map)
+            hipLaunchKernelGGL((atomic_step_kernel<false, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((atomic_step_kernel<false, false>), grid, block, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const PrepArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(prep_kernel, dim3(256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_commit(const CommitArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(commit_kernel, dim3(1), dim3(256), 0, s, a);
     return hipGetLastError();
@@ -1672,6 +1949,22 @@ hipError_t launch_reset_header(Header* hdr, uint32_t* hist, hipStream_t s) {
 
 hipError_t launch_clear_status(Header* hdr, hipStream_t s) {
     hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(64), 0, s, hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_stream(const void* src, void* dst, int64_t words, int mode,
+                         int n_cu, hipStream_t s) {
+    const int blocks = 8 * (n_cu > 0 ? n_cu : 256);
+    const u32x4* in = static_cast<const u32x4*>(src);
+    u32x4* out = static_cast<u32x4*>(dst);
+    // (a value the XOR of the data practically never takes)
+    const uint32_t never = 0x9E3779B9u ^ (uint32_t)words;
+    if (mode == 0)
+        hipLaunchKernelGGL(stream_kernel<true>, dim3(blocks), dim3(256), 0, s, in, out,
+                           words, never);
+    else
+        hipLaunchKernelGGL(stream_kernel<false>, dim3(blocks), dim3(256), 0, s, in, out,
+                           words, never);
     return hipGetLastError();
 }
 

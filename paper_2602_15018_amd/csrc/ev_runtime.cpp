@@ -23,6 +23,7 @@ using nsim::Header;
 // nodes get new arguments.
 struct GraphSlot {
     int nbits = 0, stage = 0, wpb = 0, blocks = 0;
+    int one = 0;   // captured for a one-frame launch (its own step variant)
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipGraphNode_t n_step = nullptr, n_final = nullptr, n_commit = nullptr;
@@ -80,7 +81,7 @@ struct nsim_ev {
     uint32_t* seg_count = nullptr;
     uint32_t* seg_slots = nullptr;
     uint32_t* pref = nullptr;
-    uint64_t* tile_sum = nullptr;
+    uint64_t* scan_status = nullptr;         // scan look-back words
     int64_t stage_cap = 0;                    // fixed segments + pool
     int64_t* q_t = nullptr;
     uint16_t* q_x = nullptr;
@@ -111,9 +112,13 @@ struct nsim_evb {
     nsim_ev core;
 };
 
+
 namespace {
 
 const char* kNoHandle = "null handle";
+// single streams replay a captured graph for launches of at most this many
+// frames (latency-bound); longer launches are enqueued directly
+constexpr int32_t kGraphMaxFrames = 2;
 
 struct DeviceGuard {
     int prev = -1;
@@ -166,7 +171,7 @@ void free_all(nsim_ev* h) {
                     h->tlast[1], h->cpos_map, h->cneg_map, h->skey[0],
                     h->skey[1], h->sval[0], h->sval[1], h->q_t, h->q_x,
                     h->q_y, h->q_p, h->stage_key, h->seg_slots, h->seg_base,
-                    h->seg_count, h->pref, h->tile_sum, h->hist,
+                    h->seg_count, h->pref, h->scan_status, h->hist,
                     h->pass_status, h->pass_ctr, h->env_off};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -205,6 +210,13 @@ int sync_and_status(nsim_ev* h) {
             snprintf(buf, sizeof buf,
                      "event queue overflow: frames from t=%lld on were not "
                      "processed; drain and re-issue them",
+                     (long long)hd.dropped_t);
+        else if (hd.internal_err & nsim::kErrRange)
+            snprintf(buf, sizeof buf,
+                     "input outside the supported range (a pixel crossed 2^20 "
+                     "or more levels in one frame interval, or crossed more "
+                     "than 2^30 levels of one polarity in all): frames from "
+                     "t=%lld on were not processed",
                      (long long)hd.dropped_t);
         else
             snprintf(buf, sizeof buf,
@@ -259,8 +271,51 @@ struct LaunchSet {
     int32_t kl = 0;
 };
 
+// Per-launch scratch of a launch sequence: the handle's own allocation, or
+// the file-scope array of the allocation-free step.
+struct ScratchView {
+    uint32_t* stage_key = nullptr;   // [nwaves * stage_entries + pool]
+    int64_t stage_cap = 0;
+    int32_t stage_entries = 0;
+    int64_t* seg_base = nullptr;     // [nwaves]
+    uint32_t* seg_count = nullptr;
+    uint32_t* seg_slots = nullptr;
+    uint32_t* pref = nullptr;
+    uint64_t* scan_status = nullptr; // [scan_words(nwaves)]
+    uint32_t* skey[2] = {nullptr, nullptr};  // [scap] each
+    uint32_t* sval[2] = {nullptr, nullptr};
+    int64_t scap = 0;                // events one launch may produce
+    uint32_t* hist = nullptr;        // [kMaxPasses * kDigits]
+    uint32_t* pass_status = nullptr; // [kMaxPasses * max_tiles * kDigits]
+    int64_t max_tiles = 0;
+    uint32_t* pass_ctr = nullptr;    // [kMaxPasses]
+};
+
+ScratchView own_scratch(const nsim_ev* h) {
+    ScratchView v;
+    v.stage_key = h->stage_key;
+    v.stage_cap = h->stage_cap;
+    v.stage_entries = h->stage_entries;
+    v.seg_base = h->seg_base;
+    v.seg_count = h->seg_count;
+    v.seg_slots = h->seg_slots;
+    v.pref = h->pref;
+    v.scan_status = h->scan_status;
+    for (int i = 0; i < 2; ++i) {
+        v.skey[i] = h->skey[i];
+        v.sval[i] = h->sval[i];
+    }
+    v.scap = h->scap;
+    v.hist = h->hist;
+    v.pass_status = h->pass_status;
+    v.max_tiles = h->max_sort_tiles;
+    v.pass_ctr = h->pass_ctr;
+    return v;
+}
+
 void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
-                  const int64_t* t_us, int32_t kl, int64_t T0, bool dry) {
+                  const int64_t* t_us, int32_t kl, int64_t T0, bool dry,
+                  const ScratchView& sc) {
     L = LaunchSet{};
     L.kl = kl;
     nsim::StepArgs& a = L.step;
@@ -270,7 +325,7 @@ void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
     a.nwaves = h->nwaves;
     a.envs = h->envs;
     a.wave_env = h->wave_env;
-    a.stage_entries = h->stage_entries;
+    a.stage_entries = sc.stage_entries;
     a.L_init = h->L_init;
     for (int i = 0; i < 2; ++i) {
         a.nud[i] = h->nud[i];
@@ -288,13 +343,15 @@ void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
     const int64_t tmax = t_us[kl - 1];
     const double amax = std::max(std::fabs((double)T0), std::fabs((double)tmax));
     a.eT = (float)std::max(0x1p-12, amax * 0x1p-51);
-    a.out_key = h->stage_key;
-    a.out_cap = h->stage_cap;
-    a.seg_base = h->seg_base;
-    a.seg_count = h->seg_count;
-    a.seg_slots = h->seg_slots;
+    a.out_key = sc.stage_key;
+    a.out_cap = sc.stage_cap;
+    a.seg_base = sc.seg_base;
+    a.seg_count = sc.seg_count;
+    a.seg_slots = sc.seg_slots;
     a.hdr = h->hdr;
     a.flags = h->flags;
+    a.scan_words = (int32_t)nsim::scan_words(h->nwaves);
+    a.scan_status = sc.scan_status;
     for (int32_t i = 0; i < kl; ++i) a.toff[i] = (int32_t)(t_us[i] - T0);
     const int tbits = bits_for(a.toff[kl - 1]);
     a.key_tbits = tbits;
@@ -302,39 +359,39 @@ void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
     L.npass = (L.nbits + nsim::kDigitBits - 1) / nsim::kDigitBits;
 
     nsim::ScanArgs& sa = L.scan;
-    sa.seg_count = h->seg_count;
-    sa.pref = h->pref;
+    sa.seg_count = sc.seg_count;
+    sa.pref = sc.pref;
     sa.nwaves = h->nwaves;
     sa.restart_queue = h->batched ? 1 : 0;
-    sa.tile_sum = h->tile_sum;
+    sa.status = sc.scan_status;
     sa.hdr = h->hdr;
 
     nsim::GatherArgs& ga = L.gather;
-    ga.seg_base = h->seg_base;
-    ga.seg_count = h->seg_count;
-    ga.seg_slots = h->seg_slots;
-    ga.pref = h->pref;
+    ga.seg_base = sc.seg_base;
+    ga.seg_count = sc.seg_count;
+    ga.seg_slots = sc.seg_slots;
+    ga.pref = sc.pref;
     ga.nwaves = h->nwaves;
     ga.npass = L.npass;
-    ga.skey = h->stage_key;
+    ga.skey = sc.stage_key;
     ga.wave_env = h->wave_env;
     ga.key_tbits = tbits;
-    ga.dkey = h->skey[0];
-    ga.dval = h->sval[0];
+    ga.dkey = sc.skey[0];
+    ga.dval = sc.sval[0];
     ga.hdr = h->hdr;
-    ga.scratch_cap = h->scap;
+    ga.scratch_cap = sc.scap;
     ga.qcap = h->qcap;
-    ga.hist = h->hist;
-    ga.status = h->pass_status;
-    ga.max_tiles = h->max_sort_tiles;
-    ga.pass_ctr = h->pass_ctr;
+    ga.hist = sc.hist;
+    ga.status = sc.pass_status;
+    ga.max_tiles = sc.max_tiles;
+    ga.pass_ctr = sc.pass_ctr;
 
     for (int p = 0; p < L.npass; ++p) {
         nsim::PassArgs& pa = L.pass[p];
-        pa.kin = h->skey[p & 1];
-        pa.vin = h->sval[p & 1];
-        pa.kout = h->skey[(p + 1) & 1];
-        pa.vout = h->sval[(p + 1) & 1];
+        pa.kin = sc.skey[p & 1];
+        pa.vin = sc.sval[p & 1];
+        pa.kout = sc.skey[(p + 1) & 1];
+        pa.vout = sc.sval[(p + 1) & 1];
         pa.t_out = h->q_t;
         pa.x_out = h->q_x;
         pa.y_out = h->q_y;
@@ -347,21 +404,21 @@ void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
         pa.envs = h->envs;
         pa.n_env = h->n_env;
         pa.T0 = T0;
-        pa.hist = h->hist + p * nsim::kDigits;
-        pa.status = h->pass_status + (int64_t)p * h->max_sort_tiles * nsim::kDigits;
-        pa.tile_ctr = h->pass_ctr + p;
+        pa.hist = sc.hist + p * nsim::kDigits;
+        pa.status = sc.pass_status + (int64_t)p * sc.max_tiles * nsim::kDigits;
+        pa.tile_ctr = sc.pass_ctr + p;
         pa.hdr = h->hdr;
-        pa.scratch_cap = h->scap;
+        pa.scratch_cap = sc.scap;
     }
 
     nsim::CommitArgs& ca = L.commit;
     ca.hdr = h->hdr;
-    ca.scratch_cap = h->scap;
+    ca.scratch_cap = sc.scap;
     ca.qcap = h->qcap;
     ca.t_last = tmax;
     ca.t_first = t_us[0];
     ca.pixel_updates = h->P * kl;
-    ca.hist = h->hist;
+    ca.hist = sc.hist;
     ca.dry = dry ? 1 : 0;
     ca.n_env = h->n_env;
     ca.env_off = h->batched ? h->env_off : nullptr;
@@ -394,6 +451,7 @@ int capture_graph(nsim_ev* h, const LaunchSet& L, GraphSlot** out) {
         NSIM_HIP(h, hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     GraphSlot g;
     g.nbits = L.nbits;
+    g.one = L.kl == 1 ? 1 : 0;
     g.stage = h->stage_entries;
     g.wpb = h->waves_per_block;
     g.blocks = h->step_blocks;
@@ -426,7 +484,8 @@ int capture_graph(nsim_ev* h, const LaunchSet& L, GraphSlot** out) {
     } else if (e == hipSuccess) {
         e = hipErrorInvalidValue;
     }
-    const size_t expect = 5 + (size_t)L.npass;
+    // step, scan, gather, the radix passes, commit
+    const size_t expect = 4 + (size_t)L.npass;
     if (e == hipSuccess && chain.size() != expect) e = hipErrorInvalidValue;
     for (size_t i = 0; e == hipSuccess && i < chain.size(); ++i) {
         hipGraphNodeType ty;
@@ -435,7 +494,7 @@ int capture_graph(nsim_ev* h, const LaunchSet& L, GraphSlot** out) {
     }
     if (e == hipSuccess) {
         g.n_step = chain[0];
-        g.n_final = chain[3 + L.npass];
+        g.n_final = chain[2 + L.npass];
         g.n_commit = chain.back();
         e = hipGraphKernelNodeGetParams(g.n_step, &g.p_step);
         if (e == hipSuccess) e = hipGraphKernelNodeGetParams(g.n_final, &g.p_final);
@@ -453,7 +512,8 @@ int capture_graph(nsim_ev* h, const LaunchSet& L, GraphSlot** out) {
 
 GraphSlot* find_graph(nsim_ev* h, const LaunchSet& L) {
     for (GraphSlot& g : h->graphs)
-        if (g.nbits == L.nbits && g.stage == h->stage_entries &&
+        if (g.nbits == L.nbits && g.one == (L.kl == 1 ? 1 : 0) &&
+            g.stage == h->stage_entries &&
             g.wpb == h->waves_per_block && g.blocks == h->step_blocks)
             return &g;
     return nullptr;
@@ -514,7 +574,7 @@ int enqueue(nsim_ev* h, const LaunchSet& L, bool graph) {
 int time_trial(nsim_ev* h, const float* frames, const int64_t* t_us,
                int32_t kl, int64_t T0, bool graph, int reps, float* best) {
     LaunchSet L;
-    build_launch(h, L, frames, t_us, kl, T0, true);
+    build_launch(h, L, frames, t_us, kl, T0, true, own_scratch(h));
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     NSIM_HIP(h, get_event(h, &ev.first));
     NSIM_HIP(h, get_event(h, &ev.second));
@@ -657,12 +717,101 @@ void count_launch(nsim_ev* h, const LaunchSet& L) {
     h->stats.sort_passes += L.npass;
 }
 
+// The paper's kernel design (NSIM_ATOMIC_EMIT): one launch per frame; the
+// atomic step kernel, then (sorted) the preparation kernel and the radix
+// passes over the combined (time offset, pixel) key, then the commit.
+int enqueue_atomic(nsim_ev* h, const float* frame, const int64_t* t_us, int64_t T0) {
+    const bool sorted = (h->flags & NSIM_ATOMIC_UNSORTED) == 0;
+    LaunchSet L;
+    build_launch(h, L, frame, t_us, 1, T0, false, own_scratch(h));
+    const int pbits = bits_for((int64_t)h->nwaves * nsim::kWave - 1);
+    const int tbits = bits_for(t_us[0] - T0);
+    if (pbits + tbits > 32)
+        return fail(h, NSIM_EINVAL,
+                    "atomic emit: the frame gap and the pixel index need more "
+                    "than 32 key bits");
+    nsim::AtomicArgs aa{};
+    aa.s = L.step;
+    aa.sorted = sorted ? 1 : 0;
+    aa.pbits = pbits;
+    aa.npass = (pbits + tbits + nsim::kDigitBits - 1) / nsim::kDigitBits;
+    aa.width = h->W;
+    aa.dkey = h->skey[0];
+    aa.dval = h->sval[0];
+    aa.hist = h->hist;
+    aa.scap = h->scap;
+    aa.q_t = h->q_t;
+    aa.q_x = h->q_x;
+    aa.q_y = h->q_y;
+    aa.q_p = h->q_p;
+    aa.qcap = h->qcap;
+    std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
+    if (h->profiling) {
+        NSIM_HIP(h, get_event(h, &ev.first));
+        NSIM_HIP(h, get_event(h, &ev.second));
+        NSIM_HIP(h, hipEventRecord(ev.first, h->stream));
+    }
+    NSIM_HIP(h, nsim::launch_atomic_step(aa, h->log_input, h->has_map, h->stream));
+    if (h->profiling) {
+        NSIM_HIP(h, hipEventRecord(ev.second, h->stream));
+        h->pending.push_back(ev);
+    }
+    L.commit.scratch_cap = sorted ? h->scap : h->qcap;
+    if (sorted) {
+        nsim::PrepArgs pr{};
+        pr.hdr = h->hdr;
+        pr.status = h->pass_status;
+        pr.max_tiles = h->max_sort_tiles;
+        pr.pass_ctr = h->pass_ctr;
+        pr.npass = aa.npass;
+        pr.scratch_cap = h->scap;
+        pr.qcap = h->qcap;
+        NSIM_HIP(h, nsim::launch_prep(pr, h->stream));
+        for (int p = 0; p < aa.npass; ++p) {
+            nsim::PassArgs pa = L.pass[0];
+            pa.kin = h->skey[p & 1];
+            pa.vin = h->sval[p & 1];
+            pa.kout = h->skey[(p + 1) & 1];
+            pa.vout = h->sval[(p + 1) & 1];
+            pa.final_pass = (p == aa.npass - 1) ? 1 : 0;
+            pa.shift = nsim::kDigitBits * p;
+            pa.bits = std::min(nsim::kDigitBits, pbits + tbits - nsim::kDigitBits * p);
+            pa.key_pbits = pbits;
+            pa.hist = h->hist + p * nsim::kDigits;
+            pa.status = h->pass_status + (int64_t)p * h->max_sort_tiles * nsim::kDigits;
+            pa.tile_ctr = h->pass_ctr + p;
+            NSIM_HIP(h, nsim::launch_pass(pa, h->stream));
+        }
+    }
+    NSIM_HIP(h, nsim::launch_commit(L.commit, h->stream));
+    h->stats.step_launches += 1;
+    h->stats.pixel_updates += h->P;
+    h->stats.sort_passes += sorted ? aa.npass : 0;
+    return NSIM_OK;
+}
+
 int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
     if (!frames || !t_us) return fail(h, NSIM_EINVAL, "null frames or times");
     if (K < 1) return fail(h, NSIM_EINVAL, "K must be >= 1");
     int rc = check_times(h, t_us, K);
     if (rc) return rc;
     DeviceGuard dg(h->device);
+    if (h->flags & NSIM_ATOMIC_EMIT) {
+        int32_t k = 0;
+        const int64_t P = h->frame_stride;
+        if (!h->initialized) {
+            NSIM_HIP(h, enqueue_init(h, frames, t_us[0]));
+            h->initialized = true;
+            h->t_expect = t_us[0];
+            k = 1;
+        }
+        for (; k < K; ++k) {
+            rc = enqueue_atomic(h, frames + (int64_t)k * P, t_us + k, h->t_expect);
+            if (rc) return rc;
+            h->t_expect = t_us[k];
+        }
+        return NSIM_OK;
+    }
     const int64_t P = h->frame_stride;
     int32_t k = 0;
     if (!h->initialized) {
@@ -687,8 +836,12 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
         }
         if (kl == 0) kl = 1;  // a single frame always fits (gap < 2^25)
         LaunchSet L;
-        build_launch(h, L, frames + (int64_t)k * P, t_us + k, kl, T0, false);
-        rc = enqueue(h, L, false);
+        build_launch(h, L, frames + (int64_t)k * P, t_us + k, kl, T0, false,
+                     own_scratch(h));
+        // launches of a frame or two are bound by launch latency: replay the
+        // captured sequence (one graph per key width and variant)
+        const bool graph = kl <= kGraphMaxFrames && !(h->flags & NSIM_DIRECT_LAUNCH);
+        rc = enqueue(h, L, graph);
         if (rc) return rc;
         count_launch(h, L);
         h->t_expect = t_us[k + kl - 1];
@@ -735,7 +888,7 @@ int do_batch_step(nsim_ev* h, const float* frames, const int64_t* t_us,
         }
     }
     LaunchSet L;
-    build_launch(h, L, fr, t_us + k0, kl, T0, false);
+    build_launch(h, L, fr, t_us + k0, kl, T0, false, own_scratch(h));
     rc = enqueue(h, L, h->use_graph != 0);
     if (rc) return rc;
     count_launch(h, L);
@@ -838,7 +991,7 @@ int create_core(nsim_ev* h, const std::vector<EnvDesc>& envs, double log_eps,
     chk(dmalloc(&h->seg_base, h->nwaves));
     chk(dmalloc(&h->seg_count, h->nwaves));
     chk(dmalloc(&h->pref, h->nwaves));
-    chk(dmalloc(&h->tile_sum, (h->nwaves + nsim::kScanTile - 1) / nsim::kScanTile));
+    chk(dmalloc(&h->scan_status, nsim::scan_words(h->nwaves)));
     chk(dmalloc(&h->hist, nsim::kMaxPasses * nsim::kDigits));
     chk(dmalloc(&h->pass_status,
                 (size_t)nsim::kMaxPasses * h->max_sort_tiles * nsim::kDigits));
@@ -897,6 +1050,7 @@ int create_core(nsim_ev* h, const std::vector<EnvDesc>& envs, double log_eps,
 
 extern "C" {
 
+
 int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out) {
     if (!out) return NSIM_EINVAL;
     *out = nullptr;
@@ -912,7 +1066,10 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out) {
     if (cfg->max_frames_per_launch < 0 ||
         cfg->max_frames_per_launch > nsim::kMaxFramesPerLaunch)
         return NSIM_EINVAL;
-    if ((cfg->flags & ~(NSIM_INPUT_LOG | NSIM_FORCE_FP64)) != 0)
+    if ((cfg->flags & ~(NSIM_INPUT_LOG | NSIM_FORCE_FP64 | NSIM_DIRECT_LAUNCH |
+                        NSIM_ATOMIC_EMIT | NSIM_ATOMIC_UNSORTED)) != 0)
+        return NSIM_EINVAL;
+    if ((cfg->flags & NSIM_ATOMIC_UNSORTED) && !(cfg->flags & NSIM_ATOMIC_EMIT))
         return NSIM_EINVAL;
     const bool log_in = (cfg->flags & NSIM_INPUT_LOG) != 0;
     if (!log_in && !(cfg->log_eps >= 0.0 && std::isfinite(cfg->log_eps)))
@@ -1306,6 +1463,23 @@ int nsim_evb_set_profiling(nsim_evb_t* b, int on) {
 int nsim_evb_get_stats(nsim_evb_t* b, nsim_ev_stats* out) {
     if (!b) return NSIM_EINVAL;
     return nsim_ev_get_stats(&b->core, out);
+}
+
+int nsim_diag_stream(const void* src, void* dst, int64_t bytes, int32_t mode,
+                     void* stream) {
+    if (bytes < 0 || bytes % 16 != 0 || (mode != 0 && mode != 1)) return NSIM_EINVAL;
+    if (bytes == 0) return NSIM_OK;
+    if (!src || (mode == 0 && !dst)) return NSIM_EINVAL;
+    if (((uintptr_t)src | (uintptr_t)dst) % 16 != 0) return NSIM_EINVAL;
+    int dev = 0, ncu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) !=
+            hipSuccess)
+        return NSIM_EHIP;
+    if (nsim::launch_stream(src, dst, bytes / 16, mode, ncu, (hipStream_t)stream) !=
+        hipSuccess)
+        return NSIM_EHIP;
+    return NSIM_OK;
 }
 
 int nsim_diag_fast_log2(const float* x, float* out, int64_t n, void* stream) {

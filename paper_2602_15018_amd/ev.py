@@ -24,6 +24,9 @@ NSIM_EHIP = -4
 NSIM_ESTATE = -5
 NSIM_INPUT_LOG = 0x1
 NSIM_FORCE_FP64 = 0x2
+NSIM_ATOMIC_EMIT = 0x4
+NSIM_ATOMIC_UNSORTED = 0x8
+NSIM_DIRECT_LAUNCH = 0x10
 
 _CODE_NAMES = {
     NSIM_EINVAL: "NSIM_EINVAL", NSIM_ENOMEM: "NSIM_ENOMEM",
@@ -143,6 +146,7 @@ EXPORTED = [
     "nsim_ev_reset", "nsim_ev_destroy", "nsim_ev_last_error",
     "nsim_ev_state_bytes", "nsim_ev_get_state", "nsim_ev_set_state",
     "nsim_ev_set_profiling", "nsim_ev_get_stats", "nsim_diag_fast_log2",
+    "nsim_diag_stream",
     "nsim_evb_create", "nsim_evb_step", "nsim_evb_drain", "nsim_evb_events",
     "nsim_evb_sync", "nsim_evb_reset", "nsim_evb_destroy",
     "nsim_evb_last_error", "nsim_evb_get_tuning", "nsim_evb_set_profiling",
@@ -183,6 +187,7 @@ def load_library(path: str = _LIB_PATH):
         "nsim_ev_set_profiling": ([vp, c_int], c_int),
         "nsim_ev_get_stats": ([vp, ctypes.POINTER(Stats)], c_int),
         "nsim_diag_fast_log2": ([vp, vp, i64, vp], c_int),
+        "nsim_diag_stream": ([vp, vp, i64, i32, vp], c_int),
         "nsim_evb_create": ([ctypes.POINTER(_EnvDesc), i32,
                              ctypes.POINTER(_BatchConfig), vp,
                              ctypes.POINTER(vp)], c_int),
@@ -228,7 +233,8 @@ class EventSim:
     def __init__(self, width, height, c_pos=0.2, c_neg=0.2, c_pos_map=None,
                  c_neg_map=None, log_eps=1e-3, refractory_us=0,
                  capacity_events=1 << 22, input_is_log=False,
-                 force_fp64=False, max_frames_per_launch=0, stream=None):
+                 force_fp64=False, max_frames_per_launch=0, stream=None,
+                 direct_launch=False, emit="ordered"):
         import torch
 
         if not torch.cuda.is_available():
@@ -257,7 +263,10 @@ class EventSim:
         cfg.refractory_us = int(refractory_us)
         cfg.capacity_events = int(capacity_events)
         cfg.flags = (NSIM_INPUT_LOG if input_is_log else 0) | \
-            (NSIM_FORCE_FP64 if force_fp64 else 0)
+            (NSIM_FORCE_FP64 if force_fp64 else 0) | \
+            (NSIM_DIRECT_LAUNCH if direct_launch else 0) | \
+            {"ordered": 0, "atomic": NSIM_ATOMIC_EMIT,
+             "atomic_unsorted": NSIM_ATOMIC_EMIT | NSIM_ATOMIC_UNSORTED}[emit]
         cfg.max_frames_per_launch = int(max_frames_per_launch)
         self.input_is_log = bool(input_is_log)
         self.capacity = int(capacity_events)
@@ -544,3 +553,17 @@ def fast_log2(x):
     if rc != NSIM_OK:
         raise NsimError(rc, "nsim_diag_fast_log2 failed")
     return out
+
+
+def hbm_stream(src, dst=None):
+    """Stream the bytes of device tensor ``src`` through the library's
+    reference kernel: a copy into ``dst`` (same size) or, without ``dst``, a
+    read-only pass.  Enqueued on torch's current stream."""
+    lib = load_library()
+    n = src.numel() * src.element_size()
+    if dst is not None and dst.numel() * dst.element_size() != n:
+        raise ValueError("dst must have the size of src")
+    rc = lib.nsim_diag_stream(_dev_ptr(src), _dev_ptr(dst) if dst is not None else None,
+                              n, 0 if dst is not None else 1, _stream_ptr())
+    if rc != NSIM_OK:
+        raise NsimError(rc, "nsim_diag_stream failed")

@@ -298,6 +298,62 @@ def test_inversion_gpu():
     np.testing.assert_array_equal(a[3], -b[3])
 
 
+# ------------------------------------------- the paper's kernel design (A/B)
+
+def _sorted_tyx(ev):
+    t, x, y, p = ev
+    o = np.lexsort((p, x, y, t))
+    return t[o], x[o], y[o], p[o]
+
+
+ATOMIC_CASES = [
+    # workload, H, W, F, log input with large jumps
+    ("vga640x480_1000f_1000fps", 120, 200, 40, False),
+    ("hd1280x720_2000f_2000fps_agile", 96, 300, 30, False),
+    (None, 9, 70, 12, True),
+]
+
+
+@pytest.mark.parametrize("emit", ["atomic", "atomic_unsorted"])
+@pytest.mark.parametrize("case", range(len(ATOMIC_CASES)))
+def test_atomic_emit_matches_oracle(emit, case):
+    """One launch per frame, one atomic per wave: the sorted variant gives
+    the oracle's stream exactly; the unsorted one (the paper's output, in
+    the order waves reserved their slots) the same events as a multiset."""
+    from paper_2602_15018_amd.ev import EventSim
+    dev = _dev()
+    name, H, W, F, as_log = ATOMIC_CASES[case]
+    if name is None:
+        rng = np.random.default_rng(21)
+        fr = np.cumsum(rng.normal(0, 6.0, size=(F, H, W)), axis=0).astype(np.float32)
+        cp = rng.uniform(0.05, 0.5, size=(H, W)).astype(np.float32)
+        cn = rng.uniform(0.05, 0.5, size=(H, W)).astype(np.float32)
+        t = 1000 * np.arange(F)
+        tref = 30
+    else:
+        w = scene.WORKLOADS[name]
+        fr = scene.render_workload(w, 0, F, device=dev, height=H, width=W).cpu().numpy()
+        t = scene.frame_times(w, 0, F)
+        cp, cn = scene.threshold_maps(w, H, W)
+        tref = w.refractory_us
+    ref = oracle.run(fr, t, cp, cn, refractory_us=tref, input_is_log=as_log)["events"]
+    sim = EventSim(W, H, c_pos_map=cp, c_neg_map=cn, refractory_us=tref,
+                   input_is_log=as_log, emit=emit, capacity_events=1 << 22)
+    frd = torch.from_numpy(fr).to(dev)
+    sim.step(frd[:F // 2], t[:F // 2])
+    sim.step(frd[F // 2:], t[F // 2:])
+    got = as_numpy(sim.drain())
+    st = sim.stats()
+    sim.close()
+    want = (ref.t, ref.x, ref.y, ref.p)
+    assert len(ref) > 2000
+    assert st["step_launches"] == F - 1
+    if emit == "atomic":
+        assert exact_equal(got, want)
+    else:
+        assert exact_equal(_sorted_tyx(got), _sorted_tyx(want))
+
+
 # ------------------------------------------------------------- ABI behaviour
 
 def test_overflow_all_or_nothing_and_reissue():
@@ -332,6 +388,39 @@ def test_overflow_all_or_nothing_and_reissue():
     sim.close()
     got = tuple(np.concatenate(g) for g in got)
     assert exact_equal(ref, got)
+
+
+def test_range_limit_reports_estate():
+    """A log jump of 2^21 thresholds in one frame interval is past the
+    supported 2^20 - 1 crossings per pixel and interval: the step is not
+    committed (no truncated stream), NSIM_ESTATE is reported once with a
+    message naming the limit, and the stream goes on from the last committed
+    frame, equal to the oracle's."""
+    from paper_2602_15018_amd.ev import EventSim, NsimError
+    dev = _dev()
+    H, W = 2, 70
+    C = 2.0 ** -20
+    rng = np.random.default_rng(31)
+    L = (C * rng.uniform(-4.0, 4.0, size=(3, H, W))).astype(np.float32)
+    t = np.array([0, 1000, 2000], np.int64)
+    sim = EventSim(W, H, c_pos=C, c_neg=C, input_is_log=True)
+    Ld = torch.from_numpy(L).to(dev)
+    sim.step(Ld[0:2], t[0:2])
+    sim.sync()
+    bad = Ld[2:3].clone()
+    bad[0, 1, 5] = 2.0          # 2^21 levels above the reference
+    sim.step(bad, t[2:3])
+    with pytest.raises(NsimError) as e:
+        sim.sync()
+    assert e.value.code == -5 and "range" in str(e.value)
+    assert sim.committed_time() == 1000
+    sim.sync()                  # reported once
+    sim.step(Ld[2:3], t[2:3])
+    got = as_numpy(sim.drain())
+    sim.close()
+    ref = oracle.run(L, t, C, C, input_is_log=True)["events"]
+    assert len(ref) > 100
+    assert exact_equal(got, (ref.t, ref.x, ref.y, ref.p))
 
 
 def test_checkpoint_resume():

@@ -138,7 +138,16 @@ def test_forward_parity_bf16(N, H, W):
     assert np.max(np.abs(got - ref)) < 5e-2
 
 
-@pytest.mark.parametrize("N,H,W", [(2, 20, 28), (1, 32, 48)])
+# (2, 20, 28) and (1, 32, 48) fit one weight-gradient pixel block (at most
+# 4096 pixels per block).  (2, 88, 116): 20,416 pixels at full resolution
+# split into 5 blocks of 4096 starting mid-row (4096 = 35 rows of 116 + 36),
+# one spanning the boundary between the two images, and a ragged last block
+# of 4032; the half-resolution layers (5104 pixels) split into 2 blocks of
+# 2560 and 2544.  (3, 52, 68): 10,608 pixels in 3 blocks of 3584 (block 1
+# starts 48 pixels into image 1), last one 3440.  Every split goes through
+# the partial sums and their fixed-order reduction.
+@pytest.mark.parametrize("N,H,W", [(2, 20, 28), (1, 32, 48), (2, 88, 116),
+                                   (3, 52, 68)])
 def test_backward_parity_bf16(N, H, W):
     dev = _dev()
     p = _params(8)
@@ -177,3 +186,35 @@ def test_adam_first_step_closed_form():
     up.close()
     want = p0.double() - 1e-3 * g / (g.abs() + 1e-8)
     assert torch.max(torch.abs(p1 - want)).item() < 1e-6
+
+
+def test_adam_three_steps_vs_oracle():
+    """Three training steps on different crops with a decaying learning rate:
+    after each GPU Adam step the parameters equal the oracle's Adam (FP64)
+    applied to the gradients the GPU computed, so the moments' decay and the
+    bias corrections of steps 2 and 3 are checked, not only the first step
+    where the corrections cancel."""
+    dev = _dev()
+    p = _params(10)
+    up = _up(2 * 24 * 32)
+    flat0 = _flat(p)
+    up.set_params(torch.from_numpy(flat0).to(dev))
+    ref_p = {"a": flat0.astype(np.float64)}
+    ref_m = {"a": np.zeros(flat0.size)}
+    ref_v = {"a": np.zeros(flat0.size)}
+    for step, lr in enumerate((1e-3, 8e-4, 5e-4), start=1):
+        fr = _frames(500 + 10 * step, 2, 24, 32)
+        up.backward(torch.from_numpy(fr[:, 0]).to(dev), torch.from_numpy(fr[:, 8]).to(dev),
+                    torch.from_numpy(np.ascontiguousarray(fr[:, 1:8])).to(dev))
+        g = up.grads().cpu().numpy().astype(np.float64)
+        up.adam_step(lr)
+        got = up.params().cpu().numpy().astype(np.float64)
+        ref_p, ref_m, ref_v = unet.adam_step(ref_p, {"a": g}, ref_m, ref_v, step, lr=lr)
+        # FP32 parameters and moments: a few ulp of the parameter plus a
+        # relative 1e-5 of the step
+        err = np.abs(got - ref_p["a"])
+        assert np.max(err) < 1e-6, (step, float(np.max(err)))
+        ref_p = {"a": got}   # continue from the GPU's FP32 parameters
+    moved = np.abs(got - flat0.astype(np.float64))
+    assert np.median(moved) > 1e-4
+    up.close()
