@@ -5,14 +5,19 @@ frame through the fused step kernel, the radix sort into the event queue,
 and the drain of all events to caller-owned device arrays.  Frames are
 generated and resident in HBM before the timed region.
 
-Workload: the 1280x720 agile-flight stream, 2000 float32 frames at 2000 FPS
-(dt = 500 us), per-pixel thresholds N(0.2, 0.03) clipped to [0.05, 0.5],
-100 us refractory period, log eps 1e-3.
+Default workload (--workload hd): the 1280x720 agile-flight stream, 2000
+float32 frames at 2000 FPS (dt = 500 us), per-pixel thresholds N(0.2, 0.03)
+clipped to [0.05, 0.5], 100 us refractory period, log eps 1e-3.  Also:
+--workload vga (640x480, 1000 frames at 1000 FPS, same sensor), dvs
+(240x180, 200 frames at 1000 FPS, uniform thresholds, no refractory),
+perframe (one frame per call at 640x480 and 1280x720, in kHz), batch64 and
+learned.
 
 Prints one JSON line: Gpixel-updates/s (whole job), events/s, the fused
 step kernel's achieved HBM bandwidth against the 8 TB/s peak (algorithmic
-bytes over its HIP-event-timed duration), and the FP64 CPU oracle timed on
-a bounded sample on the host.
+bytes over its HIP-event-timed duration) beside the bandwidth a plain
+streaming kernel reaches in the same process, and the FP64 CPU oracle timed
+on a bounded sample on one pinned host core.
 """
 from __future__ import annotations
 
@@ -28,19 +33,30 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-WORKLOAD = "hd1280x720_2000f_2000fps_agile"
+STREAMS = {
+    "hd": "hd1280x720_2000f_2000fps_agile",
+    "vga": "vga640x480_1000f_1000fps",
+    "dvs": "dvs240x180_200f_1000fps",
+}
+WORKLOAD = STREAMS["hd"]
 METRIC = ("Gpixel-updates/s and events/s on 1 MI355X; % HBM peak; speedup vs "
           "plain at stated error")
 HBM_PEAK_GBS = 8000.0
-# Algorithmic bytes of the fused step kernel: per pixel per launch it reads
-# the state (L_init 8, counters 8, previous sample 4, refractory time 4) and
-# both threshold maps (8), and writes counters, previous sample and
-# refractory time (16); per pixel-update it reads one float32 frame sample
-# (4); per event it writes one packed staging entry (4).
-STATE_READ_B = 32
-STATE_WRITE_B = 16
+# Algorithmic bytes of the event path per unit of work: one float32 frame
+# sample per pixel-update (4), one SoA event out (int64 t, uint16 x, y, int8
+# p: 13), and per pixel per launch the minimal state read and written (12 B
+# each way: level, counters, refractory time) plus both threshold maps (8 B,
+# none with scalar thresholds).
 FRAME_B = 4
-PACKED_EVENT_B = 4
+EVENT_B = 13
+STATE_B = 12
+THRESH_B = 8
+
+
+def alg_bytes(pixels, pixel_updates, events, launches, mismatch):
+    """Algorithmic bytes of the event path for the given work."""
+    return (FRAME_B * pixel_updates + EVENT_B * events +
+            launches * pixels * (2 * STATE_B + (THRESH_B if mismatch else 0)))
 
 
 def log(msg):
@@ -59,26 +75,42 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-frames-per-launch", type=int, default=0)
     ap.add_argument("--workload", default="hd",
-                    choices=["hd", "batch64", "learned"],
-                    help="hd: the 1280x720 stream (default); batch64: 64 "
+                    choices=["hd", "vga", "dvs", "perframe", "batch64", "learned"],
+                    help="hd: the 1280x720 stream (default); vga, dvs: the "
+                         "640x480 and 240x180 streams; perframe: one frame "
+                         "per call at 640x480 and 1280x720 (kHz); batch64: 64 "
                          "environments of uneven size stepped together, "
                          "against the same environments as separate streams; "
                          "learned: train the upsampler, then 125-FPS frames "
                          "-> upsampler -> events against the 1000-FPS path")
+    ap.add_argument("--emit", default="ordered",
+                    choices=["ordered", "atomic", "atomic_unsorted"],
+                    help="stream workloads: the ordered path (default) or the "
+                         "paper's one-atomic-per-wave kernel, one launch per "
+                         "frame, sorted afterwards or left unsorted")
+    ap.add_argument("--no-ceiling", action="store_true",
+                    help="skip the streaming-kernel bandwidth ceiling")
     ap.add_argument("--train-sequences", type=int, default=10_000)
+    ap.add_argument("--train-epochs", type=int, default=4,
+                    help="learned: passes over the training sequences")
     ap.add_argument("--eval-pairs", type=int, default=16)
     ap.add_argument("--no-plain", action="store_true",
                     help="batch64: leave out the separate-stream comparison")
     ap.add_argument("--calib-copy", action="store_true",
-                    help="first run a plain 1 GiB device copy (the reference "
-                         "dispatch that scales profiler byte counters)")
+                    help="first run the library's reference streams over 1 "
+                         "GiB (a copy, then a read-only pass): the known byte "
+                         "counts that scale profiler traffic counters")
     return ap.parse_args()
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles",
-                            "step_kernel_hd1280x720_traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2602_15018_amd", "csrc",
                           "ev_kernels.hip")
+
+
+def traffic_file(workload):
+    short = {STREAMS["hd"]: "hd1280x720", STREAMS["vga"]: "vga640x480",
+             STREAMS["dvs"]: "dvs240x180"}.get(workload, workload)
+    return os.path.join(ROOT, "profiles", "step_kernel_%s_traffic.json" % short)
 
 
 def kernel_hash():
@@ -86,12 +118,12 @@ def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(frames_per_launch):
+def measured_traffic(workload, frames_per_launch):
     """HBM bytes per step-kernel launch from the committed counter profile,
     or None when it was taken on a different kernel source or launch
     length."""
     try:
-        rec = json.load(open(TRAFFIC_FILE))
+        rec = json.load(open(traffic_file(workload)))
     except (OSError, ValueError):
         return None
     if rec.get("kernel_hash") != kernel_hash():
@@ -101,51 +133,92 @@ def measured_traffic(frames_per_launch):
     return rec.get("bytes_per_launch")
 
 
+def cpu_info():
+    model, mhz = None, None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name") and model is None:
+                model = line.split(":", 1)[1].strip()
+            elif line.startswith("cpu MHz") and mhz is None:
+                mhz = float(line.split(":", 1)[1])
+    except OSError:
+        pass
+    return {"model": model, "mhz": mhz, "cpu_count": os.cpu_count(),
+            "cpus_allowed": len(os.sched_getaffinity(0))}
+
+
 def cpu_baseline(frames_dev, t, cp, cn, w, n_intervals):
-    """Time the FP64 oracle (one host thread) on the first n_intervals frame
-    intervals of the same stream at full resolution."""
+    """Time the FP64 oracle on one host core (this thread pinned to the
+    first CPU it may use, restored afterwards) on the first n_intervals
+    frame intervals of the same stream at full resolution: the event
+    recurrence plus the stable sort.  Frame generation is not timed."""
     import oracle
 
     n = min(n_intervals, frames_dev.shape[0] - 1)
     fr = frames_dev[: n + 1].cpu().numpy()
-    s = oracle.OracleStream(w.width, w.height, cp, cn, w.log_eps,
-                            w.refractory_us, fragile_band_L=0.0,
-                            fragile_band_tau=0.0)
-    s.step(fr[:1], t[:1])  # initialisation frame, not timed
-    t0 = time.perf_counter()
-    s.step(fr[1:], t[1 : n + 1])
-    dt = time.perf_counter() - t0
-    ne = len(s.events(sort=False))
-    t1 = time.perf_counter()
-    s.events(sort=True)
-    dts = time.perf_counter() - t1
-    s.close()
+    info = cpu_info()
+    allowed = os.sched_getaffinity(0)
+    core = min(allowed)
+    os.sched_setaffinity(0, {core})
+    try:
+        s = oracle.OracleStream(w.width, w.height, cp, cn, w.log_eps,
+                                w.refractory_us, fragile_band_L=0.0,
+                                fragile_band_tau=0.0)
+        s.step(fr[:1], t[:1])  # initialisation frame, not timed
+        t0 = time.perf_counter()
+        s.step(fr[1:], t[1: n + 1])
+        dt = time.perf_counter() - t0
+        ne = len(s.events(sort=False))
+        t1 = time.perf_counter()
+        s.events(sort=True)
+        dts = time.perf_counter() - t1
+        s.close()
+    finally:
+        os.sched_setaffinity(0, allowed)
     pu = w.pixels * n
+    sec = dt + dts
     return {
-        "value": pu / (dt + dts) / 1e9,
+        "value": pu / sec / 1e9,
         "unit": "Gpixel-updates/s",
         "cores": 1,
         "kind": "oracle",
-        "sample": "first %d frame intervals of the same stream at full "
-                  "1280x720 (%d pixel-updates, %d events), event recurrence "
-                  "plus stable sort" % (n, pu, ne),
-        "seconds": dt + dts,
-        "events_per_s": ne / (dt + dts),
+        "sample": "first %d of %d frame intervals of the same %dx%d stream "
+                  "(%d pixel-updates, %d events), event recurrence plus stable "
+                  "sort, one thread pinned to CPU %d" % (
+                      n, w.frames - 1, w.width, w.height, pu, ne, core),
+        "seconds": sec,
+        "events_per_s": ne / sec,
+        "full_stream_seconds_extrapolated": sec * (w.frames - 1) / n,
+        "cpu": info,
     }
 
 
-def make_sim(w, F, cp, cn, max_frames_per_launch=0):
-    """The event path exactly as the benchmark times it: queue sized for the
-    whole stream, default frames per launch unless overridden."""
-    from paper_2602_15018_amd.ev import EventSim
+def hbm_ceiling(dev, nbytes=1 << 30, reps=5):
+    """Bandwidth of the library's reference streaming kernel in this
+    process: a read-only pass over `nbytes` and a copy of `nbytes` (best of
+    `reps`, HIP events on torch's current stream, which the library
+    enqueues on)."""
+    import torch
 
-    est_events = int(0.09 * w.pixels * (F - 1)) + (1 << 20)
-    cap = min(est_events, (1 << 30) - 1)
-    sim = EventSim(w.width, w.height, c_pos_map=cp, c_neg_map=cn,
-                   log_eps=w.log_eps, refractory_us=w.refractory_us,
-                   capacity_events=cap,
-                   max_frames_per_launch=max_frames_per_launch)
-    return sim, cap
+    from paper_2602_15018_amd.ev import hbm_stream
+    src = torch.empty(nbytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    src.fill_(1.0)
+    out = {}
+    for name, d, moved in (("read", None, nbytes), ("copy", dst, 2 * nbytes)):
+        best = 1e30
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(
+                enable_timing=True)
+            e0.record()
+            hbm_stream(src, d)
+            e1.record()
+            e1.synchronize()
+            best = min(best, e0.elapsed_time(e1))
+        out[name] = moved / (best * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return out
 
 
 def bench_batch(args):
@@ -219,8 +292,9 @@ def bench_batch(args):
         1, s1["step_timed"] - s0["step_timed"])
     launches = s1["step_launches"] - s0["step_launches"]
     ev_prof = s1["events"] - s0["events"]
-    alg = (total * (FRAME_B + STATE_READ_B + STATE_WRITE_B) +
-           PACKED_EVENT_B * ev_prof / max(1, launches))
+    # per call: every pixel updated once, its state read and written, the
+    # call's events out
+    alg = alg_bytes(total, total, ev_prof / max(1, launches), 1, True)
     achieved = alg / (k1_ms * 1e-3) / 1e9
 
     # the same environments as separate streams, stepped in turn
@@ -304,11 +378,12 @@ def bench_batch(args):
 
 
 def bench_learned(args):
-    """Learned upsampler: one pass over seeded training sequences (batch 16,
-    256x256 crops), then on held-out 640x480 scenes the event-count and
-    timestamp error of (125-FPS frames -> upsampler -> events at 1000 FPS)
-    and of linear interpolation against the 1000-FPS stream, and the time of
-    both paths.  One timed step = one 640x480 stream of 8 * eval_pairs
+    """Learned upsampler: several passes over seeded training sequences
+    (batch 16, 256x256 crops, held-out L1 after each), then on held-out
+    640x480 scenes the event-count error and the matched-event timestamp
+    error of (125-FPS frames -> upsampler -> events at 1000 FPS) and of
+    linear interpolation against the 1000-FPS stream, and the time of both
+    paths, with and without rendering.  One timed step = one 640x480 stream of 8 * eval_pairs
     frame intervals through the learned path (render at 125 FPS, log,
     upsample, events)."""
     import torch
@@ -322,9 +397,13 @@ def bench_learned(args):
     H, W = w.height, w.width
     up = Upsampler(max(16 * 256 * 256, 8 * H * W), seed=1)
     lin = Upsampler(8 * H * W, seed=1)
-    log("training on %d sequences" % args.train_sequences)
-    losses, t_train, t_wall = learned.train(up, args.train_sequences, 16, 256,
-                                            log=log)
+    log("training on %d sequences, %d epochs" % (args.train_sequences,
+                                                 args.train_epochs))
+    held = learned.training_batch(scene.EVAL_SEED0 + 1000 + np.arange(16),
+                                  np.random.default_rng(7), 256, dev)
+    tr = learned.train(up, args.train_sequences, 16, 256, log=log,
+                       epochs=args.train_epochs, heldout=held)
+    losses = tr["losses"]
     cp, cn = scene.threshold_maps(w)
     P = args.eval_pairs
     evals = {"learned": [], "linear": []}
@@ -424,14 +503,18 @@ def bench_learned(args):
             "train_sequences": args.train_sequences, "train_batch": 16,
             "train_crop": 256, "refractory_us": w.refractory_us,
         },
-        "training": {"seconds_in_steps": t_train, "seconds_wall": t_wall,
+        "training": {"seconds_in_steps": tr["seconds_in_steps"],
+                     "seconds_wall": tr["seconds_wall"], "epochs": tr["epochs"],
+                     "steps": tr["steps"], "heldout_l1_per_epoch": tr["heldout_l1"],
                      "loss_first": losses[0][1], "loss_last": losses[-1][1]},
         "error_vs_full_rate": {
             "learned": {k: mean("learned", k) for k in evals["learned"][0]},
             "linear": {k: mean("linear", k) for k in evals["linear"][0]},
         },
         "speedup": {
+            "renderer": "scene.render (torch, procedural gratings and blobs)",
             "measured_render": t_plain_step / t_learned_step,
+            "without_render": t_events_plain / (t_upsample + t_events_learned),
             "paper_render_rate_context": plain_ctx / learned_ctx,
             "ms_plain": t_plain_step * 1e3, "ms_learned": t_learned_step * 1e3,
             "ms_render_full": t_render_full * 1e3,
@@ -461,41 +544,54 @@ def bench_learned(args):
     print(json.dumps(result), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print("bench.py runs on one GPU only; this build has no multi-GPU path "
-              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
-        sys.exit(2)
+def make_sim(w, F, cp, cn, max_frames_per_launch=0, direct_launch=False,
+             emit="ordered"):
+    """The event path exactly as the benchmark times it: queue sized for the
+    whole stream, default frames per launch unless overridden."""
+    from paper_2602_15018_amd.ev import EventSim
+
+    est_events = int(0.09 * w.pixels * (F - 1)) + (1 << 20)
+    cap = min(est_events, (1 << 30) - 1)
+    sim = EventSim(w.width, w.height, c_pos_map=cp, c_neg_map=cn,
+                   c_pos=w.c_nominal, c_neg=w.c_nominal,
+                   log_eps=w.log_eps, refractory_us=w.refractory_us,
+                   capacity_events=cap,
+                   max_frames_per_launch=max_frames_per_launch,
+                   direct_launch=direct_launch, emit=emit)
+    return sim, cap
+
+
+def resident_frames(w, F, dev):
     import torch
 
-    dev = torch.device("cuda", 0)
-    if args.calib_copy:
-        src = torch.empty(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-        log("calibration copy: 1 GiB read + 1 GiB written")
-    if args.workload == "batch64":
-        bench_batch(args)
-        return
-    if args.workload == "learned":
-        bench_learned(args)
-        return
-
     from paper_2602_15018_amd import scene
-    w = scene.WORKLOADS[WORKLOAD]
-    F = args.frames or w.frames
     t = scene.frame_times(w, 0, F)
     cp, cn = scene.threshold_maps(w)
+    if not w.mismatch:
+        cp = cn = None
     frames = torch.empty((F, w.height, w.width), dtype=torch.float32, device=dev)
     log("rendering %d frames %dx%d" % (F, w.width, w.height))
     scene.render_workload(w, 0, F, device=dev, out=frames)
     torch.cuda.synchronize()
     log("frames resident (%.2f GB)" % (frames.numel() * 4 / 1e9))
+    return frames, t, cp, cn
 
-    sim, cap = make_sim(w, F, cp, cn, args.max_frames_per_launch)
+
+def bench_stream(args, dev):
+    """One whole stream per step (reset, all frames, drain)."""
+    import torch
+
+    from paper_2602_15018_amd import scene
+    name = STREAMS[args.workload]
+    w = scene.WORKLOADS[name]
+    F = args.frames or w.frames
+    frames, t, cp, cn = resident_frames(w, F, dev)
+    ceiling = None if args.no_ceiling else hbm_ceiling(dev)
+    if ceiling:
+        log("streaming kernel: read %.0f GB/s, copy %.0f GB/s" % (
+            ceiling["read"], ceiling["copy"]))
+
+    sim, cap = make_sim(w, F, cp, cn, args.max_frames_per_launch, emit=args.emit)
     out = (torch.empty(cap, dtype=torch.int64, device=dev),
            torch.empty(cap, dtype=torch.uint16, device=dev),
            torch.empty(cap, dtype=torch.uint16, device=dev),
@@ -531,10 +627,10 @@ def main():
     launches = st["step_launches"] - base["step_launches"]
     k1_ms = st["step_kernel_ms"] / max(1, st["step_timed"])
     launches_per_step = launches / args.steps
-    alg_bytes_step = (FRAME_B * pu_step + PACKED_EVENT_B * ev_step +
-                      launches_per_step * w.pixels * (STATE_READ_B + STATE_WRITE_B))
-    alg_bytes_launch = alg_bytes_step / launches_per_step
-    achieved = alg_bytes_launch / (k1_ms * 1e-3) / 1e9
+    fpl = round((F - 1) / launches_per_step, 1)
+    alg_step = alg_bytes(w.pixels, pu_step, ev_step, launches_per_step, w.mismatch)
+    alg_launch = alg_step / launches_per_step
+    achieved = alg_launch / (k1_ms * 1e-3) / 1e9
     fp64 = st["fp64_evaluations"] - base["fp64_evaluations"]
 
     result = {
@@ -551,11 +647,12 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": WORKLOAD,
+            "workload": name,
             "height": w.height, "width": w.width, "frames": F,
             "fps": w.fps, "refractory_us": w.refractory_us,
             "threshold_mismatch": w.mismatch,
-            "frames_per_launch": round((F - 1) / launches_per_step, 1),
+            "frames_per_launch": fpl,
+            "emit": args.emit,
         },
         "events_per_s": ev_step * args.steps / elapsed,
         "events_per_step": ev_step,
@@ -567,17 +664,156 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(round((F - 1) / launches_per_step, 1)),
+            "traffic": measured_traffic(name, fpl),
             "avg_launch_ms": k1_ms,
-            "alg_bytes_per_launch": alg_bytes_launch,
+            "alg_bytes_per_launch": alg_launch,
             "launches_per_step": launches_per_step,
+            "ceiling_gbs": ceiling["read"] if ceiling else None,
+            "ceiling_copy_gbs": ceiling["copy"] if ceiling else None,
+            "pipeline_frac": alg_step / (ms_per_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
         },
     }
     if not args.no_cpu:
         log("CPU oracle sample (%d frame intervals)" % args.cpu_sample_frames)
-        result["cpu_baseline"] = cpu_baseline(frames, t, cp, cn, w,
-                                              args.cpu_sample_frames)
+        result["cpu_baseline"] = cpu_baseline(frames, t, cp if cp is not None
+                                              else w.c_nominal,
+                                              cn if cn is not None else w.c_nominal,
+                                              w, args.cpu_sample_frames)
     print(json.dumps(result), flush=True)
+
+
+def waves_with_events(ev, t, W, t0):
+    """Atomics the paper's kernel issues: one per wave of 64 pixels that has
+    events in a frame interval, summed over the intervals."""
+    import torch
+    tt, x, y, _ = ev
+    if tt.numel() == 0:
+        return 0
+    times = torch.as_tensor(np.asarray(t, np.int64), device=tt.device)
+    fidx = torch.searchsorted(times, tt, right=False)   # interval (t_{f-1}, t_f]
+    wave = (y.to(torch.int64) * W + x.to(torch.int64)) // 64
+    key = fidx * (1 << 32) + wave
+    return int(torch.unique(key).numel())
+
+
+def bench_perframe(args, dev):
+    """One frame per call (the paper's per-frame latency figure): the
+    640x480 and 1280x720 streams, every frame its own step call, for the
+    ordered path and for the paper's kernel design (one atomic per wave),
+    sorted afterwards and unsorted.  'stream' = calls back to back with the
+    events queued on the device and drained once at the end; 'latency' =
+    each call followed by a drain of its events to caller arrays and a host
+    synchronisation.  One timed step = the whole 1280x720 stream in stream
+    mode on the ordered path."""
+    import torch
+
+    from paper_2602_15018_amd import scene
+    res = {}
+    for key in ("vga", "hd"):
+        w = scene.WORKLOADS[STREAMS[key]]
+        F = args.frames or w.frames
+        frames, t, cp, cn = resident_frames(w, F, dev)
+        res[key] = {"workload": STREAMS[key], "frames": F}
+        for emit in ("ordered", "atomic", "atomic_unsorted"):
+            sim, cap = make_sim(w, F, cp, cn, emit=emit)
+            out = (torch.empty(cap, dtype=torch.int64, device=dev),
+                   torch.empty(cap, dtype=torch.uint16, device=dev),
+                   torch.empty(cap, dtype=torch.uint16, device=dev),
+                   torch.empty(cap, dtype=torch.int8, device=dev))
+
+            def stream_mode():
+                sim.reset()
+                for k in range(F):
+                    sim.step(frames[k:k + 1], t[k:k + 1])
+                return sim.drain(out=out)
+
+            def latency_mode(nf):
+                sim.reset()
+                sim.step(frames[0:1], t[0:1])
+                sim.sync()
+                t0 = time.perf_counter()
+                for k in range(1, nf):
+                    sim.step(frames[k:k + 1], t[k:k + 1])
+                    sim.drain(out=out)
+                return time.perf_counter() - t0
+
+            for _ in range(max(1, args.warmup)):
+                ev = stream_mode()
+            n_ev = int(ev[0].numel())
+            atomics = waves_with_events(ev, t, w.width, t[0]) if emit != "ordered" else None
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                stream_mode()
+            torch.cuda.synchronize()
+            el = (time.perf_counter() - t0) / args.steps
+            nl = min(F, 501)
+            lat = latency_mode(nl)
+            sim.close()
+            per = el / (F - 1)
+            r = {
+                "us_per_frame_stream": per * 1e6, "khz_stream": 1e-3 / per,
+                "us_per_frame_latency": lat / (nl - 1) * 1e6,
+                "khz_latency": 1e-3 * (nl - 1) / lat,
+                "events_per_stream": n_ev,
+                "gpixel_updates_per_s": w.pixels * (F - 1) / el / 1e9,
+            }
+            if atomics is not None:
+                r["atomics_per_frame"] = atomics / (F - 1)
+            res[key][emit] = r
+            if key == "hd" and emit == "ordered":
+                hd_stream_s, hd_w, hd_F, hd_ev = el, w, F, n_ev
+            log("%s %s: %s" % (key, emit, json.dumps(r)))
+        del frames
+        torch.cuda.empty_cache()
+    result = {
+        "metric": METRIC,
+        "value": hd_w.pixels * (hd_F - 1) / hd_stream_s / 1e9,
+        "unit": "Gpixel-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": max(1, args.warmup),
+        "ms_per_step": hd_stream_s * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "perframe_" + STREAMS["hd"], "frames_per_call": 1},
+        "events_per_s": hd_ev / hd_stream_s,
+        "per_frame": res,
+        "paper_context_khz": {"vga": 31, "hd": 23},
+    }
+    print(json.dumps(result), flush=True)
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only; this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    dev = torch.device("cuda", 0)
+    if args.calib_copy:
+        from paper_2602_15018_amd.ev import hbm_stream
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        hbm_stream(src, dst)
+        hbm_stream(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("calibration streams: 1 GiB copied (1 GiB read + 1 GiB written), "
+            "then 1 GiB read")
+    if args.workload == "batch64":
+        bench_batch(args)
+    elif args.workload == "learned":
+        bench_learned(args)
+    elif args.workload == "perframe":
+        bench_perframe(args, dev)
+    else:
+        bench_stream(args, dev)
 
 
 if __name__ == "__main__":

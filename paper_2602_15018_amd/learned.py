@@ -5,8 +5,10 @@ The paper's event simulation wants 1000+ FPS frames (Sec. 1, contribution on
 efficient high-fidelity event simulation); rendering only every eighth frame
 and predicting the seven in between is our addition.  The full-rate plain
 path is both its fallback and its judge: ``compare_streams`` reports the
-per-pixel, per-polarity event-count error and the timestamp error of the
-learned stream against the full-rate stream of the same scene.
+per-pixel, per-polarity event-count error of the learned stream against the
+full-rate stream of the same scene, and the timestamp error of the events
+the two streams share (matched per pixel in time order, same polarity,
+within a window).
 
 Everything numeric on the path runs in the libraries' kernels (rendering is
 the synthetic input generator; the learning-rate schedule and the metrics
@@ -46,19 +48,31 @@ def training_batch(seeds, rng, crop, device):
             L[:, 1:RATE].contiguous())
 
 
+def heldout_l1(up, batch):
+    """Mean |prediction - target| of the network on a held-out batch."""
+    L0, L8, T = batch
+    return float((up.forward(L0, L8) - T).abs().mean().item())
+
+
 def train(up, n_sequences=10_000, batch=16, crop=256, lr=1e-3,
-          seed0=scene.TRAIN_SEED0, rng_seed=0, device=None, log=None):
-    """One pass over n_sequences seeded training sequences (Adam, cosine
-    learning-rate decay).  Returns (losses sampled every 25 steps, seconds in
-    train steps, wall seconds)."""
+          seed0=scene.TRAIN_SEED0, rng_seed=0, device=None, log=None,
+          epochs=1, heldout=None):
+    """``epochs`` passes over n_sequences seeded training sequences (a new
+    random crop of each sequence every pass; Adam, cosine learning-rate decay
+    over all steps).  Returns a dict: losses sampled every 25 steps, seconds
+    in train steps, wall seconds, and the L1 on the ``heldout`` batch (from
+    ``training_batch``) before training and after every epoch."""
     torch = _torch()
     device = device or torch.device("cuda", 0)
     rng = np.random.default_rng(rng_seed)
-    steps = max(1, n_sequences // batch)
-    losses, t_train = [], 0.0
+    per_epoch = max(1, n_sequences // batch)
+    steps = per_epoch * epochs
+    losses, t_train, held = [], 0.0, []
+    if heldout is not None:
+        held.append(heldout_l1(up, heldout))
     t0 = time.perf_counter()
     for s in range(steps):
-        seeds = seed0 + s * batch + np.arange(batch)
+        seeds = seed0 + (s % per_epoch) * batch + np.arange(batch)
         L0, L8, T = training_batch(seeds, rng, crop, device)
         lr_s = lr * 0.5 * (1.0 + math.cos(math.pi * s / steps))
         torch.cuda.synchronize()
@@ -70,7 +84,13 @@ def train(up, n_sequences=10_000, batch=16, crop=256, lr=1e-3,
             losses.append((s, float(loss.item())))
             if log:
                 log("train step %d/%d loss %.5f" % (s, steps, losses[-1][1]))
-    return losses, t_train, time.perf_counter() - t0
+        if heldout is not None and (s + 1) % per_epoch == 0:
+            held.append(heldout_l1(up, heldout))
+            if log:
+                log("epoch %d held-out L1 %.5f" % ((s + 1) // per_epoch, held[-1]))
+    return {"losses": losses, "seconds_in_steps": t_train,
+            "seconds_wall": time.perf_counter() - t0, "epochs": epochs,
+            "steps": steps, "heldout_l1": held}
 
 
 def full_rate_frames(seed, n_pairs, device, height=None, width=None):
@@ -126,37 +146,62 @@ def stream_events(frames, t, cp, cn, refractory_us, input_is_log, capacity):
             ev[2].to(torch.int32).cpu().numpy(), ev[3].cpu().numpy())
 
 
-def compare_streams(got, ref, width, height):
-    """Count error per (pixel, polarity) and timestamp error of the k-th
-    event of each (pixel, polarity) in both streams.
+MATCH_WINDOW_US = 1000   # one frame interval of the 1000-FPS stream
 
-    Returns E_count = sum |n_got - n_ref| / sum n_ref, the fraction of
-    reference events without a k-th partner, and |dt| quantiles (us)."""
-    def keyed(ev):
-        t, x, y, p = ev
-        key = (y.astype(np.int64) * width + x) * 2 + (p > 0)
-        order = np.lexsort((t, key))
-        key, t = key[order], t[order]
-        start = np.searchsorted(key, key, "left")
-        rank = np.arange(key.size) - start
-        return key, rank, t
 
-    P2 = width * height * 2
-    kg, rg, tg = keyed(got)
-    kr, rr, tr = keyed(ref)
-    ng = np.bincount(kg, minlength=P2)
-    nr = np.bincount(kr, minlength=P2)
-    total = max(1, int(nr.sum()))
-    e_count = float(np.abs(ng - nr).sum()) / total
-    big = np.int64(1) << 24
-    _, ig, ir = np.intersect1d(kg * big + rg, kr * big + rr, assume_unique=True,
-                               return_indices=True)
-    dt = np.abs(tg[ig] - tr[ir]).astype(np.float64)
+def compare_streams(got, ref, width, height, window_us=MATCH_WINDOW_US):
+    """Event-count error per (pixel, polarity) and timestamp error of
+    matched events of ``got`` against ``ref``.
+
+    Matching, per pixel, walks both streams in time order with two
+    pointers: the two current events match when they have the same polarity
+    and their times differ by at most ``window_us``; otherwise the earlier
+    one (the reference's on a tie) is unmatched and its pointer advances.
+    Events left when one stream runs out are unmatched.
+
+    Returns E_count = sum over (pixel, polarity) |n_got - n_ref| / sum n_ref,
+    the unmatched events of both streams over n_ref, and quantiles and mean
+    of |t_got - t_ref| (us) over matched pairs."""
+    def by_pixel(ev):
+        t, x, y, p = (np.asarray(a) for a in ev)
+        pix = y.astype(np.int64) * width + x.astype(np.int64)
+        order = np.lexsort((t, pix))
+        return pix[order], t[order].astype(np.int64), (p[order] > 0)
+
+    P = width * height
+    pg, tg, ug = by_pixel(got)
+    pr, tr, ur = by_pixel(ref)
+    ng2 = np.bincount(pg * 2 + ug, minlength=2 * P)
+    nr2 = np.bincount(pr * 2 + ur, minlength=2 * P)
+    n_ref = int(nr2.sum())
+    e_count = float(np.abs(ng2 - nr2).sum()) / max(1, n_ref)
+
+    end_g = np.cumsum(np.bincount(pg, minlength=P))
+    end_r = np.cumsum(np.bincount(pr, minlength=P))
+    ig = end_g - np.bincount(pg, minlength=P)
+    ir = end_r - np.bincount(pr, minlength=P)
+    dts = []
+    live = np.nonzero((ig < end_g) & (ir < end_r))[0]
+    while live.size:
+        a, b = ig[live], ir[live]
+        d = tg[a] - tr[b]
+        match = (ug[a] == ur[b]) & (np.abs(d) <= window_us)
+        dts.append(np.abs(d[match]))
+        adv_g = match | (d < 0)
+        adv_r = match | (d >= 0) & ~match
+        ig[live] += adv_g
+        ir[live] += adv_r
+        live = live[(ig[live] < end_g[live]) & (ir[live] < end_r[live])]
+    dt = np.concatenate(dts).astype(np.float64) if dts else np.zeros(0)
+    matched = int(dt.size)
+    unmatched = (int(ng2.sum()) - matched) + (n_ref - matched)
     q = np.quantile(dt, [0.5, 0.9, 0.99]) if dt.size else np.zeros(3)
     return {
-        "events_ref": int(nr.sum()), "events_got": int(ng.sum()),
+        "events_ref": n_ref, "events_got": int(ng2.sum()),
         "count_error": e_count,
-        "unpaired_fraction": 1.0 - dt.size / total,
+        "matched": matched,
+        "unmatched_fraction": unmatched / max(1, n_ref),
+        "window_us": window_us,
         "dt_p50_us": float(q[0]), "dt_p90_us": float(q[1]),
         "dt_p99_us": float(q[2]), "dt_mean_us": float(dt.mean()) if dt.size else 0.0,
     }
