@@ -8,6 +8,9 @@ two share no code: the only things both sides see are the seeded inputs.
 ``nsim_oracle.c`` is the definition (paper Sec. 2, event-camera paragraph
 and Fig. 3 caption; the readings it takes are listed in its header).
 ``brute.py`` is an independent per-microsecond tick stepper used to pin it.
+``repr_oracle.c`` builds the consumers' representations from an event
+stream: the time surface (appendix on the RL setup, its update equation) and
+polarity event frames over fixed windows (Fig. 2 / Fig. 5 captions).
 This module only marshals arrays through ctypes.
 """
 from __future__ import annotations
@@ -21,6 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "nsim_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "repr_oracle.c")]
 _LIB = os.path.join(_HERE, "libnsim_oracle.so")
 
 _lib = None
@@ -28,13 +32,13 @@ _lib = None
 
 def build(force: bool = False) -> str:
     """Compile the oracle with gcc (plain C11, no fused multiply-add)."""
-    stale = (not os.path.exists(_LIB)) or (
-        os.path.getmtime(_LIB) < os.path.getmtime(_SRC))
+    stale = (not os.path.exists(_LIB)) or any(
+        os.path.getmtime(_LIB) < os.path.getmtime(src) for src in _SRCS)
     if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call([
             "gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-            "-fno-fast-math", "-Wall", "-o", tmp, _SRC, "-lm"])
+            "-fno-fast-math", "-Wall", "-o", tmp, *_SRCS, "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -80,6 +84,14 @@ def _load():
     lib.nso_get_state.restype = None
     lib.nso_sort.argtypes = [vp]
     lib.nso_sort.restype = ctypes.c_int
+    d = ctypes.c_double
+    lib.nso_ts_update.argtypes = [i32, i32, d, vp, vp, vp, vp, i64, vp, vp, vp]
+    lib.nso_ts_update.restype = ctypes.c_int
+    lib.nso_ts_read.argtypes = [i32, i32, d, vp, vp, vp, i64, vp]
+    lib.nso_ts_read.restype = None
+    lib.nso_event_frames.argtypes = [i32, i32, vp, vp, vp, vp, i64, i64, i64,
+                                     i32, vp]
+    lib.nso_event_frames.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -212,3 +224,55 @@ def run(frames, t_us, c_pos=0.2, c_neg=0.2, log_eps=1e-3, refractory_us=0,
         out["state"] = s.state()
     s.close()
     return out
+
+
+def _event_arrays(ev):
+    return (np.ascontiguousarray(ev.t, dtype=np.int64),
+            np.ascontiguousarray(ev.x, dtype=np.uint16),
+            np.ascontiguousarray(ev.y, dtype=np.uint16),
+            np.ascontiguousarray(ev.p, dtype=np.int8))
+
+
+class TimeSurface:
+    """FP64 time surface of a W x H sensor: per pixel and polarity the value
+    as of its last event (S), that event's time and whether it ever fired;
+    arrays [2][H][W], channel 0 for p = -1 and 1 for p = +1."""
+
+    def __init__(self, width, height, tau_us=10_000.0):
+        self.width, self.height, self.tau_us = int(width), int(height), float(tau_us)
+        shape = (2, self.height, self.width)
+        self.S = np.zeros(shape)
+        self.t_last = np.zeros(shape, np.int64)
+        self.has = np.zeros(shape, np.int32)
+
+    def update(self, ev) -> None:
+        """Apply the events in their stream order."""
+        t, x, y, p = _event_arrays(ev)
+        rc = _load().nso_ts_update(self.width, self.height, self.tau_us,
+                                   _ptr(t), _ptr(x), _ptr(y), _ptr(p),
+                                   int(t.shape[0]), _ptr(self.S),
+                                   _ptr(self.t_last), _ptr(self.has))
+        if rc:
+            raise ValueError("event outside the sensor, bad polarity or an "
+                             "entry going back in time")
+
+    def read(self, t_query) -> np.ndarray:
+        """The surface decayed to time t_query."""
+        out = np.empty((2, self.height, self.width))
+        _load().nso_ts_read(self.width, self.height, self.tau_us,
+                            _ptr(self.S), _ptr(self.t_last), _ptr(self.has),
+                            int(t_query), _ptr(out))
+        return out
+
+
+def event_frames(ev, width, height, t0, window_us, n_frames) -> np.ndarray:
+    """Per-pixel, per-polarity event counts in n_frames consecutive windows
+    of window_us microseconds from t0: int32 [n_frames][2][H][W]."""
+    t, x, y, p = _event_arrays(ev)
+    counts = np.zeros((int(n_frames), 2, int(height), int(width)), np.int32)
+    rc = _load().nso_event_frames(int(width), int(height), _ptr(t), _ptr(x),
+                                  _ptr(y), _ptr(p), int(t.shape[0]), int(t0),
+                                  int(window_us), int(n_frames), _ptr(counts))
+    if rc:
+        raise ValueError("event outside the sensor or bad polarity")
+    return counts

@@ -370,3 +370,27 @@ def random_frames(seed, F, H, W, lo=0.01, hi=1.0, jump=0.6):
         logI = np.clip(logI + step, math.log(lo), math.log(hi))
         out[f] = np.exp(logI)
     return out
+
+
+def synthetic_events(seed, width, height, n, t_start, t_end, active=0.05,
+                     skew=1.5):
+    """A seeded event stream in the drained layout (t int64, x, y uint16,
+    p int8), sorted by (t, y, x), for the representation kernels' tests.
+
+    Events fall on a random subset of `active` x pixels, with per-pixel
+    rates from a power law (exponent `skew`) so that a few pixels carry many
+    events, as edges do in a moving scene; times uniform in [t_start,
+    t_end), polarity +1 / -1 with equal odds, several events per
+    microsecond and repeated (t, pixel) pairs included."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    P = width * height
+    k = max(1, int(active * P))
+    pix = rng.choice(P, size=k, replace=False)
+    w = rng.pareto(skew, size=k) + 1.0
+    idx = rng.choice(pix, size=n, p=w / w.sum())
+    t = rng.integers(t_start, t_end, size=n, dtype=np.int64)
+    p = np.where(rng.uniform(size=n) < 0.5, -1, 1).astype(np.int8)
+    y, x = np.divmod(idx, width)
+    order = np.lexsort((x, y, t))
+    return (t[order], x[order].astype(np.uint16), y[order].astype(np.uint16),
+            p[order])
