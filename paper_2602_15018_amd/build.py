@@ -1,5 +1,6 @@
 """Build the HIP libraries in-tree with hipcc for gfx950: libnsim_ev.so (the
-event path) and libnsim_up.so (the learned temporal upsampler)."""
+event path), libnsim_up.so (the learned temporal upsampler) and
+libnsim_repr.so (time surface and polarity event frames)."""
 from __future__ import annotations
 
 import os
@@ -14,6 +15,8 @@ LIB = os.path.join(PKG, "libnsim_ev.so")
 SOURCES = ["ev_kernels.hip", "ev_runtime.cpp"]
 UP_LIB = os.path.join(PKG, "libnsim_up.so")
 UP_SOURCES = ["up_kernels.hip", "up_runtime.cpp"]
+REPR_LIB = os.path.join(PKG, "libnsim_repr.so")
+REPR_SOURCES = ["repr_kernels.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
@@ -54,8 +57,9 @@ def build_one(lib, sources, verbose=False, extra=()) -> str:
 
 
 def build(verbose: bool = False, extra=()) -> str:
-    """Compile every source and link both libraries (always rebuilds)."""
+    """Compile every source and link the libraries (always rebuilds)."""
     build_one(UP_LIB, UP_SOURCES, verbose, extra)
+    build_one(REPR_LIB, REPR_SOURCES, verbose, extra)
     return build_one(LIB, SOURCES, verbose, extra)
 
 

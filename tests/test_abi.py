@@ -13,6 +13,8 @@ LIBS = {
            os.path.join(PKG, "libnsim_ev.so")),
     "up": (os.path.join(ROOT, "include", "nsim_up.h"),
            os.path.join(PKG, "libnsim_up.so")),
+    "repr": (os.path.join(ROOT, "include", "nsim_repr.h"),
+             os.path.join(PKG, "libnsim_repr.so")),
 }
 
 
@@ -32,6 +34,9 @@ def test_header_declares_expected_api():
     for n in ("nsim_up_create", "nsim_up_forward", "nsim_up_train_step",
               "nsim_up_destroy"):
         assert n in names
+    names = declared_functions("repr")
+    for n in ("nsim_ts_update", "nsim_ts_read", "nsim_event_frames"):
+        assert n in names
 
 
 @pytest.mark.parametrize("which", sorted(LIBS))
@@ -46,9 +51,10 @@ def test_library_exports_every_declared_symbol(which):
 
 
 def test_binding_knows_every_declared_symbol():
-    from paper_2602_15018_amd import ev, up
+    from paper_2602_15018_amd import ev, representations as rp, up
     assert sorted(ev.EXPORTED) == declared_functions("ev")
     assert sorted(up.EXPORTED) == declared_functions("up")
+    assert sorted(rp.EXPORTED) == declared_functions("repr")
 
 
 def test_binding_fails_loudly_without_device():
@@ -63,3 +69,6 @@ def test_binding_fails_loudly_without_device():
         EventBatch([dict(width=8, height=8)])
     with pytest.raises(RuntimeError):
         Upsampler(1024)
+    from paper_2602_15018_amd.representations import TimeSurface
+    with pytest.raises(RuntimeError):
+        TimeSurface(8, 8)
