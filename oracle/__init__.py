@@ -84,6 +84,15 @@ def _load():
     lib.nso_get_state.restype = None
     lib.nso_sort.argtypes = [vp]
     lib.nso_sort.restype = ctypes.c_int
+    lib.nso_set_sensor.argtypes = [vp, ctypes.c_float, ctypes.c_double,
+                                   ctypes.c_double, ctypes.c_uint64]
+    lib.nso_set_sensor.restype = ctypes.c_int
+    lib.nso_get_filtered.argtypes = [vp, vp]
+    lib.nso_get_filtered.restype = None
+    lib.nso_philox4x32.argtypes = [vp, vp, vp]
+    lib.nso_philox4x32.restype = None
+    lib.nso_noise_thresholds.argtypes = [ctypes.c_double, vp]
+    lib.nso_noise_thresholds.restype = None
     d = ctypes.c_double
     lib.nso_ts_update.argtypes = [i32, i32, d, vp, vp, vp, vp, i64, vp, vp, vp]
     lib.nso_ts_update.restype = ctypes.c_int
@@ -116,7 +125,8 @@ class OracleStream:
 
     def __init__(self, width, height, c_pos=0.2, c_neg=0.2, log_eps=1e-3,
                  refractory_us=0, input_is_log=False, fragile_band_L=1e-5,
-                 fragile_band_tau=1e-3):
+                 fragile_band_tau=1e-3, saturation=float("inf"),
+                 bandwidth_tau_us=0.0, noise_rate_hz=0.0, noise_seed=0):
         lib = _load()
         self._keep = []
         cfg = _Config()
@@ -143,6 +153,10 @@ class OracleStream:
         self._h = h
         self.width, self.height = cfg.width, cfg.height
         self._sorted = False
+        if lib.nso_set_sensor(h, float(saturation), float(bandwidth_tau_us),
+                              float(noise_rate_hz), int(noise_seed)):
+            self.close()
+            raise ValueError("oracle rejected the sensor settings")
 
     def close(self):
         if getattr(self, "_h", None):
@@ -189,6 +203,13 @@ class OracleStream:
             lib.nso_get_fragile(self._h, _ptr(pix), _ptr(frame))
         return pix, frame
 
+    def filtered(self) -> np.ndarray:
+        """Low-pass filtered log intensity per pixel after the last frame
+        (FP64, before the comparator's FP32 rounding)."""
+        out = np.empty(self.width * self.height)
+        _load().nso_get_filtered(self._h, _ptr(out))
+        return out
+
     def state(self) -> dict:
         P = self.width * self.height
         out = dict(L_init=np.empty(P), L_prev=np.empty(P),
@@ -202,7 +223,7 @@ class OracleStream:
 
 def run(frames, t_us, c_pos=0.2, c_neg=0.2, log_eps=1e-3, refractory_us=0,
         input_is_log=False, chunks=None, want_fragile=False,
-        want_state=False):
+        want_state=False, sensor=None):
     """Run a whole stream through the oracle and return the sorted events.
 
     ``frames`` is [F][H][W] float32, ``t_us`` the F integer timestamps.
@@ -210,7 +231,8 @@ def run(frames, t_us, c_pos=0.2, c_neg=0.2, log_eps=1e-3, refractory_us=0,
     """
     frames = np.asarray(frames)
     F, H, W = frames.shape
-    s = OracleStream(W, H, c_pos, c_neg, log_eps, refractory_us, input_is_log)
+    s = OracleStream(W, H, c_pos, c_neg, log_eps, refractory_us, input_is_log,
+                     **(sensor or {}))
     t = np.asarray(t_us, dtype=np.int64)
     bounds = [0, F] if not chunks else list(chunks)
     for a, b in zip(bounds[:-1], bounds[1:]):
@@ -223,6 +245,22 @@ def run(frames, t_us, c_pos=0.2, c_neg=0.2, log_eps=1e-3, refractory_us=0,
     if want_state:
         out["state"] = s.state()
     s.close()
+    return out
+
+
+def philox4x32(ctr, key) -> np.ndarray:
+    """Philox4x32-10 of one 128-bit counter under a 64-bit key (4 words)."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.empty(4, np.uint32)
+    _load().nso_philox4x32(_ptr(c), _ptr(k), _ptr(out))
+    return out
+
+
+def noise_thresholds(lam) -> np.ndarray:
+    """The oracle's inverse-CDF thresholds of a Poisson count of mean lam."""
+    out = np.empty(4, np.uint64)
+    _load().nso_noise_thresholds(float(lam), _ptr(out))
     return out
 
 

@@ -39,6 +39,29 @@
  * values promoted exactly to double.  Build with -ffp-contract=off so that
  * no multiply-add is fused.
  *
+ * Sensor non-idealities (Sec. 2, event-camera paragraph: the simulator
+ * models noise, limited bandwidth and saturation, and each can be switched
+ * off; the paper gives no model, so these are readings, all off by default):
+ *   - saturation: intensities clip at a full-well level, I -> min(I, I_sat)
+ *     (in FP32, before the log);
+ *   - bandwidth: the photoreceptor is a first-order low-pass filter on log
+ *     intensity with time constant tau_bw, the input held at the new sample
+ *     over each interval (exact discretisation):
+ *       Lf = L + exp(-dt / tau_bw) * (Lf_prev - L),  Lf = L at the first frame;
+ *     with saturation or bandwidth on, the comparator sees Lf (or L) rounded
+ *     to FP32, the precision of a log-intensity frame;
+ *   - noise: background-activity events, independent of the signal, a
+ *     Poisson number per pixel and frame interval with mean
+ *     lambda = rate * dt; they do not move the reference level, are not
+ *     refractory-filtered and do not set t_last.  Their randomness comes from
+ *     the counter-based generator Philox4x32-10 (Salmon et al., SC 2011),
+ *     keyed by the 64-bit seed, counter (pixel, frame index low, high, j):
+ *     j = 0 gives the count by inverse CDF against 32-bit thresholds
+ *     floor(2^32 * P(K <= i)), i = 0..3 (at most 4 events); j = 1..k give
+ *     event j-1's time t_prev + 1 + floor(w0 * dt / 2^32) and polarity +1
+ *     iff bit 31 of w1 is set.  Within one (t, y, x), signal events come
+ *     before noise events.
+ *
  * Fragile flags: for the comparison protocol the oracle also records each
  * (pixel, frame) whose log intensity lies within `fragile_band_L` of a
  * candidate level R + k C_pos or R - k C_neg (k >= 1, R taken before the
@@ -69,6 +92,7 @@ typedef struct {
 typedef struct {
     double L_init;
     double L_prev;
+    double L_lp;       /* low-pass filtered log intensity (bandwidth) */
     int64_t n_up;
     int64_t n_down;
     int64_t t_last;
@@ -91,6 +115,12 @@ typedef struct {
     uint16_t* ev_x;
     uint16_t* ev_y;
     int8_t* ev_p;
+    /* sensor non-idealities (all off by default) */
+    int front_end;          /* saturation or bandwidth on */
+    float sat;              /* full-well intensity, +inf: off */
+    double bw_tau;          /* low-pass time constant (us), 0: off */
+    double noise_rate;      /* background events per pixel per us, 0: off */
+    uint32_t noise_key[2];
     /* fragile (pixel, frame) pairs */
     int64_t n_fr, cap_fr;
     int64_t* fr_pix;
@@ -152,6 +182,61 @@ static double log_intensity(const nso_stream* s, float v) {
     return log((double)v + s->cfg.log_eps);
 }
 
+/* Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as
+ * easy as 1, 2, 3", SC 2011): ten rounds of two 32x32->64 multiplies with
+ * the published multipliers, the key bumped by the published Weyl
+ * constants between rounds. */
+static void philox4x32(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]) {
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        c0 = hi1 ^ c1 ^ k0;
+        c1 = lo1;
+        c2 = hi0 ^ c3 ^ k1;
+        c3 = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
+void nso_philox4x32(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
+    philox4x32(ctr, key, out);
+}
+
+/* Inverse-CDF thresholds of a Poisson count with mean lambda:
+ * T[i] = floor(2^32 * P(K <= i)), i = 0..3; a uniform 32-bit word u gives
+ * K = #{i : u >= T[i]} (capped at 4). */
+static void noise_thresholds(double lambda, uint64_t T[4]) {
+    double term = exp(-lambda), cdf = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        if (i > 0) term = term * lambda / (double)i;
+        cdf += term;
+        const double v = floor(cdf * 4294967296.0);
+        T[i] = v >= 4294967296.0 ? 4294967296ull : (uint64_t)v;
+    }
+}
+
+void nso_noise_thresholds(double lambda, uint64_t* T) { noise_thresholds(lambda, T); }
+
+/* Comparator input with the sensor front-end on: saturation, log, the
+ * low-pass filter (a = exp(-dt / tau_bw) of the interval; first frame:
+ * settled), then FP32 rounding. */
+static double front_end(const nso_stream* s, nso_pixel* q, float v, int first, double a) {
+    const float Is = v > s->sat ? s->sat : v;
+    const double L = log((double)Is + s->cfg.log_eps);
+    const double Lf = (first || s->bw_tau <= 0.0) ? L : L + a * (q->L_lp - L);
+    q->L_lp = Lf;
+    return (double)(float)Lf;
+}
+
 /* Reference level from the lattice counters, with the fixed grouping
  * L_init + (n_up * C_pos - n_down * C_neg). */
 static double reference_level(const nso_pixel* q, double cp, double cn) {
@@ -203,6 +288,7 @@ nso_stream* nso_create(const nso_config* cfg) {
     }
     s->cfg.c_pos_map = NULL;
     s->cfg.c_neg_map = NULL;
+    s->sat = INFINITY;
     return s;
 }
 
@@ -220,6 +306,34 @@ void nso_destroy(nso_stream* s) {
     free(s);
 }
 
+/* Switch on sensor non-idealities before the first step.  saturation: the
+ * full-well intensity (+inf: off); bandwidth_tau_us: the low-pass time
+ * constant (0: off); noise_rate_hz: background events per pixel per second
+ * (0: off) with a 64-bit seed.  Saturation and bandwidth need intensity
+ * input.  Returns 0, or -1 for bad values or a stream already started. */
+int nso_set_sensor(nso_stream* s, float saturation, double bandwidth_tau_us,
+                   double noise_rate_hz, uint64_t noise_seed) {
+    if (!s || s->initialized || !(saturation > 0.0f) || !(bandwidth_tau_us >= 0.0) ||
+        !(noise_rate_hz >= 0.0))
+        return -1;
+    const int fe = isinf(saturation) == 0 || bandwidth_tau_us > 0.0;
+    if (fe && s->cfg.input_is_log) return -1;
+    s->front_end = fe;
+    s->sat = saturation;
+    s->bw_tau = bandwidth_tau_us;
+    s->noise_rate = noise_rate_hz * 1e-6;
+    s->noise_key[0] = (uint32_t)noise_seed;
+    s->noise_key[1] = (uint32_t)(noise_seed >> 32);
+    return 0;
+}
+
+/* The low-pass filtered log intensity of every pixel after the last frame
+ * (before FP32 rounding; the plain log without bandwidth). */
+void nso_get_filtered(const nso_stream* s, double* out) {
+    if (!s) return;
+    for (int64_t i = 0; i < s->P; ++i) out[i] = s->px[i].L_lp;
+}
+
 /* One frame interval (t_prev, t_now] for every pixel, row-major. */
 static int process_frame(nso_stream* s, const float* frame, int64_t t_now) {
     const int W = s->cfg.width, H = s->cfg.height;
@@ -229,13 +343,18 @@ static int process_frame(nso_stream* s, const float* frame, int64_t t_now) {
     const double bandL = s->cfg.fragile_band_L;
     const double bandT = s->cfg.fragile_band_tau;
     s->frame_index++;
+    const int64_t fi = s->frame_index;
+    const double a_bw = s->bw_tau > 0.0 ? exp(-(double)dt / s->bw_tau) : 0.0;
+    uint64_t T_noise[4] = {0, 0, 0, 0};
+    if (s->noise_rate > 0.0) noise_thresholds(s->noise_rate * (double)dt, T_noise);
     for (int y = 0; y < H; ++y) {
         for (int x = 0; x < W; ++x) {
             const int64_t pix = (int64_t)y * W + x;
             nso_pixel* q = &s->px[pix];
             const double cp = (double)s->c_pos[pix];
             const double cn = (double)s->c_neg[pix];
-            const double L1 = log_intensity(s, frame[pix]);
+            const double L1 = s->front_end ? front_end(s, q, frame[pix], 0, a_bw)
+                                           : log_intensity(s, frame[pix]);
             const double L0 = q->L_prev;
             double R = reference_level(q, cp, cn);
 
@@ -278,6 +397,19 @@ static int process_frame(nso_stream* s, const float* frame, int64_t t_now) {
                 }
             }
             q->L_prev = L1;
+            if (s->noise_rate > 0.0) {
+                uint32_t ctr[4] = {(uint32_t)pix, (uint32_t)fi, (uint32_t)(fi >> 32), 0u};
+                uint32_t w[4];
+                philox4x32(ctr, s->noise_key, w);
+                int k = 0;
+                while (k < 4 && (uint64_t)w[0] >= T_noise[k]) ++k;
+                for (int j = 0; j < k; ++j) {
+                    ctr[3] = (uint32_t)(j + 1);
+                    philox4x32(ctr, s->noise_key, w);
+                    const int64_t off = (int64_t)(((uint64_t)w[0] * (uint64_t)dt) >> 32);
+                    if (push_event(s, tp + 1 + off, x, y, (w[1] >> 31) ? 1 : -1)) return -2;
+                }
+            }
         }
     }
     s->t_prev = t_now;
@@ -298,7 +430,8 @@ int nso_step(nso_stream* s, const float* frames, const int64_t* t, int32_t K) {
     if (!s->initialized) {
         for (int64_t pix = 0; pix < s->P; ++pix) {
             nso_pixel* q = &s->px[pix];
-            q->L_init = log_intensity(s, frames[pix]);
+            q->L_init = s->front_end ? front_end(s, q, frames[pix], 1, 0.0)
+                                     : log_intensity(s, frames[pix]);
             q->L_prev = q->L_init;
             q->n_up = q->n_down = 0;
             q->t_last = 0;
