@@ -122,6 +122,40 @@ int nsim_ev_step(nsim_ev_t* h, const float* frames, const int64_t* t_us,
 int nsim_ev_step_log(nsim_ev_t* h, const float* log_frames,
                      const int64_t* t_us, int32_t K);
 
+/* Sensor non-idealities (Sec. 2, event-camera paragraph: the simulator
+ * models noise, limited bandwidth and saturation, each of which the user may
+ * switch off; the paper gives no model, so these are stated readings).
+ * Call before the first step of a single stream (NSIM_EINVAL otherwise, and
+ * for batches).  All are off by default.
+ *   saturation: full-well intensity; frames clip at it before the log,
+ *     I -> min(I, saturation) in FP32.  +INFINITY: off.  Must be > 0.
+ *   bandwidth_tau_us: time constant of a first-order low-pass filter of the
+ *     log intensity (photoreceptor bandwidth); over each frame interval dt
+ *     the input is held at the new sample:
+ *       Lf = L + exp(-dt / tau) * (Lf_prev - L),  Lf = L at the first frame.
+ *     0: off.
+ *   With saturation or bandwidth on, the comparator input is the FP32
+ *   rounding of the filtered log intensity (computed in FP64); they need
+ *   intensity frames (a handle without NSIM_INPUT_LOG).  Memory: 16 B per
+ *   pixel plus one FP32 log frame per frame of a launch.
+ *   noise_rate_hz: background-activity events per pixel per second: in every
+ *     frame interval each pixel adds a Poisson number of events with mean
+ *     rate * dt (at most 4) at uniform integer times in the interval, random
+ *     polarity; they bypass the refractory period and do not move the
+ *     reference level.  The draws come from Philox4x32-10 (Salmon et al.,
+ *     SC 2011) under the 64-bit noise_seed, counter (row-major pixel, frame
+ *     index (the initialising frame is 0) low and high words, j): j = 0 gives
+ *     the count against thresholds floor(2^32 * P(K <= i)), j >= 1 event
+ *     j-1's time t_prev + 1 + floor(w0 * dt / 2^32) and polarity +1 iff bit
+ *     31 of w1.  A stream with noise runs the per-frame pipeline of
+ *     NSIM_ATOMIC_EMIT (sorted unless NSIM_ATOMIC_UNSORTED), whose (time,
+ *     pixel) sort keys order noise among signal events; at one (t, x, y)
+ *     signal events come first.  0: off.
+ * Streams with any of them on cannot be checkpointed (nsim_ev_get_state and
+ * nsim_ev_set_state return NSIM_EINVAL). */
+int nsim_ev_set_sensor(nsim_ev_t* h, float saturation, double bandwidth_tau_us,
+                       double noise_rate_hz, uint64_t noise_seed);
+
 /* Synchronise the stream and copy up to `cap` queued events, in output
  * order, to caller-owned device arrays (t: int64 microseconds, x, y: uint16,
  * p: int8 +1/-1).  *n_out (host) receives the number copied; the rest stay

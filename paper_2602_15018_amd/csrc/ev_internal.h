@@ -63,6 +63,8 @@ struct alignas(64) Header {
                           // interval or a lattice counter passed 2^30
     int32_t stage_full;   // 1: the staging pool could not hold a launch
     int64_t alloc;        // packed-event slots handed out in this launch
+    int64_t frame_count;  // frames committed, the initialising frame included
+                          // (the index of the next frame: noise counter)
     // diagnostic counters (summed over launches; filled only in builds with
     // NSIM_STEP_DIAG): 0 FP64 count evaluations (lanes), 1 FP64 timestamp
     // evaluations (events), 2 waves regenerated after staging overflow,
@@ -221,6 +223,15 @@ struct AtomicArgs {
     uint16_t* q_y;
     int8_t* q_p;
     int64_t qcap;
+    // background-activity noise (sensor non-ideality): Poisson count per
+    // pixel and frame interval from Philox4x32-10 under `noise_key`, counter
+    // (row-major pixel, frame index low, high, j); thresholds floor(2^32 *
+    // P(K <= i)) for the interval's mean; the frame index is read from the
+    // header (frames committed)
+    int32_t noise;
+    uint32_t noise_key[2];
+    int32_t pad1;
+    uint64_t noise_T[4];
 };
 
 // Sorted atomic path: clears the look-back words of the tiles the step's
@@ -248,6 +259,8 @@ struct CommitArgs {
     int64_t* env_off;        // [n_env + 1] output offsets, or NULL
     const uint32_t* pref;    // per-wave exclusive prefix of the step
     const EnvRec* envs;
+    int32_t frames;          // frames of the launch (added to frame_count)
+    int32_t pad;
 };
 
 struct StateCopyArgs {
@@ -261,6 +274,30 @@ struct StateCopyArgs {
     uint8_t* buf;
 };
 
+// Sensor front-end (saturation, bandwidth low-pass) over K frames of one
+// launch: per pixel, clip at the full-well intensity, FP64 log, the
+// first-order filter with the interval's decay factor, and the FP32 log
+// frame the event kernels then read as log input.  The filter state is
+// ping-ponged like the pixel state (read [cur], written [cur ^ 1], the
+// commit flips cur); the initialising frame writes [cur] itself.
+struct FrontArgs {
+    const float* frames;   // [K][frame_stride] intensities
+    float* out;            // [K][frame_stride] FP32 log frames
+    int64_t frame_stride;
+    int32_t K;
+    int32_t nwaves;
+    const EnvRec* envs;
+    const int32_t* wave_env;
+    double* lp[2];         // filtered log intensity [P], ping-pong
+    Header* hdr;
+    double log_eps;
+    float sat;             // full-well intensity (+inf: no clipping)
+    int32_t first;         // 1: the initialising frame (K = 1)
+    int32_t bw;            // 1: low-pass filter on
+    int32_t pad;
+    double decay[kMaxFramesPerLaunch];  // exp(-dt_k / tau_bw) per frame
+};
+
 // Launchers (ev_kernels.hip).  Each returns the hipError_t of the launch.
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
@@ -272,6 +309,7 @@ hipError_t launch_commit(const CommitArgs& a, hipStream_t s);
 hipError_t launch_atomic_step(const AtomicArgs& a, bool log_input, bool has_map,
                               hipStream_t s);
 hipError_t launch_prep(const PrepArgs& a, hipStream_t s);
+hipError_t launch_frontend(const FrontArgs& a, hipStream_t s);
 hipError_t launch_reset_header(Header* hdr, uint32_t* hist, hipStream_t s);
 hipError_t launch_clear_status(Header* hdr, hipStream_t s);
 hipError_t launch_state_copy(const StateCopyArgs& a, hipStream_t s);

@@ -1226,7 +1226,10 @@ __global__ __launch_bounds__(kScanTile) void scan_kernel(const ScanArgs a) {
 __global__ void init_kernel(const InitArgs a) {
     const int cur = a.hdr->cur;
     const int pix = blockIdx.x * blockDim.x + threadIdx.x;
-    if (pix == 0) a.hdr->t_prev = a.t0;
+    if (pix == 0) {
+        a.hdr->t_prev = a.t0;
+        a.hdr->frame_count = 1;
+    }
     if (a.env_off && pix <= a.n_env) a.env_off[pix] = 0;  // no output yet
     const int wid = pix / kWave;
     if (wid >= a.nwaves) return;
@@ -1544,6 +1547,44 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
     }
 }
 
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds, each two
+// 32x32 -> 64-bit products with the published multipliers, the key bumped
+// by the published Weyl constants; c holds the counter in, the block out.
+__device__ __forceinline__ void philox4x32_10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
+        const uint32_t lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+        const uint32_t n0 = hi1 ^ c[1] ^ k0;
+        const uint32_t n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Background-activity events of one pixel and frame interval: how many
+// (counter word 3 = 0, inverse CDF), and event j's time offset in [1, dt]
+// and polarity (counter word 3 = j + 1).
+__device__ __forceinline__ int noise_count(const AtomicArgs& aa, uint32_t px, uint64_t fi) {
+    uint32_t c[4] = {px, (uint32_t)fi, (uint32_t)(fi >> 32), 0u};
+    philox4x32_10(c, aa.noise_key[0], aa.noise_key[1]);
+    const uint64_t u = c[0];
+    return (int)(u >= aa.noise_T[0]) + (int)(u >= aa.noise_T[1]) +
+           (int)(u >= aa.noise_T[2]) + (int)(u >= aa.noise_T[3]);
+}
+
+__device__ __forceinline__ int noise_event(const AtomicArgs& aa, uint32_t px, uint64_t fi,
+                                           int j, int dt, bool& up) {
+    uint32_t c[4] = {px, (uint32_t)fi, (uint32_t)(fi >> 32), (uint32_t)(j + 1)};
+    philox4x32_10(c, aa.noise_key[0], aa.noise_key[1]);
+    up = (c[1] >> 31) != 0u;
+    return 1 + (int)(((uint64_t)c[0] * (uint64_t)(uint32_t)dt) >> 32);
+}
+
 // ---- the paper's kernel design, as an A/B -------------------------------
 //
 // One launch per frame; every lane takes one pixel: it decides its
@@ -1629,6 +1670,11 @@ __global__ __launch_bounds__(256) void atomic_step_kernel(const AtomicArgs aa) {
                 ++e;
             }
         }
+        // background noise events of this pixel and interval (not filtered,
+        // written after the pixel's signal events)
+        const uint64_t fi = (uint64_t)hdr->frame_count;
+        const int nn = (aa.noise && valid) ? noise_count(aa, (uint32_t)local, fi) : 0;
+        e += nn;
         // one atomic per wave
         const uint64_t lt = lanemask_lt();
         int excl, total;
@@ -1676,6 +1722,27 @@ __global__ __launch_bounds__(256) void atomic_step_kernel(const AtomicArgs aa) {
             }
             ++pos;
         }
+        for (int j = 0; j < nn; ++j) {
+            bool nup;
+            const int tt = noise_event(aa, (uint32_t)local, fi, j, ts.dt, nup);
+            if (pos < room) {
+                if (aa.sorted) {
+                    const uint32_t key = ((uint32_t)tt << aa.pbits) | (uint32_t)pix;
+                    aa.dkey[pos] = key;
+                    aa.dval[pos] = ((uint32_t)pix << 1) | (nup ? 1u : 0u);
+                    for (int p = 0; p < aa.npass; ++p)
+                        atomicAdd(&s_h[p * kDigits + ((key >> (kDigitBits * p)) & (kDigits - 1))],
+                                  1u);
+                } else {
+                    int64_t r = (tail + pos) % aa.qcap;
+                    aa.q_t[r] = a.T0 + (int64_t)tt;
+                    aa.q_x[r] = (uint16_t)x;
+                    aa.q_y[r] = (uint16_t)y;
+                    aa.q_p[r] = nup ? (int8_t)1 : (int8_t)-1;
+                }
+            }
+            ++pos;
+        }
         // commit-candidate state
         if (valid) {
             const int nxt = cur ^ 1;
@@ -1697,6 +1764,30 @@ __global__ __launch_bounds__(256) void atomic_step_kernel(const AtomicArgs aa) {
         for (int i = threadIdx.x; i < aa.npass * kDigits; i += blockDim.x)
             if (s_h[i]) atomicAdd(&aa.hist[i], s_h[i]);
     }
+}
+
+// Sensor front-end over a launch's frames (saturation, log, first-order
+// low-pass in FP64, FP32 log frame out); one thread per pixel, frames in
+// order.  Skipped once a step has failed (nothing more is committed).
+__global__ __launch_bounds__(256) void frontend_kernel(const FrontArgs a) {
+    if (a.hdr->status != 0) return;
+    const int cur = a.hdr->cur;
+    const int pix = blockIdx.x * blockDim.x + threadIdx.x;
+    const int wid = pix / kWave;
+    if (wid >= a.nwaves) return;
+    const EnvRec er = a.envs[a.wave_env[wid]];
+    const int local = pix - er.wave0 * kWave;
+    if (local >= er.npix) return;
+    double lp = a.first ? 0.0 : a.lp[cur][pix];
+    for (int k = 0; k < a.K; ++k) {
+        const int64_t i = (int64_t)k * a.frame_stride + er.frame_off + local;
+        const float v = a.frames[i];
+        const float Is = v > a.sat ? a.sat : v;
+        const double L = log((double)Is + a.log_eps);
+        lp = (a.first || !a.bw) ? L : L + a.decay[k] * (lp - L);
+        a.out[i] = (float)lp;
+    }
+    a.lp[a.first ? cur : cur ^ 1][pix] = lp;
 }
 
 __global__ void prep_kernel(const PrepArgs a) {
@@ -1729,6 +1820,7 @@ __global__ void commit_kernel(const CommitArgs a) {
             h->cur ^= 1;
             h->t_prev = a.t_last;
             h->events_total += n;
+            h->frame_count += a.frames;
         } else if (h->status == 0) {
             h->status = h->internal_err ? -5 : -3;
             h->dropped_t = a.t_first;
@@ -1762,6 +1854,7 @@ __global__ void reset_kernel(Header* h, uint32_t* hist) {
         h->internal_err = 0;
         h->alloc = 0;
         h->stage_full = 0;
+        h->frame_count = 0;
     }
     for (int i = threadIdx.x; i < kMaxPasses * kDigits; i += blockDim.x) hist[i] = 0u;
 }
@@ -1929,6 +2022,14 @@ hipError_t launch_atomic_step(const AtomicArgs& a, bool log_input, bool has_map,
         else
             hipLaunchKernelGGL((atomic_step_kernel<false, false>), grid, block, 0, s, a);
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_frontend(const FrontArgs& a, hipStream_t s) {
+    if (a.K < 1 || a.K > kMaxFramesPerLaunch || (a.first && a.K != 1))
+        return hipErrorInvalidValue;
+    const int blocks = (a.nwaves * kWave + 255) / 256;
+    hipLaunchKernelGGL(frontend_kernel, dim3(blocks > 0 ? blocks : 1), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <cstdio>
 #include <new>
 #include <string>
@@ -92,6 +93,17 @@ struct nsim_ev {
     uint32_t* pass_ctr = nullptr;
     int64_t* env_off = nullptr;               // batched: [n_env + 1]
 
+    // sensor non-idealities (single streams; all off by default)
+    bool fe = false;                  // saturation or bandwidth on
+    bool noise = false;
+    float sat = INFINITY;             // full-well intensity
+    double bw_tau = 0.0;              // low-pass time constant (us)
+    double noise_rate_us = 0.0;       // background events per pixel per us
+    uint32_t noise_key[2] = {0u, 0u};
+    double* lp[2] = {nullptr, nullptr};   // filtered log intensity, ping-pong
+    float* fe_buf = nullptr;          // [fe_frames][frame_stride] log frames
+    int32_t fe_frames = 0;
+
     // host side
     Header* hdr_host = nullptr;   // pinned
     int64_t* xfer_host = nullptr; // pinned scalar for head / state time
@@ -172,7 +184,8 @@ void free_all(nsim_ev* h) {
                     h->skey[1], h->sval[0], h->sval[1], h->q_t, h->q_x,
                     h->q_y, h->q_p, h->stage_key, h->seg_slots, h->seg_base,
                     h->seg_count, h->pref, h->scan_status, h->hist,
-                    h->pass_status, h->pass_ctr, h->env_off};
+                    h->pass_status, h->pass_ctr, h->env_off, h->lp[0], h->lp[1],
+                    h->fe_buf};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hdr_host) (void)hipHostFree(h->hdr_host);
@@ -424,6 +437,7 @@ void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
     ca.env_off = h->batched ? h->env_off : nullptr;
     ca.pref = h->pref;
     ca.envs = h->envs;
+    ca.frames = kl;
 }
 
 // Enqueue a launch sequence with ordinary launches.  With `ev` set, HIP
@@ -432,7 +446,7 @@ hipError_t enqueue_direct(nsim_ev* h, const LaunchSet& L, hipStream_t s,
                           std::pair<hipEvent_t, hipEvent_t>* ev) {
     hipError_t e;
     if (ev && (e = hipEventRecord(ev->first, s)) != hipSuccess) return e;
-    if ((e = nsim::launch_step(L.step, h->log_input, h->has_map,
+    if ((e = nsim::launch_step(L.step, h->log_input || h->fe, h->has_map,
                                h->waves_per_block, h->step_blocks, s)) !=
         hipSuccess)
         return e;
@@ -690,11 +704,43 @@ int check_times(nsim_ev* h, const int64_t* t_us, int32_t K) {
     return NSIM_OK;
 }
 
+// Sensor front-end over kl frames whose times are t_us[0..kl) after T0 (the
+// initialising frame: first = true, kl = 1); the log frames land in fe_buf.
+hipError_t enqueue_frontend(nsim_ev* h, const float* frames, const int64_t* t_us,
+                            int32_t kl, int64_t T0, bool first) {
+    nsim::FrontArgs fa{};
+    fa.frames = frames;
+    fa.out = h->fe_buf;
+    fa.frame_stride = h->frame_stride;
+    fa.K = kl;
+    fa.nwaves = h->nwaves;
+    fa.envs = h->envs;
+    fa.wave_env = h->wave_env;
+    fa.lp[0] = h->lp[0];
+    fa.lp[1] = h->lp[1];
+    fa.hdr = h->hdr;
+    fa.log_eps = h->log_eps;
+    fa.sat = h->sat;
+    fa.first = first ? 1 : 0;
+    fa.bw = h->bw_tau > 0.0 ? 1 : 0;
+    int64_t tp = T0;
+    for (int32_t k = 0; k < kl; ++k) {
+        fa.decay[k] = fa.bw ? std::exp(-(double)(t_us[k] - tp) / h->bw_tau) : 0.0;
+        tp = t_us[k];
+    }
+    return nsim::launch_frontend(fa, h->stream);
+}
+
 hipError_t enqueue_init(nsim_ev* h, const float* frame, int64_t t0) {
+    if (h->fe) {
+        const hipError_t e = enqueue_frontend(h, frame, &t0, 1, t0, true);
+        if (e != hipSuccess) return e;
+        frame = h->fe_buf;
+    }
     nsim::InitArgs ia{};
     ia.frame = frame;
     ia.nwaves = h->nwaves;
-    ia.flags = h->flags;
+    ia.flags = h->fe ? (h->flags | NSIM_INPUT_LOG) : h->flags;
     ia.envs = h->envs;
     ia.wave_env = h->wave_env;
     ia.log_eps = h->log_eps;
@@ -720,8 +766,24 @@ void count_launch(nsim_ev* h, const LaunchSet& L) {
 // The paper's kernel design (NSIM_ATOMIC_EMIT): one launch per frame; the
 // atomic step kernel, then (sorted) the preparation kernel and the radix
 // passes over the combined (time offset, pixel) key, then the commit.
+// Inverse-CDF thresholds of a Poisson count with mean lambda, as 32-bit
+// fixed point: T[i] = floor(2^32 * P(K <= i)), i = 0..3.
+void noise_thresholds(double lambda, uint64_t T[4]) {
+    double term = std::exp(-lambda), cdf = 0.0;
+    for (int i = 0; i < 4; ++i) {
+        if (i > 0) term = term * lambda / (double)i;
+        cdf += term;
+        const double v = std::floor(cdf * 4294967296.0);
+        T[i] = v >= 4294967296.0 ? 4294967296ull : (uint64_t)v;
+    }
+}
+
 int enqueue_atomic(nsim_ev* h, const float* frame, const int64_t* t_us, int64_t T0) {
     const bool sorted = (h->flags & NSIM_ATOMIC_UNSORTED) == 0;
+    if (h->fe) {
+        NSIM_HIP(h, enqueue_frontend(h, frame, t_us, 1, T0, false));
+        frame = h->fe_buf;
+    }
     LaunchSet L;
     build_launch(h, L, frame, t_us, 1, T0, false, own_scratch(h));
     const int pbits = bits_for((int64_t)h->nwaves * nsim::kWave - 1);
@@ -745,13 +807,20 @@ int enqueue_atomic(nsim_ev* h, const float* frame, const int64_t* t_us, int64_t 
     aa.q_y = h->q_y;
     aa.q_p = h->q_p;
     aa.qcap = h->qcap;
+    if (h->noise) {
+        aa.noise = 1;
+        aa.noise_key[0] = h->noise_key[0];
+        aa.noise_key[1] = h->noise_key[1];
+        noise_thresholds(h->noise_rate_us * (double)(t_us[0] - T0), aa.noise_T);
+    }
     std::pair<hipEvent_t, hipEvent_t> ev{nullptr, nullptr};
     if (h->profiling) {
         NSIM_HIP(h, get_event(h, &ev.first));
         NSIM_HIP(h, get_event(h, &ev.second));
         NSIM_HIP(h, hipEventRecord(ev.first, h->stream));
     }
-    NSIM_HIP(h, nsim::launch_atomic_step(aa, h->log_input, h->has_map, h->stream));
+    NSIM_HIP(h, nsim::launch_atomic_step(aa, h->log_input || h->fe, h->has_map,
+                                         h->stream));
     if (h->profiling) {
         NSIM_HIP(h, hipEventRecord(ev.second, h->stream));
         h->pending.push_back(ev);
@@ -796,7 +865,9 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
     int rc = check_times(h, t_us, K);
     if (rc) return rc;
     DeviceGuard dg(h->device);
-    if (h->flags & NSIM_ATOMIC_EMIT) {
+    // the paper's per-frame design, or background noise (whose events need
+    // the (time, pixel) keys of that pipeline's sort)
+    if ((h->flags & NSIM_ATOMIC_EMIT) || h->noise) {
         int32_t k = 0;
         const int64_t P = h->frame_stride;
         if (!h->initialized) {
@@ -835,12 +906,18 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
             ++kl;
         }
         if (kl == 0) kl = 1;  // a single frame always fits (gap < 2^25)
+        const float* fr = frames + (int64_t)k * P;
+        if (h->fe) {
+            NSIM_HIP(h, enqueue_frontend(h, fr, t_us + k, kl, T0, false));
+            fr = h->fe_buf;
+        }
         LaunchSet L;
-        build_launch(h, L, frames + (int64_t)k * P, t_us + k, kl, T0, false,
-                     own_scratch(h));
+        build_launch(h, L, fr, t_us + k, kl, T0, false, own_scratch(h));
         // launches of a frame or two are bound by launch latency: replay the
-        // captured sequence (one graph per key width and variant)
-        const bool graph = kl <= kGraphMaxFrames && !(h->flags & NSIM_DIRECT_LAUNCH);
+        // captured sequence (one graph per key width and variant; not with
+        // the sensor front-end, which runs before each launch)
+        const bool graph = kl <= kGraphMaxFrames && !(h->flags & NSIM_DIRECT_LAUNCH) &&
+                           !h->fe;
         rc = enqueue(h, L, graph);
         if (rc) return rc;
         count_launch(h, L);
@@ -1181,6 +1258,58 @@ int nsim_ev_committed_time(nsim_ev_t* h, int64_t* t_us) {
     return st;
 }
 
+int nsim_ev_set_sensor(nsim_ev_t* h, float saturation, double bandwidth_tau_us,
+                       double noise_rate_hz, uint64_t noise_seed) {
+    if (!h) return NSIM_EINVAL;
+    if (h->batched) return fail(h, NSIM_EINVAL, "sensor settings: single streams only");
+    if (h->initialized)
+        return fail(h, NSIM_EINVAL, "sensor settings must precede the first step");
+    if (!(saturation > 0.0f) || !(bandwidth_tau_us >= 0.0) ||
+        !std::isfinite(bandwidth_tau_us) || !(noise_rate_hz >= 0.0) ||
+        !std::isfinite(noise_rate_hz))
+        return fail(h, NSIM_EINVAL, "sensor settings out of range");
+    const bool fe = !std::isinf(saturation) || bandwidth_tau_us > 0.0;
+    if (fe && h->log_input)
+        return fail(h, NSIM_EINVAL,
+                    "saturation and bandwidth need intensity input, not log frames");
+    if (h->fe != fe || h->fe_frames == 0) {
+        DeviceGuard dg(h->device);
+        for (int i = 0; i < 2; ++i) {
+            if (h->lp[i]) (void)hipFree(h->lp[i]);
+            h->lp[i] = nullptr;
+        }
+        if (h->fe_buf) (void)hipFree(h->fe_buf);
+        h->fe_buf = nullptr;
+        h->fe_frames = 0;
+        if (fe) {
+            const int64_t npad = (int64_t)h->nwaves * nsim::kWave;
+            const int32_t kmax = std::max<int32_t>(
+                h->max_frames > 0 ? h->max_frames : nsim::kAutoFramesPerLaunch, 1);
+            hipError_t e = dmalloc(&h->lp[0], npad);
+            if (e == hipSuccess) e = dmalloc(&h->lp[1], npad);
+            if (e == hipSuccess) e = dmalloc(&h->fe_buf, (size_t)kmax * h->frame_stride);
+            if (e != hipSuccess) {
+                for (int i = 0; i < 2; ++i) {
+                    if (h->lp[i]) (void)hipFree(h->lp[i]);
+                    h->lp[i] = nullptr;
+                }
+                if (h->fe_buf) (void)hipFree(h->fe_buf);
+                h->fe_buf = nullptr;
+                return fail(h, NSIM_ENOMEM, "sensor front-end buffers");
+            }
+            h->fe_frames = kmax;
+        }
+    }
+    h->fe = fe;
+    h->sat = saturation;
+    h->bw_tau = bandwidth_tau_us;
+    h->noise = noise_rate_hz > 0.0;
+    h->noise_rate_us = noise_rate_hz * 1e-6;
+    h->noise_key[0] = (uint32_t)noise_seed;
+    h->noise_key[1] = (uint32_t)(noise_seed >> 32);
+    return NSIM_OK;
+}
+
 int nsim_ev_reset(nsim_ev_t* h) {
     if (!h) return NSIM_EINVAL;
     DeviceGuard dg(h->device);
@@ -1211,6 +1340,9 @@ int64_t nsim_ev_state_bytes(const nsim_ev_t* h) {
 
 int nsim_ev_get_state(nsim_ev_t* h, void* dev_buf, int64_t bytes) {
     if (!h) return NSIM_EINVAL;
+    if (h->fe || h->noise)
+        return fail(h, NSIM_EINVAL,
+                    "no checkpoint of a stream with sensor non-idealities");
     if (!dev_buf || bytes < nsim_ev_state_bytes(h))
         return fail(h, NSIM_EINVAL, "state buffer too small or null");
     if (!h->initialized)
@@ -1233,6 +1365,9 @@ int nsim_ev_get_state(nsim_ev_t* h, void* dev_buf, int64_t bytes) {
 
 int nsim_ev_set_state(nsim_ev_t* h, const void* dev_buf, int64_t bytes) {
     if (!h) return NSIM_EINVAL;
+    if (h->fe || h->noise)
+        return fail(h, NSIM_EINVAL,
+                    "no checkpoint of a stream with sensor non-idealities");
     if (!dev_buf || bytes < nsim_ev_state_bytes(h))
         return fail(h, NSIM_EINVAL, "state buffer too small or null");
     DeviceGuard dg(h->device);

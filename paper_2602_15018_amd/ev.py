@@ -145,7 +145,8 @@ EXPORTED = [
     "nsim_ev_sync", "nsim_ev_pending", "nsim_ev_committed_time",
     "nsim_ev_reset", "nsim_ev_destroy", "nsim_ev_last_error",
     "nsim_ev_state_bytes", "nsim_ev_get_state", "nsim_ev_set_state",
-    "nsim_ev_set_profiling", "nsim_ev_get_stats", "nsim_diag_fast_log2",
+    "nsim_ev_set_profiling", "nsim_ev_get_stats", "nsim_ev_set_sensor",
+    "nsim_diag_fast_log2",
     "nsim_diag_stream",
     "nsim_evb_create", "nsim_evb_step", "nsim_evb_drain", "nsim_evb_events",
     "nsim_evb_sync", "nsim_evb_reset", "nsim_evb_destroy",
@@ -186,6 +187,8 @@ def load_library(path: str = _LIB_PATH):
         "nsim_ev_set_state": ([vp, vp, i64], c_int),
         "nsim_ev_set_profiling": ([vp, c_int], c_int),
         "nsim_ev_get_stats": ([vp, ctypes.POINTER(Stats)], c_int),
+        "nsim_ev_set_sensor": ([vp, ctypes.c_float, ctypes.c_double,
+                                ctypes.c_double, ctypes.c_uint64], c_int),
         "nsim_diag_fast_log2": ([vp, vp, i64, vp], c_int),
         "nsim_diag_stream": ([vp, vp, i64, i32, vp], c_int),
         "nsim_evb_create": ([ctypes.POINTER(_EnvDesc), i32,
@@ -234,7 +237,8 @@ class EventSim:
                  c_neg_map=None, log_eps=1e-3, refractory_us=0,
                  capacity_events=1 << 22, input_is_log=False,
                  force_fp64=False, max_frames_per_launch=0, stream=None,
-                 direct_launch=False, emit="ordered"):
+                 direct_launch=False, emit="ordered", saturation=None,
+                 bandwidth_tau_us=0.0, noise_rate_hz=0.0, noise_seed=0):
         import torch
 
         if not torch.cuda.is_available():
@@ -277,6 +281,11 @@ class EventSim:
         if rc != NSIM_OK:
             raise NsimError(rc, "nsim_ev_create rejected the configuration")
         self._h = h
+        if saturation is not None or bandwidth_tau_us or noise_rate_hz:
+            sat = float("inf") if saturation is None else float(saturation)
+            self._check(self._lib.nsim_ev_set_sensor(
+                self._h, sat, float(bandwidth_tau_us), float(noise_rate_hz),
+                int(noise_seed) & ((1 << 64) - 1)))
 
     # -- helpers
     def _check(self, rc):
