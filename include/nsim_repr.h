@@ -80,6 +80,25 @@ int nsim_ts_update(double* S, int64_t* t_last, int32_t width, int32_t height,
                    void* workspace, int64_t workspace_bytes,
                    int64_t* n_skipped, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * update as nsim_ts_update, with the workspace taken from a static device
+ * array of this library instead of an argument.  It allocates nothing
+ * (no hipMalloc, hipFree or allocating library call).
+ * Limit: 2 * width * height <= NSIM_TS_NOALLOC_MAX_ENTRIES (2^21 entries:
+ * up to 1280 x 720 and beyond); larger sensors return NSIM_EINVAL.  Each
+ * device holds one copy of the array (32 MiB) from the library's first use
+ * on it until the process ends.  Every call on a device shares that copy:
+ * calls that overlap on one device (several streams or host threads) race
+ * and must be serialised by the caller.  The array is cleared by each call
+ * before use; results equal nsim_ts_update's bit for bit. */
+#define NSIM_TS_NOALLOC_MAX_ENTRIES (1 << 21)
+int nsim_ts_update_noalloc(double* S, int64_t* t_last, int32_t width,
+                           int32_t height, double tau_us, const int64_t* t,
+                           const uint16_t* x, const uint16_t* y,
+                           const int8_t* p, int64_t n, int64_t* n_skipped,
+                           void* stream);
+
 /* Readout of a time surface at time T (microseconds): out[e] = S[e] *
  * exp(-(T - t_last[e]) / tau_us), 0 where t_last[e] == NSIM_TS_NEVER.
  * out: device float [2][height][width], overwritten. */

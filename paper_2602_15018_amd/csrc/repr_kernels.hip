@@ -19,6 +19,8 @@
 
 #include <stdint.h>
 
+#include <mutex>
+
 #include "nsim_repr.h"
 
 namespace {
@@ -163,6 +165,32 @@ __global__ __launch_bounds__(kThreads) void frames_kernel(Ev ev, int64_t n, int3
         atomicAdd((unsigned long long*)n_skipped, (unsigned long long)skipped);
 }
 
+// Workspace of nsim_ts_update_noalloc: a static array of this library, one
+// copy per device (2 x 2^21 words, 32 MiB, held until the process ends).
+// Host code never passes its name to a kernel (on the host the name is only
+// a stand-in); it uses the device address looked up once per device.
+constexpr int64_t kNoallocMaxEntries = NSIM_TS_NOALLOC_MAX_ENTRIES;
+static __device__ __align__(256) uint64_t scratch[2 * kNoallocMaxEntries];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of `scratch` on the current device (looked up on the
+// first call per device, with that device current), or nullptr.
+void* scratch_address() {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
+
 int grid_for(int64_t n) {
     const int64_t b = (n + kThreads - 1) / kThreads;
     return (int)(b < 1 ? 1 : (b > kMaxBlocks ? kMaxBlocks : b));
@@ -170,6 +198,31 @@ int grid_for(int64_t n) {
 
 bool valid_size(int32_t W, int32_t H) {
     return W >= 1 && H >= 1 && W <= 65535 && H <= 65535;
+}
+
+// The update's four launches on a workspace of 2 x entries words (the fill
+// kernel clears it first, so its contents on entry do not matter).
+int enqueue_ts_update(double* S, int64_t* t_last, int32_t width, int32_t height,
+                      double tau_us, const int64_t* t, const uint16_t* x,
+                      const uint16_t* y, const int8_t* p, int64_t n, uint64_t* ws,
+                      int64_t* n_skipped, hipStream_t s) {
+    if (!t || !x || !y || !p) return NSIM_EINVAL;
+    const int64_t entries = 2 * (int64_t)width * height;
+    uint64_t* tmax = ws;
+    uint64_t* acc = ws + entries;
+    const Ev ev{t, x, y, p};
+    const double inv_tau = 1.0 / tau_us;
+    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(2 * entries)), dim3(kThreads), 0, s,
+                       tmax, 2 * entries);
+    hipLaunchKernelGGL(ts_max_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, ev, n,
+                       width, height, (const int64_t*)t_last, tmax, n_skipped);
+    hipLaunchKernelGGL(ts_sum_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, ev, n,
+                       width, height, inv_tau, (const int64_t*)t_last,
+                       (const uint64_t*)tmax, acc);
+    hipLaunchKernelGGL(ts_final_kernel, dim3(grid_for(entries)), dim3(kThreads), 0, s,
+                       entries, inv_tau, S, t_last, (const uint64_t*)tmax,
+                       (const uint64_t*)acc);
+    return hipGetLastError() == hipSuccess ? NSIM_OK : NSIM_EHIP;
 }
 
 }  // namespace
@@ -188,27 +241,27 @@ int nsim_ts_update(double* S, int64_t* t_last, int32_t width, int32_t height,
     if (!valid_size(width, height) || !(tau_us > 0.0) || n < 0 || !S || !t_last)
         return NSIM_EINVAL;
     if (n == 0) return NSIM_OK;
-    if (!t || !x || !y || !p || !workspace ||
-        workspace_bytes < nsim_ts_workspace_bytes(width, height) ||
+    if (!workspace || workspace_bytes < nsim_ts_workspace_bytes(width, height) ||
         ((uintptr_t)workspace % 8) != 0)
         return NSIM_EINVAL;
-    const int64_t entries = 2 * (int64_t)width * height;
-    uint64_t* tmax = static_cast<uint64_t*>(workspace);
-    uint64_t* acc = tmax + entries;
-    const hipStream_t s = static_cast<hipStream_t>(stream);
-    const Ev ev{t, x, y, p};
-    const double inv_tau = 1.0 / tau_us;
-    hipLaunchKernelGGL(fill_kernel, dim3(grid_for(2 * entries)), dim3(kThreads), 0, s,
-                       tmax, 2 * entries);
-    hipLaunchKernelGGL(ts_max_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, ev, n,
-                       width, height, (const int64_t*)t_last, tmax, n_skipped);
-    hipLaunchKernelGGL(ts_sum_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, ev, n,
-                       width, height, inv_tau, (const int64_t*)t_last,
-                       (const uint64_t*)tmax, acc);
-    hipLaunchKernelGGL(ts_final_kernel, dim3(grid_for(entries)), dim3(kThreads), 0, s,
-                       entries, inv_tau, S, t_last, (const uint64_t*)tmax,
-                       (const uint64_t*)acc);
-    return hipGetLastError() == hipSuccess ? NSIM_OK : NSIM_EHIP;
+    return enqueue_ts_update(S, t_last, width, height, tau_us, t, x, y, p, n,
+                             static_cast<uint64_t*>(workspace), n_skipped,
+                             static_cast<hipStream_t>(stream));
+}
+
+int nsim_ts_update_noalloc(double* S, int64_t* t_last, int32_t width, int32_t height,
+                           double tau_us, const int64_t* t, const uint16_t* x,
+                           const uint16_t* y, const int8_t* p, int64_t n,
+                           int64_t* n_skipped, void* stream) {
+    if (!valid_size(width, height) || !(tau_us > 0.0) || n < 0 || !S || !t_last)
+        return NSIM_EINVAL;
+    if (2 * (int64_t)width * height > kNoallocMaxEntries) return NSIM_EINVAL;
+    if (n == 0) return NSIM_OK;
+    void* ws = scratch_address();
+    if (!ws) return NSIM_EHIP;
+    return enqueue_ts_update(S, t_last, width, height, tau_us, t, x, y, p, n,
+                             static_cast<uint64_t*>(ws), n_skipped,
+                             static_cast<hipStream_t>(stream));
 }
 
 int nsim_ts_read(const double* S, const int64_t* t_last, int32_t width, int32_t height,

@@ -18,8 +18,8 @@ NSIM_TS_NEVER = -(1 << 63)
 
 # Names every build must export (the declarations of include/nsim_repr.h).
 EXPORTED = [
-    "nsim_ts_workspace_bytes", "nsim_ts_update", "nsim_ts_read",
-    "nsim_event_frames",
+    "nsim_ts_workspace_bytes", "nsim_ts_update", "nsim_ts_update_noalloc",
+    "nsim_ts_read", "nsim_event_frames",
 ]
 
 _lib = None
@@ -44,6 +44,8 @@ def load_library(path: str = _LIB_PATH):
         "nsim_ts_workspace_bytes": ([i32, i32], i64),
         "nsim_ts_update": ([vp, vp, i32, i32, f64, vp, vp, vp, vp, i64, vp,
                             i64, vp, vp], c_int),
+        "nsim_ts_update_noalloc": ([vp, vp, i32, i32, f64, vp, vp, vp, vp,
+                                    i64, vp, vp], c_int),
         "nsim_ts_read": ([vp, vp, i32, i32, f64, i64, vp, vp], c_int),
         "nsim_event_frames": ([vp, vp, vp, vp, i64, i32, i32, i64, i64, i32,
                                vp, vp, vp], c_int),
@@ -103,6 +105,17 @@ def ts_update(S, t_last, width, height, tau_us, events, workspace,
         int(workspace.numel() * workspace.element_size()), _ptr(n_skipped),
         _stream())
     _check(rc, "nsim_ts_update")
+
+
+def ts_update_noalloc(S, t_last, width, height, tau_us, events,
+                      n_skipped=None):
+    """ts_update with the library's static workspace (allocates nothing)."""
+    lib = _require_device()
+    t, x, y, p, n = _events(events)
+    rc = lib.nsim_ts_update_noalloc(
+        _ptr(S), _ptr(t_last), width, height, float(tau_us), _ptr(t),
+        _ptr(x), _ptr(y), _ptr(p), n, _ptr(n_skipped), _stream())
+    _check(rc, "nsim_ts_update_noalloc")
 
 
 def ts_read(S, t_last, width, height, tau_us, T, out):
