@@ -75,14 +75,22 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-frames-per-launch", type=int, default=0)
     ap.add_argument("--workload", default="hd",
-                    choices=["hd", "vga", "dvs", "perframe", "batch64", "learned"],
+                    choices=["hd", "vga", "dvs", "perframe", "batch64", "learned",
+                             "repr"],
                     help="hd: the 1280x720 stream (default); vga, dvs: the "
                          "640x480 and 240x180 streams; perframe: one frame "
                          "per call at 640x480 and 1280x720 (kHz); batch64: 64 "
                          "environments of uneven size stepped together, "
                          "against the same environments as separate streams; "
                          "learned: train the upsampler, then 125-FPS frames "
-                         "-> upsampler -> events against the 1000-FPS path")
+                         "-> upsampler -> events against the 1000-FPS path; "
+                         "repr: time surface (10 ms steps) and 20 ms polarity "
+                         "frames of the 640x480 stream's events")
+    ap.add_argument("--sensor", default="",
+                    help="stream workloads: sensor non-idealities, a comma "
+                         "list of saturation=I, bandwidth_tau_us=T, "
+                         "noise_rate_hz=R, noise_seed=S (e.g. "
+                         "saturation=0.9,bandwidth_tau_us=200,noise_rate_hz=1)")
     ap.add_argument("--emit", default="ordered",
                     choices=["ordered", "atomic", "atomic_unsorted"],
                     help="stream workloads: the ordered path (default) or the "
@@ -147,7 +155,7 @@ def cpu_info():
             "cpus_allowed": len(os.sched_getaffinity(0))}
 
 
-def cpu_baseline(frames_dev, t, cp, cn, w, n_intervals):
+def cpu_baseline(frames_dev, t, cp, cn, w, n_intervals, sensor=None):
     """Time the FP64 oracle on one host core (this thread pinned to the
     first CPU it may use, restored afterwards) on the first n_intervals
     frame intervals of the same stream at full resolution: the event
@@ -163,7 +171,7 @@ def cpu_baseline(frames_dev, t, cp, cn, w, n_intervals):
     try:
         s = oracle.OracleStream(w.width, w.height, cp, cn, w.log_eps,
                                 w.refractory_us, fragile_band_L=0.0,
-                                fragile_band_tau=0.0)
+                                fragile_band_tau=0.0, **(sensor or {}))
         s.step(fr[:1], t[:1])  # initialisation frame, not timed
         t0 = time.perf_counter()
         s.step(fr[1:], t[1: n + 1])
@@ -544,8 +552,21 @@ def bench_learned(args):
     print(json.dumps(result), flush=True)
 
 
+def sensor_settings(spec):
+    """--sensor a=v,b=v -> EventSim keyword arguments."""
+    out = {}
+    for item in filter(None, (spec or "").split(",")):
+        k, v = item.split("=")
+        k = k.strip()
+        if k not in ("saturation", "bandwidth_tau_us", "noise_rate_hz",
+                     "noise_seed"):
+            raise SystemExit("unknown sensor setting %r" % k)
+        out[k] = int(v) if k == "noise_seed" else float(v)
+    return out
+
+
 def make_sim(w, F, cp, cn, max_frames_per_launch=0, direct_launch=False,
-             emit="ordered"):
+             emit="ordered", sensor=None):
     """The event path exactly as the benchmark times it: queue sized for the
     whole stream, default frames per launch unless overridden."""
     from paper_2602_15018_amd.ev import EventSim
@@ -557,7 +578,7 @@ def make_sim(w, F, cp, cn, max_frames_per_launch=0, direct_launch=False,
                    log_eps=w.log_eps, refractory_us=w.refractory_us,
                    capacity_events=cap,
                    max_frames_per_launch=max_frames_per_launch,
-                   direct_launch=direct_launch, emit=emit)
+                   direct_launch=direct_launch, emit=emit, **(sensor or {}))
     return sim, cap
 
 
@@ -591,7 +612,9 @@ def bench_stream(args, dev):
         log("streaming kernel: read %.0f GB/s, copy %.0f GB/s" % (
             ceiling["read"], ceiling["copy"]))
 
-    sim, cap = make_sim(w, F, cp, cn, args.max_frames_per_launch, emit=args.emit)
+    sensor = sensor_settings(args.sensor)
+    sim, cap = make_sim(w, F, cp, cn, args.max_frames_per_launch, emit=args.emit,
+                        sensor=sensor)
     out = (torch.empty(cap, dtype=torch.int64, device=dev),
            torch.empty(cap, dtype=torch.uint16, device=dev),
            torch.empty(cap, dtype=torch.uint16, device=dev),
@@ -652,7 +675,9 @@ def bench_stream(args, dev):
             "fps": w.fps, "refractory_us": w.refractory_us,
             "threshold_mismatch": w.mismatch,
             "frames_per_launch": fpl,
-            "emit": args.emit,
+            "emit": ("atomic (per-frame pipeline: background noise)"
+                     if sensor.get("noise_rate_hz") else args.emit),
+            "sensor": sensor or None,
         },
         "events_per_s": ev_step * args.steps / elapsed,
         "events_per_step": ev_step,
@@ -678,7 +703,7 @@ def bench_stream(args, dev):
         result["cpu_baseline"] = cpu_baseline(frames, t, cp if cp is not None
                                               else w.c_nominal,
                                               cn if cn is not None else w.c_nominal,
-                                              w, args.cpu_sample_frames)
+                                              w, args.cpu_sample_frames, sensor)
     print(json.dumps(result), flush=True)
 
 
@@ -787,6 +812,151 @@ def bench_perframe(args, dev):
     print(json.dumps(result), flush=True)
 
 
+def bench_repr(args, dev):
+    """Event representations of the 640x480 stream (1000 frames at 1000 FPS,
+    its events from the event path, resident before timing): the time
+    surface of the RL policy (tau = 10 ms) updated once per 10 ms control
+    step and read out after each step, and polarity event frames over 20 ms
+    windows.  One timed step = the whole stream's events through both."""
+    import torch
+
+    import oracle
+    from paper_2602_15018_amd import representations as rp
+    from paper_2602_15018_amd import scene
+
+    w = scene.WORKLOADS[STREAMS["vga"]]
+    F = args.frames or w.frames
+    frames, t, cp, cn = resident_frames(w, F, dev)
+    sim, cap = make_sim(w, F, cp, cn)
+    sim.step(frames, t)
+    ev = sim.drain()
+    sim.close()
+    del frames
+    torch.cuda.empty_cache()
+    n = int(ev[0].numel())
+    W, H = w.width, w.height
+    tau, step_us, window = 10_000.0, 10_000, 20_000
+    t0, t1 = int(t[0]), int(t[-1])
+    bounds = torch.searchsorted(
+        ev[0], torch.arange(t0, t1 + step_us, step_us, device=dev,
+                            dtype=torch.int64), right=True).cpu().tolist()
+    batches = [(a, b) for a, b in zip(bounds[:-1], bounds[1:])]
+    nf = (t1 - t0) // window
+    ts = rp.TimeSurface(W, H, tau, device=dev)
+    obs = torch.empty((2, H, W), dtype=torch.float32, device=dev)
+    counts = torch.zeros((nf, 2, H, W), dtype=torch.int32, device=dev)
+    ends = [t0 + step_us * (i + 1) for i in range(len(batches))]
+
+    def surface():
+        ts.S.zero_()
+        ts.t_last.fill_(rp.NSIM_TS_NEVER)
+        for (a, b), T in zip(batches, ends):
+            ts.update(tuple(x[a:b] for x in ev))
+            ts.read(T, out=obs)
+
+    def ev_frames():
+        counts.zero_()
+        rp.event_frames(ev, W, H, t0, window, nf, counts)
+
+    def timed(fn, reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(
+            enable_timing=True)
+        fn()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) * 1e-3 / reps
+
+    for _ in range(args.warmup):
+        surface()
+        ev_frames()
+    torch.cuda.synchronize()
+    w0 = time.perf_counter()
+    for _ in range(args.steps):
+        surface()
+        ev_frames()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - w0) / args.steps
+    t_surface = timed(surface, args.steps)
+    t_frames = timed(ev_frames, args.steps)
+    # time-surface updates alone, and their algorithmic bytes: every event
+    # read once (13 B), every entry it touches read and written (S, t_last:
+    # 32 B) -- per 10 ms batch
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(
+        enable_timing=True)
+    ts.S.zero_()
+    ts.t_last.fill_(rp.NSIM_TS_NEVER)
+    e0.record()
+    for (a, b) in batches:
+        ts.update(tuple(x[a:b] for x in ev))
+    e1.record()
+    e1.synchronize()
+    t_upd = e0.elapsed_time(e1) * 1e-3
+    ent = (ev[3] > 0).to(torch.int64) * (W * H) + ev[2].to(torch.int64) * W + \
+        ev[1].to(torch.int64)
+    touched = 0
+    for (a, b) in batches:
+        touched += int(torch.unique(ent[a:b]).numel())
+    alg_upd = 13.0 * n + 32.0 * touched
+    ach = alg_upd / t_upd / 1e9
+    # the oracle on one core over the first 100 ms of events
+    evh = tuple(x.cpu().numpy() for x in ev)
+    m = bounds[min(10, len(bounds) - 1)]
+    sample = oracle.Events(evh[0][:m], evh[1][:m].view(np.uint16),
+                           evh[2][:m].view(np.uint16), evh[3][:m])
+    allowed = os.sched_getaffinity(0)
+    os.sched_setaffinity(0, {min(allowed)})
+    try:
+        c0 = time.perf_counter()
+        ots = oracle.TimeSurface(W, H, tau)
+        for i in range(min(10, len(batches))):
+            a, b = batches[i]
+            ots.update(oracle.Events(*(x[a:b] for x in (
+                evh[0], evh[1].view(np.uint16), evh[2].view(np.uint16), evh[3]))))
+            ots.read(ends[i])
+        oracle.event_frames(sample, W, H, t0, window, 5)
+        c_el = time.perf_counter() - c0
+    finally:
+        os.sched_setaffinity(0, allowed)
+    result = {
+        "metric": METRIC,
+        "value": n / el / 1e9,
+        "unit": "Gevents/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "repr_" + STREAMS["vga"], "events": n,
+                   "tau_us": tau, "step_us": step_us, "window_us": window,
+                   "updates": len(batches), "frames": nf},
+        "ms_time_surface": t_surface * 1e3,
+        "ms_event_frames": t_frames * 1e3,
+        "roofline": {
+            "kernel": "time-surface update (clear, max, sum, final)",
+            "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+            "ms_updates": t_upd * 1e3, "alg_bytes": alg_upd,
+            "entries_touched": touched,
+        },
+        "cpu_baseline": {
+            "value": m / c_el / 1e9, "unit": "Gevents/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "first 100 ms of the stream's events (%d): 10 time-"
+                      "surface updates and readouts, 5 event frames, one "
+                      "pinned core" % m,
+            "seconds": c_el,
+        },
+    }
+    print(json.dumps(result), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -812,6 +982,8 @@ def main():
         bench_learned(args)
     elif args.workload == "perframe":
         bench_perframe(args, dev)
+    elif args.workload == "repr":
+        bench_repr(args, dev)
     else:
         bench_stream(args, dev)
 

@@ -284,8 +284,7 @@ struct LaunchSet {
     int32_t kl = 0;
 };
 
-// Per-launch scratch of a launch sequence: the handle's own allocation, or
-// the file-scope array of the allocation-free step.
+// Per-launch scratch of a launch sequence (the handle's own allocation).
 struct ScratchView {
     uint32_t* stage_key = nullptr;   // [nwaves * stage_entries + pool]
     int64_t stage_cap = 0;
