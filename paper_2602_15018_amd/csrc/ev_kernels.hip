@@ -1341,6 +1341,10 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
     int64_t n;
     if (!step_fits(a.hdr, a.scratch_cap, a.qcap, &n) || n == 0) return;
     const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    // tiles go to workgroups by ticket, so any number of them covers every
+    // tile: workgroups past the tile count leave at once (small launches,
+    // e.g. one frame, then do not pay for a full grid)
+    if ((int64_t)blockIdx.x >= ntiles) return;
     const int tid = threadIdx.x;
     const int w = tid / kWave;
     const int lane = lane_id();
@@ -1595,6 +1599,94 @@ __device__ __forceinline__ int noise_event(const AtomicArgs& aa, uint32_t px, ui
 // offsets are the ballot mask's prefix counts (mbcnt), otherwise a wave
 // scan.  The order of the blocks is the order in which waves reach the
 // atomic.
+// One pixel's crossings in a launch of one frame: the count, the levels'
+// bookkeeping, each crossing's timestamp (relative to T0) and the
+// refractory filter, with the ordered path's arithmetic (FP32 where a bound
+// decides, the FP64 definition otherwise).
+template <bool LOGIN>
+struct LaneFrame {
+    Px q;
+    float I, Ip;
+    int n, bad, f64count;
+    bool up, f64, have_d;
+    TsSetup ts;
+    double L0d, L1d;
+
+    template <bool MAP>
+    __device__ __forceinline__ void setup(const StepArgs& a, const int* s_toff, int cur,
+                                          int pix, int64_t sample, bool valid) {
+        load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
+                          MAP ? a.c_pos_map : nullptr, MAP ? a.c_neg_map : nullptr,
+                          a.c_pos, a.c_neg, pix, valid, a.log_eps);
+        I = valid ? __builtin_nontemporal_load(a.frames + sample) : 1.0f;
+        Ip = q.prev;
+        const bool force64 = (a.flags & 0x2u) != 0;
+        const bool cand = valid && ((I > q.Ahi) | (I < q.Alo));
+        n = 0;
+        bad = 0;
+        f64count = 0;
+        up = false;
+        f64 = false;
+        have_d = false;
+        L0d = L1d = 0.0;
+        int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+        count_frame<LOGIN>(q, I, Ip, cand, force64, a.log_eps, n, up, f64, bad, dg);
+        ts = TsSetup{};
+        if (n > 0 && !f64) {
+            Rec rc;
+            rc.meta = (uint32_t)n | (up ? (1u << 29) : 0u);
+            const double X1 = up ? q.Xh : q.Xl;
+            rc.w0 = __float_as_uint(I);
+            rc.w1 = __float_as_uint(Ip);
+            rc.w2 = (uint32_t)__double2loint(X1);
+            rc.w3 = (uint32_t)__double2hiint(X1);
+            ts = ts_setup<LOGIN>(a, rc, up ? q.cp : -q.cn, s_toff);
+        } else {
+            ts.tp = 0;
+            ts.dt = s_toff[0];
+        }
+    }
+
+    // timestamp of crossing j (0-based), relative to T0
+    __device__ __forceinline__ int time_of(const StepArgs& a, int j) {
+        int tt = 0;
+        if (!f64 && ts_fast(ts, j, tt)) return tt;
+        if (!have_d) {
+            const LogPair lp = log_pair64<LOGIN>(Ip, I, a.log_eps);
+            L0d = lp.L0;
+            L1d = lp.L1;
+            have_d = true;
+        }
+        ++f64count;
+        return time64(q.L_init, q.nup, q.ndn, q.cp, q.cn, up ? 1 : 0, j, L0d, L1d, a.T0,
+                      ts.tp, ts.dt);
+    }
+
+    // crossings that pass the refractory filter
+    __device__ __forceinline__ int emitted(const StepArgs& a) {
+        int e = 0, tl = q.tlast;
+        for (int j = 0; j < n; ++j) {
+            const int tt = time_of(a, j);
+            if (tt - tl >= a.tref) {
+                tl = tt;
+                ++e;
+            }
+        }
+        return e;
+    }
+
+    // the commit-candidate state of a valid pixel; tl = its last emitted time
+    __device__ __forceinline__ void store_state(const StepArgs& a, int cur, int pix, int tl,
+                                                int last) {
+        const int nxt = cur ^ 1;
+        a.nud[nxt][pix] = make_int2(q.nup + (up ? n : 0), q.ndn + (up ? 0 : n));
+        a.prev[nxt][pix] = I;
+        int tln = kTlastNone;
+        if (tl != kTlastNone && tl - last >= -a.tref) tln = tl - last;
+        a.tlast[nxt][pix] = tln;
+    }
+};
+
 template <bool LOGIN, bool MAP>
 __global__ __launch_bounds__(256) void atomic_step_kernel(const AtomicArgs aa) {
     const StepArgs& a = aa.s;
@@ -1615,61 +1707,16 @@ __global__ __launch_bounds__(256) void atomic_step_kernel(const AtomicArgs aa) {
         const EnvRec er = a.envs[a.wave_env[wid]];
         const int local = (wid - er.wave0) * kWave + lane;
         const bool valid = local < er.npix;
-        Px q;
-        load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
-                          MAP ? a.c_pos_map : nullptr, MAP ? a.c_neg_map : nullptr,
-                          a.c_pos, a.c_neg, pix, valid, a.log_eps);
-        const float I = valid ? __builtin_nontemporal_load(a.frames + er.frame_off + local)
-                              : 1.0f;
-        const float Ip = q.prev;
-        const bool force64 = (a.flags & 0x2u) != 0;
-        const bool cand = valid && ((I > q.Ahi) | (I < q.Alo));
-        int n = 0, bad = 0;
-        bool up = false, f64 = false;
-        int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        count_frame<LOGIN>(q, I, Ip, cand, force64, a.log_eps, n, up, f64, bad, dg);
-
-        // timestamps of the crossings (relative to T0) in order, refractory
-        TsSetup ts{};
-        if (n > 0 && !f64) {
-            Rec rc;
-            rc.meta = (uint32_t)n | (up ? (1u << 29) : 0u);
-            const double X1 = up ? q.Xh : q.Xl;
-            rc.w0 = __float_as_uint(I);
-            rc.w1 = __float_as_uint(Ip);
-            rc.w2 = (uint32_t)__double2loint(X1);
-            rc.w3 = (uint32_t)__double2hiint(X1);
-            ts = ts_setup<LOGIN>(a, rc, up ? q.cp : -q.cn, s_toff);
-        } else {
-            ts.tp = 0;
-            ts.dt = s_toff[0];
-        }
-        double L0d = 0.0, L1d = 0.0;
-        bool have_d = false;
-        int f64count = 0;
-        auto time_of = [&](int j) -> int {
-            int tt = 0;
-            if (!f64 && ts_fast(ts, j, tt)) return tt;
-            if (!have_d) {
-                const LogPair lp = log_pair64<LOGIN>(Ip, I, a.log_eps);
-                L0d = lp.L0;
-                L1d = lp.L1;
-                have_d = true;
-            }
-            ++f64count;
-            return time64(q.L_init, q.nup, q.ndn, q.cp, q.cn, up ? 1 : 0, j, L0d,
-                          L1d, a.T0, ts.tp, ts.dt);
-        };
+        LaneFrame<LOGIN> L;
+        L.template setup<MAP>(a, s_toff, cur, pix, er.frame_off + local, valid);
+        const Px& q = L.q;
+        const int n = L.n;
+        const bool up = L.up;
+        int bad = L.bad;
         // first pass: how many crossings survive the refractory filter
-        int e = 0;
+        int e = L.emitted(a);
         int tl = q.tlast;
-        for (int j = 0; j < n; ++j) {
-            const int tt = time_of(j);
-            if (tt - tl >= a.tref) {
-                tl = tt;
-                ++e;
-            }
-        }
+
         // background noise events of this pixel and interval (not filtered,
         // written after the pixel's signal events)
         const uint64_t fi = (uint64_t)hdr->frame_count;
@@ -1701,7 +1748,7 @@ __global__ __launch_bounds__(256) void atomic_step_kernel(const AtomicArgs aa) {
         const uint32_t y = valid ? (uint32_t)(local / aa.width) : 0u;
         const uint32_t x = valid ? (uint32_t)(local - (int)y * aa.width) : 0u;
         for (int j = 0; j < n; ++j) {
-            const int tt = time_of(j);
+            const int tt = L.time_of(a, j);
             if (tt - tl < a.tref) continue;
             tl = tt;
             if (pos < room) {
@@ -1724,7 +1771,7 @@ __global__ __launch_bounds__(256) void atomic_step_kernel(const AtomicArgs aa) {
         }
         for (int j = 0; j < nn; ++j) {
             bool nup;
-            const int tt = noise_event(aa, (uint32_t)local, fi, j, ts.dt, nup);
+            const int tt = noise_event(aa, (uint32_t)local, fi, j, L.ts.dt, nup);
             if (pos < room) {
                 if (aa.sorted) {
                     const uint32_t key = ((uint32_t)tt << aa.pbits) | (uint32_t)pix;
@@ -1744,18 +1791,10 @@ __global__ __launch_bounds__(256) void atomic_step_kernel(const AtomicArgs aa) {
             ++pos;
         }
         // commit-candidate state
-        if (valid) {
-            const int nxt = cur ^ 1;
-            a.nud[nxt][pix] = make_int2(q.nup + (up ? n : 0), q.ndn + (up ? 0 : n));
-            a.prev[nxt][pix] = I;
-            const int last = s_toff[0];
-            int tln = kTlastNone;
-            if (tl != kTlastNone && tl - last >= -a.tref) tln = tl - last;
-            a.tlast[nxt][pix] = tln;
-        }
+        if (valid) L.store_state(a, cur, pix, tl, s_toff[0]);
         if (q.nup + n > kMaxCounter || q.ndn + n > kMaxCounter) bad = 1;
         if (__ballot(bad != 0) && lane == 0) atomicOr(&hdr->internal_err, kErrRange);
-        const int wf64 = wave_sum(f64count + (f64 ? 1 : 0));
+        const int wf64 = wave_sum(L.f64count + (L.f64 ? 1 : 0));
         if (wf64 && lane == 0)
             atomicAdd((unsigned long long*)&hdr->fp64_evals, (unsigned long long)wf64);
     }
