@@ -726,9 +726,10 @@ def bench_perframe(args, dev):
     640x480 and 1280x720 streams, every frame its own step call, for the
     ordered path and for the paper's kernel design (one atomic per wave),
     sorted afterwards and unsorted.  'stream' = calls back to back with the
-    events queued on the device and drained once at the end; 'latency' =
-    each call followed by a drain of its events to caller arrays and a host
-    synchronisation.  One timed step = the whole 1280x720 stream in stream
+    events queued on the device and drained once at the end; 'library' = one
+    step call of the whole stream in which the library issues one launch
+    sequence per frame (no Python per frame); 'latency' = each call followed
+    by a drain of its events to caller arrays and a host synchronisation.  One timed step = the whole 1280x720 stream in stream
     mode on the ordered path."""
     import torch
 
@@ -740,7 +741,7 @@ def bench_perframe(args, dev):
         frames, t, cp, cn = resident_frames(w, F, dev)
         res[key] = {"workload": STREAMS[key], "frames": F}
         for emit in ("ordered", "atomic", "atomic_unsorted"):
-            sim, cap = make_sim(w, F, cp, cn, emit=emit)
+            sim, cap = make_sim(w, F, cp, cn, emit=emit, max_frames_per_launch=1)
             out = (torch.empty(cap, dtype=torch.int64, device=dev),
                    torch.empty(cap, dtype=torch.uint16, device=dev),
                    torch.empty(cap, dtype=torch.uint16, device=dev),
@@ -750,6 +751,13 @@ def bench_perframe(args, dev):
                 sim.reset()
                 for k in range(F):
                     sim.step(frames[k:k + 1], t[k:k + 1])
+                return sim.drain(out=out)
+
+            def library_mode():
+                # every frame its own launch sequence, issued by the
+                # library's own loop (one step call, one frame per launch)
+                sim.reset()
+                sim.step(frames, t)
                 return sim.drain(out=out)
 
             def latency_mode(nf):
@@ -772,12 +780,21 @@ def bench_perframe(args, dev):
                 stream_mode()
             torch.cuda.synchronize()
             el = (time.perf_counter() - t0) / args.steps
+            library_mode()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                library_mode()
+            torch.cuda.synchronize()
+            el_lib = (time.perf_counter() - t0) / args.steps
             nl = min(F, 501)
             lat = latency_mode(nl)
             sim.close()
             per = el / (F - 1)
             r = {
                 "us_per_frame_stream": per * 1e6, "khz_stream": 1e-3 / per,
+                "us_per_frame_library": el_lib / (F - 1) * 1e6,
+                "khz_library": 1e-3 * (F - 1) / el_lib,
                 "us_per_frame_latency": lat / (nl - 1) * 1e6,
                 "khz_latency": 1e-3 * (nl - 1) / lat,
                 "events_per_stream": n_ev,
