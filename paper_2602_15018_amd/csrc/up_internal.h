@@ -15,8 +15,14 @@ namespace nup {
 
 constexpr int kWave = 64;
 constexpr int kConvThreads = 256;     // 4 waves, 64 output pixels each
-constexpr int kWgradThreads = 256;    // 4 waves over one pixel range
-constexpr int kWgradKTile = 64;       // K columns per weight-gradient block
+constexpr int kWgradThreads = 256;    // 4 waves over a range of image rows
+constexpr int kWgSeg = 64;            // pixels of a row segment
+constexpr int kWgHalo = kWgSeg + 2;   // input columns a segment's taps reach
+constexpr int kWgSlots = 72;          // LDS row of one input channel
+constexpr int kWgDzStride = 68;       // LDS row of one gradient channel
+constexpr int kWgTiles = 36;          // 16 x 16 output tiles per block
+constexpr int kWgTPW = kWgTiles / 4;  // tiles per wave
+constexpr int kWgMaxCout = 64, kWgMaxCin = 96;
 constexpr int kHeadIn = 16;
 constexpr int kHeadOut = 7;
 
@@ -47,10 +53,11 @@ struct ConvArgs {
 };
 
 // Weight gradient of a 3x3 convolution: dW[co][k] = sum over pixels m of
-// dz[m][co] * X[m][k], X the im2col of the input (sources as ConvArgs),
-// dz = dy where y > 0.  Block (kt, pb) writes its partial sums of K columns
-// [64 kt, 64 kt + 64) over pixel block pb to part_w[pb][Cout][Kpad]; blocks
-// of kt == 0 also write the bias partial part_b[pb][Cout].
+// dz[m][co] * X[m][k], X the im2col of the input (sources as ConvArgs,
+// K = 9 Cin, channel counts multiples of 4), dz = dy where y > 0.  Block
+// (tg, rb) writes its partial sums over image rows [rb rows_per_block, ...)
+// for its output tiles to part_w[rb][Cout][Kpad]; blocks of tg == 0 also
+// write the bias partial part_b[rb][Cout].
 struct WgradArgs {
     const uint16_t* inA;
     const uint16_t* inB;
@@ -62,11 +69,11 @@ struct WgradArgs {
     int32_t Ca, Cb, Cin;
     int32_t Cout, K, Kpad;
     int32_t b_half;
-    int32_t pix_per_block;
+    int32_t rows_per_block;
 };
 
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s);
-hipError_t launch_wgrad(const WgradArgs& a, int n_pix_blocks, hipStream_t s);
+hipError_t launch_wgrad(const WgradArgs& a, int n_row_blocks, hipStream_t s);
 // out[i] = sum over b of part[b * stride + src(i)], with src remapping the
 // padded [Cout][9][Cpad] layout to [Cout][9][Ci] (identity for biases).
 hipError_t launch_reduce(const float* part, int nblk, int64_t stride,

@@ -197,161 +197,185 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const ConvArgs a) {
     }
 }
 
-// Weight gradient.  Wave layout: A = dz^T (rows co, k-dim pixels),
-// B = X (k-dim pixels, columns K).  Each wave accumulates a Cout x 64 tile
-// over the pixels of its quarter of the block's pixel range; the four
-// waves' tiles are summed in LDS and written as the block's partial.
-template <int MT>
+// Weight gradient, staged by image rows.  Block (tg, rb) owns the 16 x 16
+// output tiles [kWgTiles tg, kWgTiles (tg + 1)) of the [Cout][Kpad] grid
+// (wave w: tiles w, w + 4, ...) and the image rows [rb rows_per_block, ...)
+// of all N H rows, each row in segments of 64 pixels.  Per segment the
+// upstream gradient, masked by the ReLU (dz = dy where y > 0), is staged
+// transposed in LDS as [co][pixel], and the three input rows the taps reach
+// as [ky][c][slot] with slot xx holding source column x0 - 1 + xx (zero
+// outside the image: the taps' zero padding), both from 8-byte loads of
+// four channels.  An MFMA operand is then four consecutive pixels of one
+// channel: one 8-byte LDS read for dz; for the input the same read plus the
+// next 4 bytes, shifted by the tap's column offset kx (a byte alignment).
+// Each output tile belongs to one wave, so partials need no block
+// reduction; block rb writes part_w[rb], blocks of tg == 0 also the bias
+// partial part_b[rb] (summed by one thread per channel in pixel order).
 __global__ __launch_bounds__(kWgradThreads) void wgrad_kernel(const WgradArgs a) {
-    __shared__ float s_red[MT * 16 * kWgradKTile];
-    __shared__ float s_bias[4][MT * 16];
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
+    // LDS: [Cout][kWgDzStride] gradient, then [3][Cin][kWgSlots] input
+    extern __shared__ __align__(16) uint16_t s_mem[];
+    uint16_t* s_dz = s_mem;
+    uint16_t* s_x = s_mem + a.Cout * kWgDzStride;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wv = tid / kWave;
     const int r16 = lane & 15, g4 = lane >> 4;
-    // Pixel indices fit in 32 bits (the launcher rejects more than
-    // kConvMaxPixels pixels); element offsets are formed in 64 bits.
-    const int HW = a.H * a.W;
-    const int M = a.N * HW;
-    const int kt = blockIdx.x;
-    const int pb = blockIdx.y;
-    const int p0 = pb * a.pix_per_block;
-    const int p1 = M - p0 > a.pix_per_block ? p0 + a.pix_per_block : M;
-    const Src src{a.inA, a.inB, nullptr, a.Ca, a.Cb, a.H, a.W, a.b_half};
-    const bool want_bias = kt == 0;
+    const int tg = blockIdx.x, rb = blockIdx.y;
+    const int R = a.N * a.H;
+    const int r0 = rb * a.rows_per_block;
+    const int r1 = R - r0 > a.rows_per_block ? r0 + a.rows_per_block : R;
+    const int ktiles = a.Kpad / 16;
+    const int T = (a.Cout / 16) * ktiles;
+    const int t_end = T < (tg + 1) * kWgTiles ? T : (tg + 1) * kWgTiles;
+    const int CQo = a.Cout / 4, CQi = a.Cin / 4;
+    const int Hh = a.H >> 1, Wh = a.W >> 1;
 
-    // this lane's B columns: k = 64 kt + 16 j + r16
-    int btap[4], bc[4];
-    bool bkv[4];
+    // this wave's tiles: rows 16 ti of dz^T, columns k = 16 kj + r16 of the
+    // im2col input (tap = k / Cin, channel k % Cin)
+    int ti[kWgTPW], xrow[kWgTPW], kx[kWgTPW];
+    bool tv[kWgTPW], kv[kWgTPW];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-        const int k = kt * kWgradKTile + 16 * j + r16;
-        bkv[j] = k < a.K;
-        btap[j] = bkv[j] ? k / a.Cin : 0;
-        bc[j] = bkv[j] ? k - btap[j] * a.Cin : 0;
+    for (int t = 0; t < kWgTPW; ++t) {
+        const int tile = tg * kWgTiles + wv + 4 * t;
+        tv[t] = tile < t_end;
+        const int tt = tv[t] ? tile : 0;
+        ti[t] = tt / ktiles;
+        const int k = 16 * (tt - ti[t] * ktiles) + r16;
+        kv[t] = tv[t] && k < a.K;
+        const int tap = kv[t] ? k / a.Cin : 0;
+        const int c = kv[t] ? k - tap * a.Cin : 0;
+        const int ky = tap / 3;
+        kx[t] = tap - 3 * ky;
+        xrow[t] = (ky * a.Cin + c) * kWgSlots;
     }
-    f4 acc[MT][4];
+    f4 acc[kWgTPW];
 #pragma unroll
-    for (int i = 0; i < MT; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-    float bsum[MT];
-#pragma unroll
-    for (int i = 0; i < MT; ++i) bsum[i] = 0.f;
+    for (int t = 0; t < kWgTPW; ++t) acc[t] = f4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    const bool bias_lane = tg == 0 && tid < a.Cout;
 
-    // (n, y, x) of the 4 pixels m0 + 4 g4 + e of this lane's k-group: one
-    // division at the start, then each step of 64 pixels moves them on by
-    // (64 / W rows, 64 % W columns) with carries (only pixels below p1 are
-    // read, and those coordinates are exact).
-    int pn[4], py[4], px[4];
+    for (int r = r0; r < r1; ++r) {
+        const int n = r / a.H, y = r - n * a.H;
+        for (int x0 = 0; x0 < a.W; x0 += kWgSeg) {
+            const int len = a.W - x0 < kWgSeg ? a.W - x0 : kWgSeg;
+            __syncthreads();   // the previous segment's operands are read
+            for (int idx = tid; idx < kWgSeg * CQo; idx += kWgradThreads) {
+                const int pp = idx / CQo, cq = idx - pp * CQo;
+                s4 v = {0, 0, 0, 0};
+                if (pp < len) {
+                    const int64_t o = ((int64_t)r * a.W + x0 + pp) * a.Cout + 4 * cq;
+                    v = *reinterpret_cast<const s4*>(a.dy + o);
+                    if (a.y) {
+                        const s4 m = *reinterpret_cast<const s4*>(a.y + o);
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int m = p0 + 16 * wv + 4 * g4 + e;
-        pn[e] = m / HW;
-        const int rem = m - pn[e] * HW;
-        py[e] = rem / a.W;
-        px[e] = rem - py[e] * a.W;
-    }
-    const int sy = 64 / a.W, sx = 64 - sy * a.W;
-    for (int m0 = p0 + 16 * wv; m0 < p1; m0 += 64) {
-        bool pv[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) pv[e] = m0 + 4 * g4 + e < p1;
-        s4 af[MT];
-#pragma unroll
-        for (int i = 0; i < MT; ++i) {
-            const int co = 16 * i + r16;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                short v = 0;
-                if (pv[e]) {
-                    const int64_t o = (int64_t)(m0 + 4 * g4 + e) * a.Cout + co;
-                    v = (short)a.dy[o];
-                    if (a.y && !bf_positive((short)a.y[o])) v = 0;
+                        for (int e = 0; e < 4; ++e)
+                            if (!bf_positive(m[e])) v[e] = 0;
+                    }
                 }
-                af[i][e] = v;
-                if (want_bias) bsum[i] += bf2f((uint16_t)v);
-            }
-        }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            s4 bf = {0, 0, 0, 0};
-            if (bkv[j]) {
-                const int ky = btap[j] / 3, kx = btap[j] - 3 * (btap[j] / 3);
+                for (int e = 0; e < 4; ++e) s_dz[(4 * cq + e) * kWgDzStride + pp] = (uint16_t)v[e];
+            }
+            const int per_row = kWgHalo * CQi;
+            for (int idx = tid; idx < 3 * per_row; idx += kWgradThreads) {
+                const int row = idx / per_row;
+                const int rem = idx - row * per_row;
+                const int xx = rem / CQi, cq = rem - xx * CQi;
+                const int xs = x0 - 1 + xx, ys = y + row - 1;
+                s4 v = {0, 0, 0, 0};
+                if (xs >= 0 && xs < a.W && ys >= 0 && ys < a.H) {
+                    const int c = 4 * cq;
+                    if (c < a.Ca) {
+                        v = *reinterpret_cast<const s4*>(
+                            a.inA + ((int64_t)(n * a.H + ys) * a.W + xs) * a.Ca + c);
+                    } else {
+                        const int pix = a.b_half ? (n * Hh + (ys >> 1)) * Wh + (xs >> 1)
+                                                 : (n * a.H + ys) * a.W + xs;
+                        v = *reinterpret_cast<const s4*>(a.inB + (int64_t)pix * a.Cb +
+                                                         (c - a.Ca));
+                    }
+                }
 #pragma unroll
                 for (int e = 0; e < 4; ++e)
-                    if (pv[e]) bf[e] = load1(src, pn[e], py[e] + ky - 1, px[e] + kx - 1, bc[j]);
+                    s_x[(row * a.Cin + 4 * cq + e) * kWgSlots + xx] = (uint16_t)v[e];
+            }
+            __syncthreads();
+            if (bias_lane) {
+                for (int pp = 0; pp < kWgSeg; pp += 4) {
+                    const s4 v = *reinterpret_cast<const s4*>(&s_dz[tid * kWgDzStride + pp]);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) bsum += bf2f((uint16_t)v[e]);
+                }
             }
 #pragma unroll
-            for (int i = 0; i < MT; ++i) acc[i][j] = mfma(af[i], bf, acc[i][j]);
-        }
+            for (int sk = 0; sk < kWgSeg / 16; ++sk) {
+                const int p0 = 16 * sk + 4 * g4;
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            px[e] += sx;
-            py[e] += sy;
-            if (px[e] >= a.W) {
-                px[e] -= a.W;
-                ++py[e];
+                for (int t = 0; t < kWgTPW; ++t) {
+                    if (!tv[t]) continue;   // (uniform over the wave)
+                    const s4 af = *reinterpret_cast<const s4*>(
+                        &s_dz[(16 * ti[t] + r16) * kWgDzStride + p0]);
+                    const uint16_t* px = &s_x[xrow[t] + p0];
+                    const uint2 w01 = *reinterpret_cast<const uint2*>(px);
+                    const uint32_t w2 = *reinterpret_cast<const uint32_t*>(px + 4);
+                    const uint32_t lo = kx[t] == 0 ? w01.x
+                                      : kx[t] == 1 ? __builtin_amdgcn_alignbyte(w01.y, w01.x, 2)
+                                                   : w01.y;
+                    const uint32_t hi = kx[t] == 0 ? w01.y
+                                      : kx[t] == 1 ? __builtin_amdgcn_alignbyte(w2, w01.y, 2)
+                                                   : w2;
+                    s4 bf;
+                    bf[0] = (short)(lo & 0xFFFFu);
+                    bf[1] = (short)(lo >> 16);
+                    bf[2] = (short)(hi & 0xFFFFu);
+                    bf[3] = (short)(hi >> 16);
+                    if (!kv[t]) bf = s4{0, 0, 0, 0};
+                    acc[t] = mfma(af, bf, acc[t]);
+                }
             }
-            if (py[e] >= a.H) {
-                const int q = py[e] / a.H;
-                pn[e] += q;
-                py[e] -= q * a.H;
-            }
         }
     }
-    // sum the four waves' tiles in LDS (fixed order), then write
-    for (int w = 0; w < 4; ++w) {
-        if (wv == w) {
+    float* out = a.part_w + (int64_t)rb * a.Cout * a.Kpad;
 #pragma unroll
-            for (int i = 0; i < MT; ++i)
+    for (int t = 0; t < kWgTPW; ++t) {
+        if (!tv[t]) continue;
+        const int tile = tg * kWgTiles + wv + 4 * t;
+        const int kj = tile - ti[t] * ktiles;
 #pragma unroll
-                for (int j = 0; j < 4; ++j)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const int row = 16 * i + 4 * g4 + r;   // co
-                        const int col = 16 * j + r16;          // k in tile
-                        float* p = &s_red[row * kWgradKTile + col];
-                        *p = (w == 0 ? 0.f : *p) + acc[i][j][r];
-                    }
-        }
-        __syncthreads();
+        for (int rr = 0; rr < 4; ++rr)
+            out[(int64_t)(16 * ti[t] + 4 * g4 + rr) * a.Kpad + 16 * kj + r16] = acc[t][rr];
     }
-    float* out = a.part_w + (int64_t)pb * a.Cout * a.Kpad;
-    for (int t = threadIdx.x; t < MT * 16 * kWgradKTile; t += kWgradThreads) {
-        const int row = t / kWgradKTile, col = t - row * kWgradKTile;
-        const int k = kt * kWgradKTile + col;
-        if (k < a.Kpad) out[(int64_t)row * a.Kpad + k] = s_red[t];
-    }
-    if (want_bias) {
-        // lanes l, l+16, l+32, l+48 hold partial sums of the same channel
-#pragma unroll
-        for (int i = 0; i < MT; ++i) {
-            float v = bsum[i];
-            v += __shfl_xor(v, 16, kWave);
-            v += __shfl_xor(v, 32, kWave);
-            if (g4 == 0) s_bias[wv][16 * i + r16] = v;
-        }
-        __syncthreads();
-        for (int co = threadIdx.x; co < MT * 16; co += kWgradThreads)
-            a.part_b[(int64_t)pb * a.Cout + co] =
-                ((s_bias[0][co] + s_bias[1][co]) + s_bias[2][co]) + s_bias[3][co];
-    }
+    if (bias_lane) a.part_b[(int64_t)rb * a.Cout + tid] = bsum;
 }
 
-__global__ void reduce_kernel(const float* part, int nblk, int64_t stride,
-                              int Cout, int Ci, int Cpad, int Kpad, int taps,
-                              float* out) {
+// Sum of the block partials: out[i] = sum over b of part[b stride + src(i)].
+// A workgroup takes 64 consecutive outputs (one per lane) and splits the
+// partials over its 16 waves (wave w: b = w, w + 16, ...), each summing in
+// order, then wave 0 adds the 16 sums in wave order: a fixed association, so
+// the result does not depend on scheduling.
+constexpr int kReduceWaves = 16;
+
+__global__ __launch_bounds__(kReduceWaves * 64) void reduce_kernel(
+    const float* part, int nblk, int64_t stride, int Cout, int Ci, int Cpad, int Kpad,
+    int taps, float* out) {
+    __shared__ float s_sum[kReduceWaves][64];
     const int64_t n = (int64_t)Cout * taps * Ci;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const int per = taps * Ci;
-    const int co = (int)(i / per);
-    const int rem = (int)(i - (int64_t)co * per);
-    const int tap = rem / Ci, ci = rem - tap * Ci;
-    const int64_t src = (int64_t)co * Kpad + tap * Cpad + ci;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int64_t i = (int64_t)blockIdx.x * 64 + lane;
     float s = 0.f;
-    for (int b = 0; b < nblk; ++b) s += part[(int64_t)b * stride + src];
-    out[i] = s;
+    if (i < n) {
+        const int per = taps * Ci;
+        const int co = (int)(i / per);
+        const int rem = (int)(i - (int64_t)co * per);
+        const int tap = rem / Ci, ci = rem - tap * Ci;
+        const int64_t src = (int64_t)co * Kpad + tap * Cpad + ci;
+        for (int b = wv; b < nblk; b += kReduceWaves) s += part[(int64_t)b * stride + src];
+    }
+    s_sum[wv][lane] = s;
+    __syncthreads();
+    if (wv == 0 && i < n) {
+        float t = 0.f;
+        for (int w = 0; w < kReduceWaves; ++w) t += s_sum[w][lane];
+        out[i] = t;
+    }
 }
 
 __global__ void make_input_kernel(const float* L0, const float* L8, uint16_t* x,
@@ -599,21 +623,20 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_wgrad(const WgradArgs& a, int n_pix_blocks, hipStream_t s) {
-    if (a.Cout % 16 || a.Cout > 64 || a.Kpad % 16 || a.K > a.Kpad || a.Cin <= 0 ||
-        a.pix_per_block <= 0 || n_pix_blocks <= 0 ||
-        (int64_t)a.N * a.H * a.W > kConvMaxPixels ||
-        (int64_t)(n_pix_blocks - 1) * a.pix_per_block >= (int64_t)a.N * a.H * a.W ||
+hipError_t launch_wgrad(const WgradArgs& a, int n_row_blocks, hipStream_t s) {
+    const int64_t R = (int64_t)a.N * a.H;
+    if (a.Cout % 16 || a.Cout > kWgMaxCout || a.Kpad % 16 || a.K > a.Kpad ||
+        a.Cin <= 0 || a.Cin > kWgMaxCin || a.Cin % 4 || a.Ca % 4 || a.Cb % 4 ||
+        a.Ca + a.Cb != a.Cin || a.K != 9 * a.Cin || a.rows_per_block <= 0 ||
+        n_row_blocks <= 0 || (int64_t)a.N * a.H * a.W > kConvMaxPixels ||
+        (int64_t)(n_row_blocks - 1) * a.rows_per_block >= R ||
         (a.b_half && (a.H % 2 || a.W % 2)))
         return hipErrorInvalidValue;
-    const dim3 grid((a.Kpad + kWgradKTile - 1) / kWgradKTile, n_pix_blocks);
-    const dim3 block(kWgradThreads);
-    switch (a.Cout / 16) {
-    case 1: hipLaunchKernelGGL(wgrad_kernel<1>, grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL(wgrad_kernel<2>, grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL(wgrad_kernel<4>, grid, block, 0, s, a); break;
-    default: return hipErrorInvalidValue;
-    }
+    const int T = (a.Cout / 16) * (a.Kpad / 16);
+    const dim3 grid((T + kWgTiles - 1) / kWgTiles, n_row_blocks);
+    const size_t lds = sizeof(uint16_t) * ((size_t)a.Cout * kWgDzStride +
+                                           (size_t)3 * a.Cin * kWgSlots);
+    hipLaunchKernelGGL(wgrad_kernel, grid, dim3(kWgradThreads), lds, s, a);
     return hipGetLastError();
 }
 
@@ -621,8 +644,8 @@ hipError_t launch_reduce(const float* part, int nblk, int64_t stride, int Cout,
                          int Ci, int Cpad, int Kpad, int taps, float* out,
                          hipStream_t s) {
     const int64_t n = (int64_t)Cout * taps * Ci;
-    hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s,
-                       part, nblk, stride, Cout, Ci, Cpad, Kpad, taps, out);
+    hipLaunchKernelGGL(reduce_kernel, dim3(blocks_for(n, 64)), dim3(kReduceWaves * 64), 0,
+                       s, part, nblk, stride, Cout, Ci, Cpad, Kpad, taps, out);
     return hipGetLastError();
 }
 

@@ -210,15 +210,19 @@ int wgrad(nsim_up* h, int li, const uint16_t* inA, int Ca, const uint16_t* inB,
           int Cb, int b_half, const uint16_t* dy, const uint16_t* y, int N,
           int H, int W) {
     const Layer& l = h->L[li];
-    const int64_t M = (int64_t)N * H * W;
-    // pixel blocks: enough to fill the chip, bounded by the partial buffer
-    int64_t nblk = (M + 4095) / 4096;
+    const int64_t R = (int64_t)N * H;
+    // blocks of whole image rows, about 512 pixels each: several blocks per
+    // compute unit, so that one block's operand loads overlap another's
+    // matrix work (each block stages a row segment, then computes on it);
+    // bounded by the partial buffers
+    int64_t nblk = ((int64_t)R * W + 511) / 512;
+    if (nblk > R) nblk = R;
     const int64_t cap_blk = h->part_cap / ((int64_t)l.co * l.Kpad);
     if (nblk > cap_blk) nblk = cap_blk;
     if (nblk > h->part_b_cap / l.co) nblk = h->part_b_cap / l.co;
     if (nblk < 1) nblk = 1;
-    const int64_t per = ((M + nblk - 1) / nblk + 63) / 64 * 64;
-    nblk = (M + per - 1) / per;
+    const int64_t per = (R + nblk - 1) / nblk;
+    nblk = (R + per - 1) / per;
     nup::WgradArgs a{};
     a.inA = inA;
     a.inB = inB;
@@ -236,7 +240,7 @@ int wgrad(nsim_up* h, int li, const uint16_t* inA, int Ca, const uint16_t* inB,
     a.K = l.K;
     a.Kpad = l.Kpad;
     a.b_half = b_half;
-    a.pix_per_block = (int32_t)per;
+    a.rows_per_block = (int32_t)per;
     UP_HIP(h, nup::launch_wgrad(a, (int)nblk, h->stream));
     UP_HIP(h, nup::launch_reduce(h->part, (int)nblk, (int64_t)l.co * l.Kpad, l.co,
                                  l.ci, l.cpad, l.Kpad, 9, h->g + l.w_off,

@@ -390,6 +390,44 @@ def test_overflow_all_or_nothing_and_reissue():
     assert exact_equal(ref, got)
 
 
+def test_overflow_inside_one_call():
+    """Many launches in one call; the queue overflows in the middle of the
+    call: the stream stops at the last committed launch (later launches of
+    the call do nothing), the error is reported once, and re-issuing from
+    the committed time gives the uninterrupted stream, equal to the
+    oracle's."""
+    from paper_2602_15018_amd.ev import EventSim, NsimError
+    dev = _dev()
+    w = scene.WORKLOADS["vga640x480_1000f_1000fps"]
+    H, W, F = 48, 64, 61
+    fr = scene.render_workload(w, 0, F, device=dev, height=H, width=W)
+    t = scene.frame_times(w, 0, F)
+    cp, cn = scene.threshold_maps(w, H, W)
+    want = oracle.run(fr.cpu().numpy(), t, cp, cn, refractory_us=100)["events"]
+    n_total = len(want.t)
+    assert n_total > 3000
+    sim = EventSim(W, H, c_pos_map=cp, c_neg_map=cn, refractory_us=100,
+                   capacity_events=n_total // 3, max_frames_per_launch=4)
+    got = [[], [], [], []]
+    k, errors = 0, 0
+    while k < F:
+        sim.step(fr[k:], t[k:])
+        try:
+            sim.sync()
+            k = F
+        except NsimError as e:
+            assert e.code == -3
+            errors += 1
+            k = int(np.searchsorted(t, sim.committed_time(), "right"))
+        part = as_numpy(sim.drain())
+        for i in range(4):
+            got[i].append(part[i])
+    sim.close()
+    assert errors >= 2
+    got = tuple(np.concatenate(g) for g in got)
+    assert exact_equal(got, (want.t, want.x, want.y, want.p))
+
+
 def test_range_limit_reports_estate():
     """A log jump of 2^21 thresholds in one frame interval is past the
     supported 2^20 - 1 crossings per pixel and interval: the step is not
