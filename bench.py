@@ -91,6 +91,10 @@ def parse():
                          "list of saturation=I, bandwidth_tau_us=T, "
                          "noise_rate_hz=R, noise_seed=S (e.g. "
                          "saturation=0.9,bandwidth_tau_us=200,noise_rate_hz=1)")
+    ap.add_argument("--fused-step", action="store_true",
+                    help="stream workloads: one kernel walks and stamps every "
+                         "launch (the default splits launches of 16 frames or "
+                         "more into a walk kernel and a timestamp kernel)")
     ap.add_argument("--emit", default="ordered",
                     choices=["ordered", "atomic", "atomic_unsorted"],
                     help="stream workloads: the ordered path (default) or the "
@@ -566,7 +570,7 @@ def sensor_settings(spec):
 
 
 def make_sim(w, F, cp, cn, max_frames_per_launch=0, direct_launch=False,
-             emit="ordered", sensor=None):
+             emit="ordered", sensor=None, fused_step=False):
     """The event path exactly as the benchmark times it: queue sized for the
     whole stream, default frames per launch unless overridden."""
     from paper_2602_15018_amd.ev import EventSim
@@ -578,7 +582,8 @@ def make_sim(w, F, cp, cn, max_frames_per_launch=0, direct_launch=False,
                    log_eps=w.log_eps, refractory_us=w.refractory_us,
                    capacity_events=cap,
                    max_frames_per_launch=max_frames_per_launch,
-                   direct_launch=direct_launch, emit=emit, **(sensor or {}))
+                   direct_launch=direct_launch, emit=emit,
+                   fused_step=fused_step, **(sensor or {}))
     return sim, cap
 
 
@@ -614,7 +619,7 @@ def bench_stream(args, dev):
 
     sensor = sensor_settings(args.sensor)
     sim, cap = make_sim(w, F, cp, cn, args.max_frames_per_launch, emit=args.emit,
-                        sensor=sensor)
+                        sensor=sensor, fused_step=args.fused_step)
     out = (torch.empty(cap, dtype=torch.int64, device=dev),
            torch.empty(cap, dtype=torch.uint16, device=dev),
            torch.empty(cap, dtype=torch.uint16, device=dev),
@@ -655,6 +660,11 @@ def bench_stream(args, dev):
     alg_launch = alg_step / launches_per_step
     achieved = alg_launch / (k1_ms * 1e-3) / 1e9
     fp64 = st["fp64_evaluations"] - base["fp64_evaluations"]
+    # launches of 16 frames or more run the split step (walk kernel, then
+    # timestamp kernel); the HIP events of the step bracket both
+    split = (args.emit == "ordered" and not sensor.get("noise_rate_hz") and
+             not args.fused_step and fpl >= 16)
+    step_kernel = "walk_kernel + stamp_kernel" if split else "step_kernel"
 
     result = {
         "metric": METRIC,
@@ -678,12 +688,13 @@ def bench_stream(args, dev):
             "emit": ("atomic (per-frame pipeline: background noise)"
                      if sensor.get("noise_rate_hz") else args.emit),
             "sensor": sensor or None,
+            "step": "split" if split else "fused",
         },
         "events_per_s": ev_step * args.steps / elapsed,
         "events_per_step": ev_step,
         "fp64_evaluations_per_pixel_update": fp64 / (pu_step * args.steps),
         "roofline": {
-            "kernel": "step_kernel",
+            "kernel": step_kernel,
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,

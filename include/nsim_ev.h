@@ -69,6 +69,12 @@ extern "C" {
 #define NSIM_DIRECT_LAUNCH 0x10u /* single streams: launch every kernel
                                     directly; by default launches of one or
                                     two frames replay a captured HIP graph */
+#define NSIM_FUSED_STEP 0x20u /* single streams: one kernel walks the
+                                 frames and stamps the crossings for every
+                                 launch (the same events); by default
+                                 launches of 16 frames or more split the
+                                 step into a walk kernel that records the
+                                 crossings and a timestamp kernel */
 
 typedef struct nsim_ev_config {
     int32_t width;   /* 1 .. 65535 */
@@ -84,7 +90,7 @@ typedef struct nsim_ev_config {
                                 the most one internal launch may produce */
     uint32_t flags;          /* NSIM_INPUT_LOG | NSIM_FORCE_FP64 |
                                 NSIM_DIRECT_LAUNCH | NSIM_ATOMIC_EMIT |
-                                NSIM_ATOMIC_UNSORTED */
+                                NSIM_ATOMIC_UNSORTED | NSIM_FUSED_STEP */
     int32_t max_frames_per_launch; /* 0 = automatic (up to 128 frames while
                                       the launch spans at most 65535 us);
                                       else 1 .. 256 */
@@ -94,8 +100,11 @@ typedef struct nsim_ev nsim_ev_t;
 
 /* Create a stream.  Allocates state (about 40 B per pixel with threshold
  * maps), per-wave staging (128 B per frame of a launch per 64 pixels, at
- * least 8 KB: 16 KB in automatic mode), and per event of capacity 13 B of
- * queue plus 20 B of staging and sort scratch.
+ * least 8 KB: 16 KB in automatic mode), per event of capacity 13 B of
+ * queue plus 20 B of staging and sort scratch, and, unless NSIM_FUSED_STEP
+ * or NSIM_ATOMIC_EMIT is set and when launches may hold 16 frames or more,
+ * crossing records of 20 B per pixel and frame of a launch (128 frames in
+ * automatic mode: 2.4 GB at 1280 x 720).
  * Returns NSIM_EINVAL for a bad config (out is set to NULL). */
 int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out);
 

@@ -23,6 +23,8 @@ constexpr int kMaxEnvs = 4096;
 constexpr int kChunk = 8;                     // frames prefetched per chunk
 constexpr int kMaxFramesPerLaunch = 256;
 constexpr int kAutoFramesPerLaunch = 128;
+constexpr int kSplitMinFrames = 16;           // launches of at least this many frames
+                                              // run the split step (walk, then timestamps)
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 24;               // items per thread per tile
 constexpr int kSortTile = kSortThreads * kSortItems;
@@ -75,8 +77,10 @@ struct alignas(64) Header {
     int64_t diag[8];
 };
 
-// Arguments of the fused step kernel.  Frame times travel by value.  Each
-// wave of 64 pixels is independent: it owns the staging segment
+// Arguments of the step: the fused step kernel, or the walk and timestamp
+// kernels of the split step, which take the same arguments.  Frame times
+// travel by value.  Each wave of 64 pixels is independent: it owns the
+// staging segment
 // [wave * stage_entries, +stage_entries) of packed entries
 // (time offset << 7 | lane << 1 | p > 0, or a hole for a suppressed
 // crossing); a wave whose crossings outgrow it takes a segment of the exact
@@ -114,6 +118,17 @@ struct StepArgs {
     uint32_t flags;
     int32_t scan_words;    // status words of the scan (cleared by block 0)
     uint64_t* scan_status;
+    // Crossing records of the split step (walk kernel -> timestamp kernel):
+    // wave w owns records [w * rec_cap, + rec_count[w]) of each array; a
+    // lane leaves at most one record per frame, so rec_cap = 64 * K always
+    // suffices.  NULL in fused launches.
+    uint32_t* rec_meta;    // lane | frame << 6 | up << 14 | f64 << 15 | n << 16
+    float* rec_I;          // the frame's sample
+    float* rec_prev;       // the sample before it
+    double* rec_X1;        // level of the first crossing (FP64 records: the
+                           // crossing count in the low word)
+    uint32_t* rec_count;   // [nwaves]
+    int64_t rec_cap;
     int32_t toff[kMaxFramesPerLaunch];  // frame k time minus T0
 };
 
@@ -302,6 +317,10 @@ struct FrontArgs {
 hipError_t launch_init(const InitArgs& a, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
                        int waves_per_block, int max_blocks, hipStream_t s);
+hipError_t launch_walk(const StepArgs& a, bool log_input, bool has_map,
+                       int waves_per_block, int max_blocks, hipStream_t s);
+hipError_t launch_stamp(const StepArgs& a, bool log_input, bool has_map,
+                        hipStream_t s);
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s);
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s);
 hipError_t launch_pass(const PassArgs& a, hipStream_t s);

@@ -471,6 +471,11 @@ __device__ __forceinline__ int wave_min(int v) {
     return v;
 }
 
+__device__ __forceinline__ int wave_max(int v) {
+    for (int o = kWave / 2; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return v;
+}
+
 __device__ __forceinline__ int wave_max_small(int v) {
     int m = 0;
     for (int b = 1; b <= kRecMax; ++b)
@@ -598,6 +603,161 @@ __device__ __forceinline__ bool ts_fast(const TsSetup& s, int j, int& tt) {
     return c1 == c2 && et < 0.25f;
 }
 
+// Interpolation of one record whose count was decided in FP32: when the
+// FP32 bound decides every crossing the record becomes ready (a single
+// crossing: its time; several: the interpolation), else it is left as it is.
+// `cstep` is the record's own threshold (+C_pos or -C_neg).
+template <bool LOGIN>
+__device__ __forceinline__ bool interp_record(const StepArgs& a, Rec& rc, float cstep,
+                                              const int* s_toff) {
+    const int n = (int)(rc.meta & 0x1FFFFFu);
+    const TsSetup s = ts_setup<LOGIN>(a, rc, cstep, s_toff);
+    bool ok = true;
+    int tt0 = 0;
+    for (int j = 0; j < n; ++j) {
+        int tt = 0;
+        ok = ok && ts_fast(s, j, tt);
+        if (j == 0) tt0 = tt;
+    }
+    if (!ok) return false;
+    Rec w;
+    w.meta = rc.meta | kRecReady;
+    if (n == 1) {
+        // the time itself (1/D is never a NaN pattern)
+        w.w0 = (uint32_t)tt0;
+        w.w1 = kTtStored;
+        w.w2 = 0u;
+        w.w3 = 0u;
+    } else {
+        w.w0 = __float_as_uint(s.N1);
+        w.w1 = __float_as_uint(s.invD);
+        w.w2 = __float_as_uint(s.alpha);
+        w.w3 = __float_as_uint(s.beta);
+    }
+    rc = w;
+    return true;
+}
+
+// Interpolation of a ready record with several crossings; `cstep` is the
+// record's own threshold (+C_pos or -C_neg).
+__device__ __forceinline__ TsSetup ready_setup(const Rec& rc, float cstep,
+                                               const int* s_toff) {
+    TsSetup s;
+    const int k = (int)((rc.meta >> 21) & 0xFFu);
+    s.tp = k > 0 ? s_toff[k - 1] : 0;
+    s.dt = s_toff[k] - s.tp;
+    s.dtf = (float)s.dt;
+    s.cstep = cstep;
+    s.N1 = __uint_as_float(rc.w0);
+    s.invD = __uint_as_float(rc.w1);
+    s.alpha = __uint_as_float(rc.w2);
+    s.beta = __uint_as_float(rc.w3);
+    return s;
+}
+
+// The entries of one record per lane, in crossing order (every lane of the
+// wave calls it; lanes with `act` have a record): the timestamps (stored,
+// interpolated, or the FP64 replica where the bound does not decide), the
+// refractory filter against the lane's last emitted time, and the packed
+// entries (or holes) at out[slot + j] while below `cap` (kNoSlot: none).
+// (cu_r, cd_r) are the pixel's lattice counters before the record; q holds
+// the pixel's L_init and thresholds.
+template <bool LOGIN>
+__device__ __forceinline__ void record_entries(const StepArgs& a, const Px& q,
+                                               const Rec& rc, bool act, int cu_r,
+                                               int cd_r, int& tlast, int& emitted,
+                                               int& f64count, uint32_t* out,
+                                               uint32_t slot, int64_t cap,
+                                               uint32_t lane_bits,
+                                               const int* s_toff, int* dg) {
+    const double eps = a.log_eps;
+    const int tref = a.tref;
+    const bool ready = (rc.meta & kRecReady) != 0;
+    const bool up = ((rc.meta >> 29) & 1u) != 0;
+    const int nrec = (int)(rc.meta & 0x1FFFFFu);
+    const uint32_t pbit = up ? 1u : 0u;
+    const bool direct = ready && rc.w1 == kTtStored;
+    if (direct) {
+        const int tt = (int)rc.w0;
+        const bool emit = (tt - tlast) >= tref;
+        if (emit) tlast = tt;
+        emitted += emit ? 1 : 0;
+        if (slot != kNoSlot && (int64_t)slot < cap)
+            out[slot] = emit ? (((uint32_t)tt << 7) | lane_bits | pbit) : kEntryHole;
+    }
+    const bool general = ready && !direct;
+    if (__ballot(general)) {
+        TsSetup s{};
+        int n = 0;
+        if (general) {
+            n = nrec;
+            s = ready_setup(rc, up ? q.cp : -q.cn, s_toff);
+        }
+        for (int j = 0; j < n; ++j) {
+            int tt;
+            ts_fast(s, j, tt);
+            const bool emit = (tt - tlast) >= tref;
+            if (emit) tlast = tt;
+            emitted += emit ? 1 : 0;
+            if (slot != kNoSlot) {
+                const int64_t sl = (int64_t)slot + j;
+                if (sl < cap)
+                    out[sl] = emit ? (((uint32_t)tt << 7) | lane_bits | pbit) : kEntryHole;
+            }
+        }
+    }
+    const bool full = act && !ready;
+    if (__ballot(full)) {
+        ++dg[6];
+        int n = 0;
+        bool f64 = false;
+        TsSetup s{};
+        if (full) {
+            n = nrec;
+            f64 = (rc.meta & kRecF64) != 0;
+            if (!f64) s = ts_setup<LOGIN>(a, rc, up ? q.cp : -q.cn, s_toff);
+            else {
+                const int k = (int)((rc.meta >> 21) & 0xFFu);
+                s.tp = k > 0 ? s_toff[k - 1] : 0;
+                s.dt = s_toff[k] - s.tp;
+            }
+        }
+        double L0d = 0.0, L1d = 0.0;
+        bool have_d = false;
+        for (int j = 0; __ballot(j < n); ++j) {
+            ++dg[5];
+            int tt = 0;
+            bool need = false;
+            if (j < n) need = f64 || !ts_fast(s, j, tt);
+            if (__ballot(need)) {
+                if (need) {
+                    ++dg[1];
+                    if (!have_d) {
+                        const LogPair lp = log_pair64<LOGIN>(rec_prev(rc), rec_I(rc), eps);
+                        L0d = lp.L0;
+                        L1d = lp.L1;
+                        have_d = true;
+                    }
+                    ++f64count;
+                    tt = time64(q.L_init, cu_r, cd_r, q.cp, q.cn, up ? 1 : 0, j, L0d,
+                                L1d, a.T0, s.tp, s.dt);
+                }
+            }
+            if (j < n) {
+                const bool emit = (tt - tlast) >= tref;
+                if (emit) tlast = tt;
+                emitted += emit ? 1 : 0;
+                if (slot != kNoSlot) {
+                    const int64_t sl = (int64_t)slot + j;
+                    if (sl < cap)
+                        out[sl] = emit ? (((uint32_t)tt << 7) | lane_bits | pbit)
+                                       : kEntryHole;
+                }
+            }
+        }
+    }
+}
+
 // Phase B for the queued records of frames <= kcut, which are a prefix of
 // each lane's queue (a lane queues its records in frame order).  Every lane
 // has passed frame kcut, so the drained records are all of the wave's
@@ -618,8 +778,6 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
                                               int& f64count, int* dg) {
     const int lane = lane_id();
     const uint32_t lane_bits = ((uint32_t)lane) << 1;
-    const double eps = a.log_eps;
-    const int tref = a.tref;
 
     // 0. the drained prefix, its crossings and the lane's first slot
     int rd = 0, ent = 0;
@@ -668,32 +826,7 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
         if (act) {
             Rec rc = recs[e];
             const bool up = ((rc.meta >> 29) & 1u) != 0;
-            const int n = (int)(rc.meta & 0x1FFFFFu);
-            const TsSetup s = ts_setup<LOGIN>(a, rc, up ? cp_o : -cn_o, s_toff);
-            bool ok = true;
-            int tt0 = 0;
-            for (int j = 0; j < n; ++j) {
-                int tt = 0;
-                ok = ok && ts_fast(s, j, tt);
-                if (j == 0) tt0 = tt;
-            }
-            if (ok) {
-                Rec w;
-                w.meta = rc.meta | kRecReady;
-                if (n == 1) {
-                    // the time itself (1/D is never a NaN pattern)
-                    w.w0 = (uint32_t)tt0;
-                    w.w1 = kTtStored;
-                    w.w2 = 0u;
-                    w.w3 = 0u;
-                } else {
-                    w.w0 = __float_as_uint(s.N1);
-                    w.w1 = __float_as_uint(s.invD);
-                    w.w2 = __float_as_uint(s.alpha);
-                    w.w3 = __float_as_uint(s.beta);
-                }
-                recs[e] = w;
-            }
+            if (interp_record<LOGIN>(a, rc, up ? cp_o : -cn_o, s_toff)) recs[e] = rc;
         }
     }
     __builtin_amdgcn_wave_barrier();
@@ -706,7 +839,6 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
         const bool act = r < rd;
         Rec rc{0u, 0u, 0u, 0u, 0u};
         if (act) rc = recs[r * kWave + lane];
-        const bool ready = (rc.meta & kRecReady) != 0;
         const bool up = ((rc.meta >> 29) & 1u) != 0;
         const int nrec = (int)(rc.meta & 0x1FFFFFu);
         const int cu_r = cu, cd_r = cd;
@@ -716,99 +848,8 @@ __device__ __forceinline__ void drain_records(const StepArgs& a, const Px& q,
             cu += nrec;
         else
             cd += nrec;
-        const bool direct = ready && rc.w1 == kTtStored;
-        if (direct) {
-            const int tt = (int)rc.w0;
-            const bool emit = (tt - tlast) >= tref;
-            if (emit) tlast = tt;
-            emitted += emit ? 1 : 0;
-            if (rslot != kNoSlot && (int64_t)rslot < cap)
-                out[rslot] = emit ? (((uint32_t)tt << 7) | lane_bits | (up ? 1u : 0u))
-                                  : kEntryHole;
-        }
-        const bool general = ready && !direct;
-        if (__ballot(general)) {
-            TsSetup s{};
-            int n = 0;
-            if (general) {
-                n = nrec;
-                const int k = (int)((rc.meta >> 21) & 0xFFu);
-                s.tp = k > 0 ? s_toff[k - 1] : 0;
-                s.dt = s_toff[k] - s.tp;
-                s.dtf = (float)s.dt;
-                s.cstep = up ? q.cp : -q.cn;
-                s.N1 = __uint_as_float(rc.w0);
-                s.invD = __uint_as_float(rc.w1);
-                s.alpha = __uint_as_float(rc.w2);
-                s.beta = __uint_as_float(rc.w3);
-            }
-            for (int j = 0; j < n; ++j) {
-                int tt;
-                ts_fast(s, j, tt);
-                const bool emit = (tt - tlast) >= tref;
-                if (emit) tlast = tt;
-                emitted += emit ? 1 : 0;
-                if (rslot != kNoSlot) {
-                    const int64_t sl = (int64_t)rslot + j;
-                    if (sl < cap)
-                        out[sl] = emit ? (((uint32_t)tt << 7) | lane_bits |
-                                          (up ? 1u : 0u))
-                                       : kEntryHole;
-                }
-            }
-        }
-        const bool full = act && !ready;
-        if (__ballot(full)) {
-            ++dg[6];
-            int n = 0;
-            bool f64 = false;
-            TsSetup s{};
-            if (full) {
-                n = nrec;
-                f64 = (rc.meta & kRecF64) != 0;
-                if (!f64) s = ts_setup<LOGIN>(a, rc, up ? q.cp : -q.cn, s_toff);
-                else {
-                    const int k = (int)((rc.meta >> 21) & 0xFFu);
-                    s.tp = k > 0 ? s_toff[k - 1] : 0;
-                    s.dt = s_toff[k] - s.tp;
-                }
-            }
-            double L0d = 0.0, L1d = 0.0;
-            bool have_d = false;
-            for (int j = 0; __ballot(j < n); ++j) {
-                ++dg[5];
-                int tt = 0;
-                bool need = false;
-                if (j < n) need = f64 || !ts_fast(s, j, tt);
-                if (__ballot(need)) {
-                    if (need) {
-                        ++dg[1];
-                        if (!have_d) {
-                            const LogPair lp =
-                                log_pair64<LOGIN>(rec_prev(rc), rec_I(rc), eps);
-                            L0d = lp.L0;
-                            L1d = lp.L1;
-                            have_d = true;
-                        }
-                        ++f64count;
-                        tt = time64(q.L_init, cu_r, cd_r, q.cp, q.cn,
-                                    up ? 1 : 0, j, L0d, L1d, a.T0, s.tp, s.dt);
-                    }
-                }
-                if (j < n) {
-                    const bool emit = (tt - tlast) >= tref;
-                    if (emit) tlast = tt;
-                    emitted += emit ? 1 : 0;
-                    if (rslot != kNoSlot) {
-                        const int64_t sl = (int64_t)rslot + j;
-                        if (sl < cap)
-                            out[sl] = emit ? (((uint32_t)tt << 7) | lane_bits |
-                                              (up ? 1u : 0u))
-                                           : kEntryHole;
-                    }
-                }
-            }
-        }
+        record_entries<LOGIN>(a, q, rc, act, cu_r, cd_r, tlast, emitted, f64count,
+                              out, rslot, cap, lane_bits, s_toff, dg);
     }
 
     // 3. the undrained records move to the front of the queue
@@ -955,6 +996,343 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
         drain_records<LOGIN>(a, q, tlast, recs, idx, rcount, simple_mask, nup0,
                              ndn0, K - 1, s_toff, out, cap, slots, over,
                              emitted, f64count, dg);
+}
+
+// ---------------------------------------------------------------------------
+// Split step (launches of many frames): the walk kernel visits the candidate
+// frames as the fused kernel does, but appends every crossing record to its
+// wave's record segment in global memory instead of queueing it in LDS, so
+// lanes never wait and nothing is drained inside the walk.  The timestamp
+// kernel then takes each wave's records, interpolates their times compacted
+// over 64 records at a time, and applies the refractory filter per pixel in
+// crossing order.
+
+// Record meta of the split step (see StepArgs::rec_meta).
+constexpr uint32_t kRmUp = 1u << 14, kRmF64 = 1u << 15;
+
+// Phase A of one lane's pixel over the launch's frames, records to `seg`
+// (the wave's segment), `nrec` the wave's record count (wave-uniform).
+// `fb` is the wave's first sample of frame 0 (wave-uniform), `loff` the
+// lane's pixel from there (0 .. 63); padding lanes read the wave's first
+// pixel (in bounds), which their thresholds keep out of every candidate set.
+template <bool LOGIN>
+__device__ __forceinline__ void walk_append(const StepArgs& a, Px& q,
+                                            const float* fb, uint32_t loff, float* fslab,
+                                            int64_t seg, uint32_t& nrec, int& bad) {
+    const double eps = a.log_eps;
+    const bool force64 = (a.flags & 0x2u) != 0;
+    const int64_t P = a.frame_stride;
+    const int K = a.K;
+    const int lane = lane_id();
+    const uint64_t lt = lanemask_lt();
+    int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    constexpr int U = kChunk;
+    // frames are loaded a chunk ahead; full chunks without per-frame tests
+    float r[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+        r[u] = u < K ? __builtin_nontemporal_load(fb + (int64_t)u * P + loff) : 1.0f;
+
+    for (int kc = 0; kc < K; kc += U) {
+        const int cnt = (K - kc) < U ? (K - kc) : U;
+        uint32_t cm = 0;
+        if (cnt == U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                fslab[u * kWave + lane] = r[u];
+                cm |= ((r[u] > q.Ahi) | (r[u] < q.Alo)) ? (1u << u) : 0u;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                fslab[u * kWave + lane] = r[u];
+                if (u < cnt && ((r[u] > q.Ahi) | (r[u] < q.Alo))) cm |= 1u << u;
+            }
+        }
+        const float* fk = fb + (int64_t)(kc + U) * P;   // the next chunk
+        if (kc + 2 * U <= K) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) r[u] = __builtin_nontemporal_load(fk + (int64_t)u * P + loff);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                r[u] = kc + U + u < K ? __builtin_nontemporal_load(fk + (int64_t)u * P + loff)
+                                      : 1.0f;
+        }
+        const float prev0 = q.prev;
+        // passes while some lane has a candidate frame left in the chunk
+        for (;;) {
+            const bool go = cm != 0u;
+            if (!__ballot(go)) break;
+            const int u = go ? __builtin_ctz(cm) : 0;
+            const float I = fslab[u * kWave + lane];
+            const float Ip = u > 0 ? fslab[(u - 1) * kWave + lane] : prev0;
+            int n;
+            bool up, f64;
+            count_frame<LOGIN>(q, I, Ip, go, force64, eps, n, up, f64, bad, dg);
+            if (go) cm &= ~((2u << u) - 1u);
+            if (bad) {
+                // a lane past the supported range takes no further part
+                q.Ahi = __builtin_inff();
+                q.Alo = -__builtin_inff();
+                cm = 0u;
+            }
+            const uint64_t wm = __ballot(n > 0);
+            if (n > 0) {
+                const int64_t at = seg + nrec + __popcll(wm & lt);
+                const double X1 = up ? q.Xh : q.Xl;
+                a.rec_meta[at] = (uint32_t)lane | ((uint32_t)(kc + u) << 6) |
+                                 (up ? kRmUp : 0u) | (f64 ? kRmF64 : 0u) |
+                                 ((uint32_t)(f64 ? 0 : n) << 16);
+                a.rec_I[at] = I;
+                a.rec_prev[at] = Ip;
+                a.rec_X1[at] = f64 ? __hiloint2double(0, n) : X1;
+                // move the reference by the n crossings
+                if (up)
+                    q.nup += n;
+                else
+                    q.ndn += n;
+                if (f64) {
+                    exact_levels<LOGIN>(q, eps);
+                } else {
+                    const double E = up ? q.Ep : q.En;
+                    q.Xh = lvl_step<LOGIN>(q.Xh, E);
+                    q.Xl = lvl_step<LOGIN>(q.Xl, E);
+                    for (int i = 1; i < n; ++i) {
+                        q.Xh = lvl_step<LOGIN>(q.Xh, E);
+                        q.Xl = lvl_step<LOGIN>(q.Xl, E);
+                    }
+                    refresh_thresholds<LOGIN>(q, eps);
+                }
+                // the rest of the chunk against the new thresholds
+                uint32_t nm = 0;
+                if (u + 1 < cnt) {
+#pragma unroll
+                    for (int v = 0; v < U; ++v) {
+                        const float J = fslab[v * kWave + lane];
+                        nm |= ((J > q.Ahi) | (J < q.Alo)) ? (1u << v) : 0u;
+                    }
+                }
+                cm = nm & ~((2u << u) - 1u) & ((1u << cnt) - 1u);
+            }
+            nrec += (uint32_t)__popcll(wm);
+        }
+        q.prev = fslab[(cnt - 1) * kWave + lane];
+    }
+}
+
+// LDS of the walk kernel per wave: the frame slab.
+constexpr int kWalkLdsPerWave = kChunk * kWave * (int)sizeof(float);
+
+template <bool LOGIN, bool MAP>
+__global__ __launch_bounds__(kStepMaxThreads) void walk_kernel(const StepArgs a) {
+    extern __shared__ char s_dyn[];
+    const int wpb = blockDim.x / kWave;
+    const int w = threadIdx.x / kWave;
+    // the scan that follows starts from cleared status words
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < a.scan_words; i += blockDim.x) a.scan_status[i] = 0ull;
+    Header* hdr = a.hdr;
+    if (hdr->status != 0) return;
+    const int cur = hdr->cur;
+    float* slab = reinterpret_cast<float*>(s_dyn + w * kWalkLdsPerWave);
+    const int lane = lane_id();
+    const int stride = gridDim.x * wpb;
+    for (int wid = __builtin_amdgcn_readfirstlane(blockIdx.x * wpb + w); wid < a.nwaves;
+         wid += stride) {
+        // (the environment record is the same for the whole wave)
+        const EnvRec er = a.envs[a.wave_env[wid]];
+        const int wave0 = __builtin_amdgcn_readfirstlane(er.wave0);
+        const int npix = __builtin_amdgcn_readfirstlane(er.npix);
+        const int64_t foff =
+            (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(er.frame_off >> 32))
+                       << 32) |
+                      (uint32_t)__builtin_amdgcn_readfirstlane((int)er.frame_off));
+        const int local = (wid - wave0) * kWave + lane;
+        const bool valid = local < npix;
+        const int pix = wid * kWave + lane;
+        Px q;
+        load_pixel<LOGIN>(q, a.L_init, a.nud[cur], a.prev[cur], a.tlast[cur],
+                          MAP ? a.c_pos_map : nullptr, MAP ? a.c_neg_map : nullptr,
+                          a.c_pos, a.c_neg, pix, valid, a.log_eps);
+        uint32_t nrec = 0;
+        int bad = 0;
+        walk_append<LOGIN>(a, q, a.frames + foff + (int64_t)(wid - wave0) * kWave,
+                           valid ? (uint32_t)lane : 0u, slab, (int64_t)wid * a.rec_cap,
+                           nrec, bad);
+        // A launch adds fewer than 256 * kMaxCross = 2^28 to a counter, so a
+        // counter that starts at most kMaxCounter (2^30) cannot wrap in int32.
+        if (q.nup > kMaxCounter || q.ndn > kMaxCounter) bad = 1;
+        if (__ballot(bad != 0)) {
+            if (lane == 0) atomicOr(&hdr->internal_err, kErrRange);
+            continue;
+        }
+        // counters and sample of the commit candidate (the timestamp kernel
+        // writes its last emitted times)
+        if (valid) {
+            const int nxt = cur ^ 1;
+            a.nud[nxt][pix] = make_int2(q.nup, q.ndn);
+            a.prev[nxt][pix] = q.prev;
+        }
+        if (lane == 0) a.rec_count[wid] = nrec;
+    }
+}
+
+// Records of a wave handled per round of the timestamp kernel.
+constexpr int kStampWin = 256;
+
+// Timestamp kernel: one wave per tile of 64 pixels, the tile's records taken
+// in windows of kStampWin in walk order.  Per window: 64 records at a time,
+// whatever pixels they belong to, the FP32 interpolation and each record's
+// rank among its pixel's records (a pixel's records are in frame order);
+// then per lane, its pixel's records in frame order: timestamps, refractory
+// filter and entries, as a drain of the fused kernel does.  Staging slots
+// are given out lane-major over the launch (all of lane 0's crossings, then
+// lane 1's, ...), which keeps entries of one microsecond in pixel order, as
+// the sort needs.
+template <bool LOGIN, bool MAP>
+__global__ __launch_bounds__(kWave) void stamp_kernel(const StepArgs a) {
+    __shared__ int s_toff[kMaxFramesPerLaunch];
+    __shared__ Rec s_rec[kStampWin];
+    __shared__ uint16_t s_idx[kStampWin];
+    __shared__ int s_cnt[kWave];
+    Header* hdr = a.hdr;
+    if (hdr->status != 0 || hdr->internal_err != 0) return;
+    const int lane = lane_id();
+    for (int i = lane; i < a.K; i += kWave) s_toff[i] = a.toff[i];
+    s_cnt[lane] = 0;
+    __syncthreads();
+    const int cur = hdr->cur, nxt = cur ^ 1;
+    const int wid = blockIdx.x;
+    const EnvRec er = a.envs[a.wave_env[wid]];
+    const bool valid = (wid - er.wave0) * kWave + lane < er.npix;
+    const int pix = wid * kWave + lane;
+    Px q{};
+    int cu = 0, cd = 0, tlast = kTlastNone, cross = 0;
+    if (valid) {
+        q.L_init = a.L_init[pix];
+        q.cp = MAP ? a.c_pos_map[pix] : a.c_pos;
+        q.cn = MAP ? a.c_neg_map[pix] : a.c_neg;
+        const int2 c0 = a.nud[cur][pix], c1 = a.nud[nxt][pix];
+        cu = c0.x;
+        cd = c0.y;
+        cross = (c1.x - c0.x) + (c1.y - c0.y);
+        tlast = a.tlast[cur][pix];
+    }
+    // the wave's staging segment, lane-major
+    const int64_t incl = (int64_t)wave_incl_scan_u64((uint64_t)cross);
+    const int64_t slots = __shfl(incl, kWave - 1, kWave);
+    int64_t base = (int64_t)wid * a.stage_entries;
+    if (slots > a.stage_entries) {
+        uint64_t bb = 0;
+        if (lane == 0)
+            bb = atomicAdd((unsigned long long*)&hdr->alloc, (unsigned long long)slots);
+        base = (int64_t)a.nwaves * a.stage_entries + (int64_t)__shfl(bb, 0, kWave);
+        if (slots >= 0xFFFFFFFFll || base + slots > a.out_cap) {
+            // the pool is exhausted: the step cannot be committed
+            if (lane == 0) atomicOr(&hdr->stage_full, 1);
+            return;
+        }
+    }
+    uint32_t* out = a.out_key + base;
+    // (slots < 2^32 - 1, so a relative slot never equals kNoSlot)
+    const int64_t cap = slots;
+    uint32_t run = (uint32_t)(incl - cross);
+    const uint32_t lane_bits = ((uint32_t)lane) << 1;
+    const uint64_t lt = lanemask_lt();
+    const int64_t seg = (int64_t)wid * a.rec_cap;
+    const int nrec = (int)a.rec_count[wid];
+    int emitted = 0, f64count = 0;
+    int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    constexpr int C = kStampWin / kWave;
+    for (int w0 = 0; w0 < nrec; w0 += kStampWin) {
+        const int wn = min(kStampWin, nrec - w0);
+        // 1. interpolation and ranks, walk order
+        int own[C], rk[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int i = c * kWave + lane;
+            const bool act = i < wn;
+            uint32_t m = 0u;
+            Rec rc{0u, 0u, 0u, 0u, 0u};
+            if (act) {
+                const int64_t at = seg + w0 + i;
+                m = a.rec_meta[at];
+                const double X1 = a.rec_X1[at];
+                const bool f64 = (m & kRmF64) != 0;
+                const uint32_t n = f64 ? (uint32_t)__double2loint(X1) : (m >> 16);
+                rc.meta = n | (((m >> 6) & 0xFFu) << 21) | ((m & kRmUp) ? (1u << 29) : 0u) |
+                          (f64 ? kRecF64 : 0u);
+                rc.w0 = __float_as_uint(a.rec_I[at]);
+                rc.w1 = __float_as_uint(a.rec_prev[at]);
+                rc.w2 = (uint32_t)__double2loint(X1);
+                rc.w3 = (uint32_t)__double2hiint(X1);
+            }
+            const int owner = (int)(m & 63u);
+            const float cp_o = __shfl(q.cp, owner, kWave);
+            const float cn_o = __shfl(q.cn, owner, kWave);
+            if (act && !(rc.meta & kRecF64)) {
+                const bool up = ((rc.meta >> 29) & 1u) != 0;
+                interp_record<LOGIN>(a, rc, up ? cp_o : -cn_o, s_toff);
+            }
+            if (act) s_rec[i] = rc;
+            uint64_t peers = __ballot(act);
+#pragma unroll
+            for (int b = 0; b < 6; ++b) {
+                const bool bit = ((owner >> b) & 1) != 0;
+                const uint64_t bb = __ballot(bit);
+                peers &= bit ? bb : ~bb;
+            }
+            const int r_in = __popcll(peers & lt);
+            own[c] = owner;
+            rk[c] = act ? s_cnt[owner] + r_in : 0;
+            __builtin_amdgcn_wave_barrier();
+            if (act && r_in == 0) s_cnt[owner] += __popcll(peers);
+            __builtin_amdgcn_wave_barrier();
+        }
+        // 2. pixel order
+        const int cnt = s_cnt[lane];
+        const int coff = wave_incl_scan(cnt) - cnt;
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const int o = __shfl(coff, own[c], kWave);
+            if (c * kWave + lane < wn) s_idx[o + rk[c]] = (uint16_t)(c * kWave + lane);
+        }
+        __builtin_amdgcn_wave_barrier();
+        s_cnt[lane] = 0;
+        // 3. per lane, in frame order: refractory filter and staged entries
+        const int rmax = wave_max(cnt);
+        for (int r = 0; r < rmax; ++r) {
+            const bool act = r < cnt;
+            Rec rc{0u, 0u, 0u, 0u, 0u};
+            if (act) rc = s_rec[s_idx[coff + r]];
+            const bool up = ((rc.meta >> 29) & 1u) != 0;
+            const int n = (int)(rc.meta & 0x1FFFFFu);
+            record_entries<LOGIN>(a, q, rc, act, cu, cd, tlast, emitted, f64count, out,
+                                  run, cap, lane_bits, s_toff, dg);
+            run += (uint32_t)n;
+            if (up)
+                cu += n;
+            else
+                cd += n;
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (valid) {
+        const int last = s_toff[a.K - 1];
+        int tl = kTlastNone;
+        if (tlast != kTlastNone && tlast - last >= -a.tref) tl = tlast - last;
+        a.tlast[nxt][pix] = tl;
+    }
+    const int64_t wemit = wave_sum64(emitted);
+    const int wf64 = wave_sum(f64count);
+    if (lane == 0) {
+        a.seg_base[wid] = base;
+        a.seg_count[wid] = (uint32_t)(wemit < 0xFFFFFFFFll ? wemit : 0xFFFFFFFFll);
+        a.seg_slots[wid] = (uint32_t)slots;
+        if (wf64)
+            atomicAdd((unsigned long long*)&hdr->fp64_evals, (unsigned long long)wf64);
+    }
 }
 
 #ifdef NSIM_TILE_TRACE
@@ -2015,6 +2393,51 @@ hipError_t launch_step(const StepArgs& a, bool log_input, bool has_map,
             NSIM_STEP(false, false);
     }
 #undef NSIM_STEP
+    return hipGetLastError();
+}
+
+hipError_t launch_walk(const StepArgs& a, bool log_input, bool has_map,
+                       int waves_per_block, int max_blocks, hipStream_t s) {
+    if (waves_per_block < 1 || waves_per_block * kWave > kStepMaxThreads ||
+        max_blocks < 0 || a.K < 1 || !a.rec_meta || !a.rec_I || !a.rec_prev ||
+        !a.rec_X1 || !a.rec_count || a.rec_cap < (int64_t)kWave * a.K)
+        return hipErrorInvalidValue;
+    int blocks = (a.nwaves + waves_per_block - 1) / waves_per_block;
+    if (max_blocks > 0 && blocks > max_blocks) blocks = max_blocks;
+    const dim3 grid(blocks);
+    const dim3 block(waves_per_block * kWave);
+    const size_t lds = (size_t)waves_per_block * kWalkLdsPerWave;
+    if (log_input) {
+        if (has_map)
+            hipLaunchKernelGGL((walk_kernel<true, true>), grid, block, lds, s, a);
+        else
+            hipLaunchKernelGGL((walk_kernel<true, false>), grid, block, lds, s, a);
+    } else {
+        if (has_map)
+            hipLaunchKernelGGL((walk_kernel<false, true>), grid, block, lds, s, a);
+        else
+            hipLaunchKernelGGL((walk_kernel<false, false>), grid, block, lds, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp(const StepArgs& a, bool log_input, bool has_map,
+                        hipStream_t s) {
+    if (a.K < 1 || a.stage_entries < 1 || a.stage_entries > kStepMaxLdsEntries ||
+        !a.rec_meta || !a.rec_count || a.nwaves < 1)
+        return hipErrorInvalidValue;
+    const dim3 grid(a.nwaves), block(kWave);
+    if (log_input) {
+        if (has_map)
+            hipLaunchKernelGGL((stamp_kernel<true, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((stamp_kernel<true, false>), grid, block, 0, s, a);
+    } else {
+        if (has_map)
+            hipLaunchKernelGGL((stamp_kernel<false, true>), grid, block, 0, s, a);
+        else
+            hipLaunchKernelGGL((stamp_kernel<false, false>), grid, block, 0, s, a);
+    }
     return hipGetLastError();
 }
 

@@ -92,6 +92,14 @@ struct nsim_ev {
     uint32_t* pass_status = nullptr;
     uint32_t* pass_ctr = nullptr;
     int64_t* env_off = nullptr;               // batched: [n_env + 1]
+    // crossing records of the split step (single streams whose launches
+    // may hold kSplitMinFrames frames or more): [nwaves * rec_cap] each
+    uint32_t* rec_meta = nullptr;
+    float* rec_I = nullptr;
+    float* rec_prev = nullptr;
+    double* rec_X1 = nullptr;
+    uint32_t* rec_count = nullptr;            // [nwaves]
+    int64_t rec_cap = 0;                      // records per wave: 64 per frame
 
     // sensor non-idealities (single streams; all off by default)
     bool fe = false;                  // saturation or bandwidth on
@@ -131,6 +139,8 @@ const char* kNoHandle = "null handle";
 // single streams replay a captured graph for launches of at most this many
 // frames (latency-bound); longer launches are enqueued directly
 constexpr int32_t kGraphMaxFrames = 2;
+// (graphs hold the fused step only)
+static_assert(nsim::kSplitMinFrames > kGraphMaxFrames, "split launches are never captured");
 
 struct DeviceGuard {
     int prev = -1;
@@ -185,7 +195,8 @@ void free_all(nsim_ev* h) {
                     h->q_y, h->q_p, h->stage_key, h->seg_slots, h->seg_base,
                     h->seg_count, h->pref, h->scan_status, h->hist,
                     h->pass_status, h->pass_ctr, h->env_off, h->lp[0], h->lp[1],
-                    h->fe_buf};
+                    h->fe_buf, h->rec_meta, h->rec_I, h->rec_prev, h->rec_X1,
+                    h->rec_count};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (h->hdr_host) (void)hipHostFree(h->hdr_host);
@@ -275,6 +286,7 @@ int bits_for(int64_t span) {
 // before them.
 struct LaunchSet {
     nsim::StepArgs step;
+    bool split = false;   // walk + timestamp kernels instead of the fused step
     nsim::ScanArgs scan;
     nsim::GatherArgs gather;
     nsim::PassArgs pass[nsim::kMaxPasses];
@@ -364,6 +376,16 @@ void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
     a.flags = h->flags;
     a.scan_words = (int32_t)nsim::scan_words(h->nwaves);
     a.scan_status = sc.scan_status;
+    L.split = h->rec_meta != nullptr && kl >= nsim::kSplitMinFrames &&
+              (int64_t)nsim::kWave * kl <= h->rec_cap;
+    if (L.split) {
+        a.rec_meta = h->rec_meta;
+        a.rec_I = h->rec_I;
+        a.rec_prev = h->rec_prev;
+        a.rec_X1 = h->rec_X1;
+        a.rec_count = h->rec_count;
+        a.rec_cap = h->rec_cap;
+    }
     for (int32_t i = 0; i < kl; ++i) a.toff[i] = (int32_t)(t_us[i] - T0);
     const int tbits = bits_for(a.toff[kl - 1]);
     a.key_tbits = tbits;
@@ -445,10 +467,16 @@ hipError_t enqueue_direct(nsim_ev* h, const LaunchSet& L, hipStream_t s,
                           std::pair<hipEvent_t, hipEvent_t>* ev) {
     hipError_t e;
     if (ev && (e = hipEventRecord(ev->first, s)) != hipSuccess) return e;
-    if ((e = nsim::launch_step(L.step, h->log_input || h->fe, h->has_map,
-                               h->waves_per_block, h->step_blocks, s)) !=
-        hipSuccess)
+    const bool log_in = h->log_input || h->fe;
+    if (L.split) {
+        if ((e = nsim::launch_walk(L.step, log_in, h->has_map, h->waves_per_block,
+                                   h->step_blocks, s)) != hipSuccess ||
+            (e = nsim::launch_stamp(L.step, log_in, h->has_map, s)) != hipSuccess)
+            return e;
+    } else if ((e = nsim::launch_step(L.step, log_in, h->has_map, h->waves_per_block,
+                                      h->step_blocks, s)) != hipSuccess) {
         return e;
+    }
     if (ev && (e = hipEventRecord(ev->second, s)) != hipSuccess) return e;
     if ((e = nsim::launch_scan(L.scan, s)) != hipSuccess) return e;
     if ((e = nsim::launch_gather(L.gather, s)) != hipSuccess) return e;
@@ -1143,7 +1171,8 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out) {
         cfg->max_frames_per_launch > nsim::kMaxFramesPerLaunch)
         return NSIM_EINVAL;
     if ((cfg->flags & ~(NSIM_INPUT_LOG | NSIM_FORCE_FP64 | NSIM_DIRECT_LAUNCH |
-                        NSIM_ATOMIC_EMIT | NSIM_ATOMIC_UNSORTED)) != 0)
+                        NSIM_ATOMIC_EMIT | NSIM_ATOMIC_UNSORTED |
+                        NSIM_FUSED_STEP)) != 0)
         return NSIM_EINVAL;
     if ((cfg->flags & NSIM_ATOMIC_UNSORTED) && !(cfg->flags & NSIM_ATOMIC_EMIT))
         return NSIM_EINVAL;
@@ -1163,9 +1192,25 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out) {
                             ? cfg->max_frames_per_launch
                             : nsim::kAutoFramesPerLaunch;
     const int32_t stage = std::max(nsim::kStepLdsEntries, 32 * fpl);
-    const int rc = create_core(h, {d}, cfg->log_eps, cfg->refractory_us,
-                               cfg->capacity_events, cfg->flags,
-                               cfg->max_frames_per_launch, stage, stream);
+    int rc = create_core(h, {d}, cfg->log_eps, cfg->refractory_us,
+                         cfg->capacity_events, cfg->flags,
+                         cfg->max_frames_per_launch, stage, stream);
+    // launches of many frames take the split step: a record per lane and
+    // frame at most (20 B each)
+    if (rc == NSIM_OK && fpl >= nsim::kSplitMinFrames &&
+        !(cfg->flags & (NSIM_FUSED_STEP | NSIM_ATOMIC_EMIT))) {
+        const size_t nrec = (size_t)h->nwaves * nsim::kWave * fpl;
+        hipError_t e = dmalloc(&h->rec_meta, nrec);
+        if (e == hipSuccess) e = dmalloc(&h->rec_I, nrec);
+        if (e == hipSuccess) e = dmalloc(&h->rec_prev, nrec);
+        if (e == hipSuccess) e = dmalloc(&h->rec_X1, nrec);
+        if (e == hipSuccess) e = dmalloc(&h->rec_count, (size_t)h->nwaves);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            rc = e == hipErrorOutOfMemory ? NSIM_ENOMEM : NSIM_EHIP;
+        }
+        h->rec_cap = (int64_t)nsim::kWave * fpl;
+    }
     if (rc) {
         free_all(h);
         delete h;

@@ -27,6 +27,7 @@ NSIM_FORCE_FP64 = 0x2
 NSIM_ATOMIC_EMIT = 0x4
 NSIM_ATOMIC_UNSORTED = 0x8
 NSIM_DIRECT_LAUNCH = 0x10
+NSIM_FUSED_STEP = 0x20
 
 _CODE_NAMES = {
     NSIM_EINVAL: "NSIM_EINVAL", NSIM_ENOMEM: "NSIM_ENOMEM",
@@ -238,7 +239,8 @@ class EventSim:
                  capacity_events=1 << 22, input_is_log=False,
                  force_fp64=False, max_frames_per_launch=0, stream=None,
                  direct_launch=False, emit="ordered", saturation=None,
-                 bandwidth_tau_us=0.0, noise_rate_hz=0.0, noise_seed=0):
+                 bandwidth_tau_us=0.0, noise_rate_hz=0.0, noise_seed=0,
+                 fused_step=False):
         import torch
 
         if not torch.cuda.is_available():
@@ -269,6 +271,7 @@ class EventSim:
         cfg.flags = (NSIM_INPUT_LOG if input_is_log else 0) | \
             (NSIM_FORCE_FP64 if force_fp64 else 0) | \
             (NSIM_DIRECT_LAUNCH if direct_launch else 0) | \
+            (NSIM_FUSED_STEP if fused_step else 0) | \
             {"ordered": 0, "atomic": NSIM_ATOMIC_EMIT,
              "atomic_unsorted": NSIM_ATOMIC_EMIT | NSIM_ATOMIC_UNSORTED}[emit]
         cfg.max_frames_per_launch = int(max_frames_per_launch)

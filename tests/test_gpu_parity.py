@@ -36,13 +36,14 @@ def _sim(W, H, **kw):
 
 def gpu_run(frames, t, c_pos=0.2, c_neg=0.2, log_eps=1e-3, refractory_us=0,
             input_is_log=False, chunks=None, capacity=1 << 22, force_fp64=False,
-            max_frames=0):
+            max_frames=0, fused_step=False):
     dev = _dev()
     fr = torch.as_tensor(frames).to(dev) if not torch.is_tensor(frames) else frames.to(dev)
     F, H, W = fr.shape
     kw = dict(log_eps=log_eps, refractory_us=refractory_us,
               input_is_log=input_is_log, capacity_events=capacity,
-              force_fp64=force_fp64, max_frames_per_launch=max_frames)
+              force_fp64=force_fp64, max_frames_per_launch=max_frames,
+              fused_step=fused_step)
     if np.ndim(c_pos) == 0:
         sim = _sim(W, H, c_pos=float(c_pos), c_neg=float(c_neg), **kw)
     else:

@@ -1,0 +1,155 @@
+"""The split step (a walk kernel that records each lane's crossings, then a
+timestamp kernel over each wave's records) against the fused one-kernel step
+and the FP64 oracle, through the C ABI.
+
+Launches of 16 frames or more take the split step unless NSIM_FUSED_STEP is
+set; both must give the same stream, entry for entry, and match the oracle
+(Sec. 2: crossing counts, interpolated timestamps, refractory filter; the
+output in (t, y, x) order).  The cases exercise what is particular to the
+split: record windows of a wave larger than one round of the timestamp
+kernel (256 records), records whose count needed FP64, staging segments
+given from the pool, launches of 16, 17 and 100 frames, and refractory
+suppression across the windows of a pixel.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2602_15018_amd import scene  # noqa: E402
+from tests.parity import as_numpy, exact_equal  # noqa: E402
+from tests.test_gpu_parity import check_parity, gpu_run  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    return torch.device("cuda", 0)
+
+
+def _busy_scene(F, H=3, W=200, seed=31):
+    rng = np.random.default_rng(seed)
+    n = np.arange(H * W).reshape(H, W)
+    k = np.arange(F)[:, None, None]
+    base = rng.uniform(0.2, 0.8, size=(H, W))[None]
+    busy = (n % 7 == 0)[None]
+    burst = (n % 11 == 3)[None] & ((k % 40) >= 17) & ((k % 40) < 23)
+    ph = rng.uniform(0.0, 2.0 * np.pi, size=(H, W))[None]
+    logI = np.log(base) + np.where(busy, 0.9, 0.02) * np.sin(2.1 * k + ph)
+    logI = logI + np.where(burst, 0.7 * (2 * (k % 2) - 1), 0.0)
+    fr = np.exp(logI).astype(np.float32)
+    cp = rng.uniform(0.1, 0.3, size=(H, W)).astype(np.float32)
+    cn = rng.uniform(0.1, 0.3, size=(H, W)).astype(np.float32)
+    return fr, 5 + 500 * np.arange(F), cp, cn
+
+
+@pytest.mark.parametrize("max_frames", [0, 16, 17, 100])
+def test_split_busy_lanes(max_frames):
+    """Busy and bursting pixels: hundreds of records per wave and launch
+    (several timestamp rounds), multi-crossing records, refractory holes."""
+    _dev()
+    fr, t, cp, cn = _busy_scene(150)
+    rep, got, ref, st = check_parity(fr, t, 200, c_pos=cp, c_neg=cn,
+                                     refractory_us=40, max_frames=max_frames)
+    assert rep["n_oracle"] > 5000
+    assert rep["exact"], rep
+    fused, _ = gpu_run(fr, t, c_pos=cp, c_neg=cn, refractory_us=40,
+                       max_frames=max_frames, fused_step=True)
+    assert exact_equal(got, fused)
+
+
+def test_split_log_input_fp64_counts_and_pool():
+    """Log input with jumps of tens of thresholds per frame over 40 frames:
+    FP64-counted records (counts carried in the record's level word),
+    timestamps from the FP64 replica, and waves whose crossings outgrow the
+    fixed staging segment (pool segments)."""
+    _dev()
+    rng = np.random.default_rng(21)
+    H, W, F = 9, 70, 40
+    L = np.cumsum(rng.normal(0, 6.0, size=(F, H, W)), axis=0).astype(np.float32)
+    cp = rng.uniform(0.05, 0.5, size=(H, W)).astype(np.float32)
+    cn = rng.uniform(0.05, 0.5, size=(H, W)).astype(np.float32)
+    t = 1000 * np.arange(F)
+    rep, got, ref, st = check_parity(L, t, W, c_pos=cp, c_neg=cn,
+                                     input_is_log=True, refractory_us=30)
+    assert rep["n_oracle"] > 50000
+    assert rep["exact"], rep
+    assert st["fp64_evaluations"] > 0
+    fused, _ = gpu_run(L, t, c_pos=cp, c_neg=cn, input_is_log=True,
+                       refractory_us=30, fused_step=True)
+    assert exact_equal(got, fused)
+
+
+def test_split_force_fp64_and_scalar_thresholds():
+    """Every candidate counted and timed in FP64 (records all FP64): the
+    same stream as the FP32 fast path, the fused step and the oracle."""
+    w = scene.WORKLOADS["hd1280x720_2000f_2000fps_agile"]
+    H, W, F = 64, 130, 40
+    fr = scene.render_workload(w, 0, F, device=_dev(), height=H, width=W)
+    t = scene.frame_times(w, 0, F)
+    a, sa = gpu_run(fr, t, c_pos=0.25, c_neg=0.18, refractory_us=100)
+    b, sb = gpu_run(fr, t, c_pos=0.25, c_neg=0.18, refractory_us=100,
+                    force_fp64=True)
+    c, _ = gpu_run(fr, t, c_pos=0.25, c_neg=0.18, refractory_us=100,
+                   force_fp64=True, fused_step=True)
+    assert len(a[0]) > 1000
+    assert sb["fp64_evaluations"] > sa["fp64_evaluations"]
+    assert exact_equal(a, b) and exact_equal(b, c)
+    rep, got, ref, st = check_parity(fr.cpu().numpy(), t, W, c_pos=0.25,
+                                     c_neg=0.18, refractory_us=100)
+    assert rep["exact"], rep
+
+
+def test_split_stage_pool_exhausted_is_all_or_nothing():
+    """A queue too small for one launch's crossings: the timestamp kernel
+    finds the staging pool exhausted and nothing is committed; with a large
+    queue the split and fused steps give the same stream."""
+    from paper_2602_15018_amd.ev import EventSim, NsimError
+    dev = _dev()
+    rng = np.random.default_rng(5)
+    H, W, F = 8, 64, 30
+    L = np.cumsum(rng.normal(0, 4.0, size=(F, H, W)), axis=0).astype(np.float32)
+    fr = torch.as_tensor(L, device=dev)
+    t = np.arange(F, dtype=np.int64) * 1000
+    sim = EventSim(W, H, c_pos=0.1, c_neg=0.1, input_is_log=True,
+                   capacity_events=2000)
+    sim.step(fr, t)
+    with pytest.raises(NsimError) as ei:
+        sim.sync()
+    assert ei.value.code == -3
+    assert sim.committed_time() == t[0]
+    assert len(as_numpy(sim.drain())[0]) == 0
+    sim.close()
+    a, _ = gpu_run(L, t, c_pos=0.1, c_neg=0.1, input_is_log=True)
+    b, _ = gpu_run(L, t, c_pos=0.1, c_neg=0.1, input_is_log=True, fused_step=True)
+    assert len(a[0]) > 100000
+    assert exact_equal(a, b)
+
+
+def test_split_equals_fused_full_hd_stream():
+    """The whole 1280x720, 2000-frame stream in the benchmark's launch
+    configuration: split and fused steps give identical streams."""
+    dev = _dev()
+    w = scene.WORKLOADS["hd1280x720_2000f_2000fps_agile"]
+    F = w.frames
+    t = scene.frame_times(w)
+    cp, cn = scene.threshold_maps(w)
+    frames = torch.empty((F, w.height, w.width), dtype=torch.float32, device=dev)
+    scene.render_workload(w, 0, F, device=dev, out=frames)
+    out = []
+    for fused in (False, True):
+        from paper_2602_15018_amd.ev import EventSim
+        est = int(0.09 * w.pixels * (F - 1)) + (1 << 20)
+        sim = EventSim(w.width, w.height, c_pos_map=cp, c_neg_map=cn,
+                       c_pos=w.c_nominal, c_neg=w.c_nominal, log_eps=w.log_eps,
+                       refractory_us=w.refractory_us, capacity_events=est,
+                       fused_step=fused)
+        sim.step(frames, t)
+        out.append(sim.drain())
+        sim.close()
+        print("hd stream fused=%s: %d events" % (fused, out[-1][0].numel()), flush=True)
+    assert out[0][0].numel() > 10 ** 8
+    for a, b in zip(out[0], out[1]):
+        assert torch.equal(a, b)
