@@ -94,6 +94,12 @@ int nsim_up_log_frames(const float* I, float* L, int64_t n, float eps,
 int nsim_up_diag_mfma(const uint16_t* A, const uint16_t* B, float* C,
                       void* stream);
 
+/* Diagnostic: C = A B for A 16x32 and B 32x16 bfloat16 row-major (device)
+ * with one 16x16x32 matrix-core instruction (gfx950), C 16x16 FP32
+ * row-major (device). */
+int nsim_up_diag_mfma32(const uint16_t* A, const uint16_t* B, float* C,
+                        void* stream);
+
 #ifdef __cplusplus
 }
 #endif

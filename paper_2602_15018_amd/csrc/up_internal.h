@@ -40,6 +40,12 @@ struct ConvArgs {
     const uint16_t* inB;
     const uint16_t* maskA;
     const uint16_t* wt;     // [Cout][Kpad]
+    // The same weights for the LDS-staged kernel (used when set): input
+    // channels padded to C8 (8, or a multiple of 16), K in chunks of
+    // conv8_chunk(C8) channels (k = chunk KC + tap CW + c), rows of
+    // Kpad8 = conv8_kpad(C8) bfloat16.
+    const uint16_t* wt8;
+    int32_t C8, Kpad8;
     const float* bias;      // [Cout] or null
     uint16_t* outA;
     uint16_t* outB;
@@ -73,6 +79,20 @@ struct WgradArgs {
 };
 
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s);
+// The LDS-staged convolution (conv8_kernel): input channels padded to C8 (8,
+// or a multiple of 16) and staged in chunks of conv8_chunk(C8) channels.
+constexpr int kConv8Rows = 4;        // output rows per workgroup (one per wave)
+constexpr int kConv8Cols = 64;       // output columns per workgroup
+__host__ __device__ constexpr int conv8_chunk(int c8) { return c8 >= 16 ? 16 : 8; }
+// pixel stride of a staged tile: an odd number of 16-byte units
+__host__ __device__ constexpr int conv8_stride(int cw) { return ((cw / 8) & 1) ? cw : cw + 8; }
+// K of the packed weights: per chunk 9 taps of CW channels, rounded up to 32
+__host__ __device__ constexpr int conv8_kpad(int c8) {
+    return (c8 / conv8_chunk(c8)) * ((9 * conv8_chunk(c8) + 31) / 32 * 32);
+}
+constexpr int64_t conv8_lds_bytes(int c8) {
+    return (int64_t)(kConv8Rows + 2) * (kConv8Cols + 2) * conv8_stride(conv8_chunk(c8)) * 2;
+}
 hipError_t launch_wgrad(const WgradArgs& a, int n_row_blocks, hipStream_t s);
 // out[i] = sum over b of part[b * stride + src(i)], with src remapping the
 // padded [Cout][9][Cpad] layout to [Cout][9][Ci] (identity for biases).
@@ -103,6 +123,11 @@ hipError_t launch_pack_weights(const float* w, uint16_t* fwd, uint16_t* bwd,
                                int KpadB, hipStream_t s);
 hipError_t launch_log_frames(const float* I, float* L, int64_t n, float eps,
                              hipStream_t s);
+hipError_t launch_mfma32_probe(const uint16_t* A, const uint16_t* B, float* C,
+                              hipStream_t s);
+hipError_t launch_pack_weights8(const float* w, uint16_t* fwd8, uint16_t* bwd8,
+                                int Cout, int Ci, int C8, int Kpad8, int KpadB8,
+                                hipStream_t s);
 hipError_t launch_mfma_probe(const uint16_t* A, const uint16_t* B, float* C,
                              hipStream_t s);
 hipError_t launch_sum(const float* x, int n, float scale, float* out,

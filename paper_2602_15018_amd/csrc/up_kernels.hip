@@ -197,6 +197,185 @@ __global__ __launch_bounds__(kConvThreads) void conv_kernel(const ConvArgs a) {
     }
 }
 
+// 16x16x32 MFMA (gfx950): per lane l, 8 elements e:
+//   A[row = l % 16][k = 8 (l / 16) + e],  B[k = 8 (l / 16) + e][col = l % 16],
+//   D as for 16x16x16.  (Only the pairing of A's and B's k slots matters for
+//   the product; the probe below checks the layout.)
+typedef short s8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ f4 mfma32(s8 a, s8 b, f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a),
+                                                   __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+
+// Convolution with its input staged in LDS, in chunks of CW input channels
+// (16, or 8 for an 8-channel input).  A workgroup owns kConv8Rows output
+// rows (one per wave) by kConv8Cols columns of one image; per chunk it
+// stages the input tile its taps reach, rows y0 - 1 .. y0 + kConv8Rows and
+// columns x0 - 1 .. x0 + kConv8Cols, as [row][column][channel] with a
+// pixel's CW channels contiguous (zero outside the image, past Cin, or where
+// the ReLU mask is not positive) and the pixel stride padded to an odd
+// number of 16-byte units, so that 16 lanes reading 16 bytes at consecutive
+// pixels hit distinct banks.  An MFMA operand of A is then one 16-byte LDS
+// read: eight channels of one tap at one pixel.  K runs chunk by chunk,
+// k = chunk KC + tap CW + c with KC = 9 CW rounded up to 32 (taps past the
+// ninth are zero); B is eight consecutive k of one output channel from the
+// packed weights (global memory, shared by the waves in the cache).
+template <int NT>
+__global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
+    extern __shared__ __align__(16) uint16_t s_in[];
+    constexpr int HC = kConv8Cols + 2;
+    constexpr int TP = (kConv8Rows + 2) * HC;    // pixels of a staged tile
+    const int C8 = a.C8;
+    const int CW = conv8_chunk(C8), CS = conv8_stride(CW);
+    const int KC = (9 * CW + 31) / 32 * 32;
+    const int nchunks = C8 / CW;
+    const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
+    const int x0 = blockIdx.x * kConv8Cols, y0 = blockIdx.y * kConv8Rows, n = blockIdx.z;
+    const int Hh = a.H >> 1, Wh = a.W >> 1;
+    const int y = y0 + wv;
+    const bool row_ok = y < a.H;
+    const int r16 = lane & 15, g = lane >> 4;
+    // 16-byte staging units when every chunk lies in one source (then
+    // C8 = Cin and no chunk reaches past a source's channels)
+    const bool wide = (a.Ca % 16) == 0 && (a.Cb % 16) == 0 && CW == 16;
+
+    f4 acc[4][NT];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    const uint16_t* wrow = a.wt8 + (int64_t)r16 * a.Kpad8 + 8 * g;
+    const int64_t wstride = (int64_t)16 * a.Kpad8;
+
+    for (int ch = 0; ch < nchunks; ++ch) {
+        const int cbase = ch * CW;
+        if (ch) __syncthreads();   // the previous chunk's operands are read
+        // 1. the chunk's input tile
+        if (wide) {
+            // two units of eight channels per pixel, from one source
+            const bool fromA = cbase < a.Ca;
+            const uint16_t* src = fromA ? a.inA : a.inB;
+            const int Cs = fromA ? a.Ca : a.Cb;
+            const int cofs = fromA ? cbase : cbase - a.Ca;
+            const bool half = !fromA && a.b_half;
+            const int Hs = half ? Hh : a.H, Ws = half ? Wh : a.W;
+            for (int e = tid; e < 2 * TP; e += kConvThreads) {
+                const int pp = e >> 1, u = e & 1;
+                const int hr = pp / HC, hc = pp - hr * HC;
+                const int yy = y0 - 1 + hr, xx = x0 - 1 + hc;
+                uint4 v = make_uint4(0u, 0u, 0u, 0u);
+                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+                    const int sy = half ? yy >> 1 : yy, sx = half ? xx >> 1 : xx;
+                    const int64_t off = ((int64_t)(n * Hs + sy) * Ws + sx) * Cs + cofs + 8 * u;
+                    v = *reinterpret_cast<const uint4*>(src + off);
+                    if (fromA && a.maskA) {
+                        const s8 mk = *reinterpret_cast<const s8*>(a.maskA + off);
+                        uint32_t m[4];
+#pragma unroll
+                        for (int q = 0; q < 4; ++q)
+                            m[q] = (bf_positive(mk[2 * q]) ? 0xFFFFu : 0u) |
+                                   (bf_positive(mk[2 * q + 1]) ? 0xFFFF0000u : 0u);
+                        v.x &= m[0];
+                        v.y &= m[1];
+                        v.z &= m[2];
+                        v.w &= m[3];
+                    }
+                }
+                *reinterpret_cast<uint4*>(s_in + pp * CS + 8 * u) = v;
+            }
+        } else {
+            // units of four channels, each from A, B or zero padding
+            const int U = CW >> 2;
+            for (int e = tid; e < U * TP; e += kConvThreads) {
+                const int pp = e / U, u = e - pp * U;
+                const int hr = pp / HC, hc = pp - hr * HC;
+                const int yy = y0 - 1 + hr, xx = x0 - 1 + hc, c = cbase + 4 * u;
+                uint2 v = make_uint2(0u, 0u);
+                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+                    if (c < a.Ca) {
+                        const int64_t off = ((int64_t)(n * a.H + yy) * a.W + xx) * a.Ca + c;
+                        v = *reinterpret_cast<const uint2*>(a.inA + off);
+                        if (a.maskA) {
+                            const s4 mk = *reinterpret_cast<const s4*>(a.maskA + off);
+                            v.x &= (bf_positive(mk[0]) ? 0xFFFFu : 0u) |
+                                   (bf_positive(mk[1]) ? 0xFFFF0000u : 0u);
+                            v.y &= (bf_positive(mk[2]) ? 0xFFFFu : 0u) |
+                                   (bf_positive(mk[3]) ? 0xFFFF0000u : 0u);
+                        }
+                    } else if (c < a.Cin) {
+                        const int cb = c - a.Ca;
+                        const int64_t pix =
+                            a.b_half ? ((int64_t)(n * Hh + (yy >> 1)) * Wh + (xx >> 1))
+                                     : ((int64_t)(n * a.H + yy) * a.W + xx);
+                        v = *reinterpret_cast<const uint2*>(a.inB + pix * a.Cb + cb);
+                    }
+                }
+                *reinterpret_cast<uint2*>(s_in + pp * CS + 4 * u) = v;
+            }
+        }
+        __syncthreads();
+
+        // 2. the chunk's K steps for the wave's row: pixels x0 + 16 i +
+        //    (lane % 16), i = 0..3; lane group g takes k = 32 ks + 8 g of the
+        //    chunk, i.e. tap (32 ks + 8 g) / CW, channels from (.. % CW)
+        if (row_ok) {
+            const uint16_t* wk = wrow + ch * KC;
+            for (int ks = 0; ks < KC / 32; ++ks) {
+                const int kl = 32 * ks + 8 * g;
+                const int tap = kl / CW, c = kl - tap * CW;
+                s8 af[4];
+                if (tap < 9) {
+                    const int ky = tap / 3, kx = tap - 3 * ky;
+                    const uint16_t* p = s_in + ((wv + ky) * HC + kx + r16) * CS + c;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        af[i] = *reinterpret_cast<const s8*>(p + 16 * i * CS);
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) af[i] = s8{0, 0, 0, 0, 0, 0, 0, 0};
+                }
+#pragma unroll
+                for (int j = 0; j < NT; ++j) {
+                    const s8 bf = *reinterpret_cast<const s8*>(wk + j * wstride + 32 * ks);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[i][j] = mfma32(af[i], bf, acc[i][j]);
+                }
+            }
+        }
+    }
+    if (!row_ok) return;
+
+    // 3. bias, ReLU, bfloat16 NHWC output (element r of lane l: pixel
+    //    16 i + 4 (l / 16) + r, channel 16 j + l % 16)
+    const int CoB = a.Cout - a.CoA;
+    const int64_t mrow = (int64_t)(n * a.H + y) * a.W;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = 16 * j + r16;
+        const float b = a.bias ? a.bias[co] : 0.f;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int x = x0 + 16 * i + 4 * g + r;
+                if (x >= a.W) continue;
+                const int64_t m = mrow + x;
+                float v = acc[i][j][r] + b;
+                if (a.relu) v = fmaxf(v, 0.f);
+                if (co < a.CoA) {
+                    uint16_t* p = a.outA + m * a.CoA + co;
+                    if (a.accumA) v += bf2f(*p);
+                    *p = f2bf(v);
+                } else {
+                    a.outB[m * CoB + (co - a.CoA)] = f2bf(v);
+                }
+            }
+        }
+    }
+}
+
 // Weight gradient, staged by image rows.  Block (tg, rb) owns the 16 x 16
 // output tiles [kWgTiles tg, kWgTiles (tg + 1)) of the [Cout][Kpad] grid
 // (wave w: tiles w, w + 4, ...) and the image rows [rb rows_per_block, ...)
@@ -588,6 +767,49 @@ __global__ void mfma_probe_kernel(const uint16_t* A, const uint16_t* B, float* C
     for (int r = 0; r < 4; ++r) C[(4 * g4 + r) * 16 + r16] = d[r];
 }
 
+// A, B: 16 x 32 and 32 x 16 row-major bfloat16; C = A B (16 x 16 FP32).
+__global__ void mfma32_probe_kernel(const uint16_t* A, const uint16_t* B, float* C) {
+    const int l = threadIdx.x;
+    const int r16 = l & 15, g = l >> 4;
+    s8 a, b;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        a[e] = (short)A[r16 * 32 + 8 * g + e];
+        b[e] = (short)B[(8 * g + e) * 16 + r16];
+    }
+    const f4 d = mfma32(a, b, f4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C[(4 * g + r) * 16 + r16] = d[r];
+}
+
+// Weights of the staged kernel, K in chunks of CW input channels (see
+// conv8_kernel): fwd8[co][k], k = chunk KC + tap CW + c for input channel
+// chunk CW + c (< Ci) and tap < 9, zero elsewhere, rows of Kpad8; bwd8[ci][k]
+// the same for the flipped kernel, whose input channels are the Cout output
+// channels, rows of KpadB8.
+__global__ void pack_weights8_kernel(const float* w, uint16_t* fwd8, uint16_t* bwd8,
+                                     int Cout, int Ci, int C8, int Kpad8, int KpadB8) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (fwd8 && i < Cout * Kpad8) {
+        const int CW = conv8_chunk(C8), KC = (9 * CW + 31) / 32 * 32;
+        const int co = i / Kpad8, k = i - co * Kpad8;
+        const int chunk = k / KC, r = k - chunk * KC;
+        const int tap = r / CW, c = chunk * CW + (r - tap * CW);
+        float v = 0.f;
+        if (tap < 9 && c < Ci) v = w[(co * 9 + tap) * Ci + c];
+        fwd8[i] = f2bf(v);
+    }
+    if (bwd8 && i < Ci * KpadB8) {
+        const int CW = conv8_chunk(Cout), KC = (9 * CW + 31) / 32 * 32;
+        const int ci = i / KpadB8, k = i - ci * KpadB8;
+        const int chunk = k / KC, r = k - chunk * KC;
+        const int tp = r / CW, co = chunk * CW + (r - tp * CW);
+        float v = 0.f;
+        if (tp < 9 && co < Cout) v = w[(co * 9 + (8 - tp)) * Ci + ci];
+        bwd8[i] = f2bf(v);
+    }
+}
+
 __global__ void sum_kernel(const float* x, int n, float scale, float* out) {
     __shared__ float s[256];
     float v = 0.f;
@@ -611,6 +833,24 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
         a.Cout % 16 || a.CoA > a.Cout || a.CoA < 0 || M <= 0 || M > kConvMaxPixels ||
         (a.b_half && (a.H % 2 || a.W % 2)))
         return hipErrorInvalidValue;
+    if (a.wt8) {
+        if (a.C8 < a.Cin || a.C8 % conv8_chunk(a.C8) || a.Kpad8 != conv8_kpad(a.C8) ||
+            a.N > 65535 || (a.H + kConv8Rows - 1) / kConv8Rows > 65535)
+            return hipErrorInvalidValue;
+        const dim3 grid((a.W + kConv8Cols - 1) / kConv8Cols,
+                        (a.H + kConv8Rows - 1) / kConv8Rows, a.N);
+        const dim3 block(kConvThreads);
+        const size_t lds = (size_t)conv8_lds_bytes(a.C8);
+        switch (a.Cout / 16) {
+        case 1: hipLaunchKernelGGL(conv8_kernel<1>, grid, block, lds, s, a); break;
+        case 2: hipLaunchKernelGGL(conv8_kernel<2>, grid, block, lds, s, a); break;
+        case 3: hipLaunchKernelGGL(conv8_kernel<3>, grid, block, lds, s, a); break;
+        case 4: hipLaunchKernelGGL(conv8_kernel<4>, grid, block, lds, s, a); break;
+        case 6: hipLaunchKernelGGL(conv8_kernel<6>, grid, block, lds, s, a); break;
+        default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     const dim3 grid(blocks_for(M, 64 * (kConvThreads / kWave))), block(kConvThreads);
     switch (a.Cout / 16) {
     case 1: hipLaunchKernelGGL(conv_kernel<1>, grid, block, 0, s, a); break;
@@ -726,6 +966,21 @@ hipError_t launch_log_frames(const float* I, float* L, int64_t n, float eps,
                              hipStream_t s) {
     hipLaunchKernelGGL(log_frames_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                        I, L, n, eps);
+    return hipGetLastError();
+}
+
+hipError_t launch_mfma32_probe(const uint16_t* A, const uint16_t* B, float* C,
+                              hipStream_t s) {
+    hipLaunchKernelGGL(mfma32_probe_kernel, dim3(1), dim3(64), 0, s, A, B, C);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_weights8(const float* w, uint16_t* fwd8, uint16_t* bwd8,
+                                int Cout, int Ci, int C8, int Kpad8, int KpadB8,
+                                hipStream_t s) {
+    const int n = Cout * Kpad8 > Ci * KpadB8 ? Cout * Kpad8 : Ci * KpadB8;
+    hipLaunchKernelGGL(pack_weights8_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, w,
+                       fwd8, bwd8, Cout, Ci, C8, Kpad8, KpadB8);
     return hipGetLastError();
 }
 

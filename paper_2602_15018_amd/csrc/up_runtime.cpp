@@ -36,9 +36,12 @@ int round16(int k) { return (k + 15) / 16 * 16; }
 struct Layer {
     int ci, cpad, co;
     int K, Kpad, KB, KpadB;
+    int c8, Kpad8, KpadB8;       // the staged kernel's layout (see nup::conv8_kpad)
     int64_t w_off, b_off;        // into the flat FP32 parameters
     uint16_t* wf = nullptr;      // forward operand [co][Kpad]
     uint16_t* wb = nullptr;      // backward-data operand [ci][KpadB]
+    uint16_t* wf8 = nullptr;     // forward operand [co][Kpad8]
+    uint16_t* wb8 = nullptr;     // backward-data operand [ci][KpadB8]
 };
 
 }  // namespace
@@ -132,6 +135,8 @@ int pack(nsim_up* h) {
         Layer& l = h->L[i];
         UP_HIP(h, nup::launch_pack_weights(h->p + l.w_off, l.wf, l.wb, l.co, l.ci,
                                            l.cpad, l.Kpad, l.KpadB, h->stream));
+        UP_HIP(h, nup::launch_pack_weights8(h->p + l.w_off, l.wf8, l.wb8, l.co, l.ci,
+                                            l.c8, l.Kpad8, l.KpadB8, h->stream));
     }
     h->packed = true;
     return NSIM_UP_OK;
@@ -166,6 +171,10 @@ nup::ConvArgs conv_args(const Layer& l, const uint16_t* inA, int Ca,
     a.CoA = l.co;
     a.K = l.K;
     a.Kpad = l.Kpad;
+    // the LDS-staged kernel
+    a.wt8 = l.wf8;
+    a.C8 = l.c8;
+    a.Kpad8 = l.Kpad8;
     a.b_half = b_half;
     a.relu = 1;
     return a;
@@ -271,6 +280,9 @@ int bwd_data(nsim_up* h, int li, const uint16_t* dy, const uint16_t* y,
     a.CoA = CoA;
     a.K = l.KB;
     a.Kpad = l.KpadB;
+    a.wt8 = l.wb8;
+    a.C8 = l.co;
+    a.Kpad8 = l.KpadB8;
     a.accumA = accum;
     UP_HIP(h, nup::launch_conv(a, h->stream));
     return NSIM_UP_OK;
@@ -370,6 +382,9 @@ int nsim_up_create(const nsim_up_config* cfg, void* stream, nsim_up_t** out) {
         l.Kpad = round16(l.K);
         l.KB = 9 * l.co;
         l.KpadB = round16(l.KB);
+        l.c8 = l.cpad <= 8 ? 8 : round16(l.cpad);
+        l.Kpad8 = nup::conv8_kpad(l.c8);
+        l.KpadB8 = nup::conv8_kpad(l.co);
         l.w_off = off;
         off += (int64_t)l.co * 9 * l.ci;
         l.b_off = off;
@@ -394,6 +409,8 @@ int nsim_up_create(const nsim_up_config* cfg, void* stream, nsim_up_t** out) {
         Layer& l = h->L[i];
         chk(alloc(h, &l.wf, (int64_t)l.co * l.Kpad));
         chk(alloc(h, &l.wb, (int64_t)l.cpad * l.KpadB));
+        chk(alloc(h, &l.wf8, (int64_t)l.co * l.Kpad8));
+        chk(alloc(h, &l.wb8, (int64_t)l.cpad * l.KpadB8));
     }
     chk(alloc(h, &h->x, 4 * M));
     chk(alloc(h, &h->a1, 16 * M));
@@ -557,6 +574,14 @@ int nsim_up_diag_mfma(const uint16_t* A, const uint16_t* B, float* C,
                       void* stream) {
     if (!A || !B || !C) return NSIM_UP_EINVAL;
     return nup::launch_mfma_probe(A, B, C, (hipStream_t)stream) == hipSuccess
+               ? NSIM_UP_OK
+               : NSIM_UP_EHIP;
+}
+
+int nsim_up_diag_mfma32(const uint16_t* A, const uint16_t* B, float* C,
+                        void* stream) {
+    if (!A || !B || !C) return NSIM_UP_EINVAL;
+    return nup::launch_mfma32_probe(A, B, C, (hipStream_t)stream) == hipSuccess
                ? NSIM_UP_OK
                : NSIM_UP_EHIP;
 }

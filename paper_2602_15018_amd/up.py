@@ -19,6 +19,7 @@ EXPORTED = [
     "nsim_up_forward", "nsim_up_backward", "nsim_up_get_grads",
     "nsim_up_adam_step", "nsim_up_train_step", "nsim_up_log_frames",
     "nsim_up_diag_mfma",
+    "nsim_up_diag_mfma32",
 ]
 
 _lib = None
@@ -59,6 +60,7 @@ def load_library(path: str = _LIB_PATH):
         "nsim_up_train_step": ([vp, vp, vp, vp, i32, i32, i32, f32, vp], c_int),
         "nsim_up_log_frames": ([vp, vp, i64, f32, vp], c_int),
         "nsim_up_diag_mfma": ([vp, vp, vp, vp], c_int),
+        "nsim_up_diag_mfma32": ([vp, vp, vp, vp], c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -179,6 +181,19 @@ def log_frames(I, eps=1e-3):
     if rc != 0:
         raise UpError("nsim_up_log_frames failed")
     return L
+
+
+def mfma32_probe(A_bf16, B_bf16):
+    """C = A B (16x32 times 32x16) with one 16x16x32 matrix-core instruction;
+    inputs are int16 device tensors holding bfloat16 bit patterns."""
+    import torch
+    lib = load_library()
+    C = torch.empty((16, 16), dtype=torch.float32, device=A_bf16.device)
+    rc = lib.nsim_up_diag_mfma32(_ptr(A_bf16.contiguous()), _ptr(B_bf16.contiguous()),
+                                 _ptr(C), _stream())
+    if rc != 0:
+        raise UpError("nsim_up_diag_mfma32 failed")
+    return C
 
 
 def mfma_probe(A_bf16, B_bf16):

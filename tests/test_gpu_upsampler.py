@@ -96,6 +96,19 @@ def test_mfma_layout_probe():
     np.testing.assert_array_equal(C, A @ B)
 
 
+def test_mfma32_layout_probe():
+    """One 16x16x32 matrix-core instruction (gfx950) on integer-valued
+    bfloat16 operands (exact in FP32) equals the matrix product."""
+    from paper_2602_15018_amd.up import mfma32_probe
+    dev = _dev()
+    r = np.random.default_rng(5)
+    A = r.integers(-8, 9, size=(16, 32)).astype(np.float32)
+    B = r.integers(-8, 9, size=(32, 16)).astype(np.float32)
+    bits = lambda M: torch.from_numpy((M.view(np.uint32) >> 16).astype(np.int16)).to(dev)
+    C = mfma32_probe(bits(A), bits(B)).cpu().numpy()
+    np.testing.assert_array_equal(C, A @ B)
+
+
 def test_log_frames_kernel():
     from paper_2602_15018_amd.up import log_frames
     dev = _dev()
