@@ -46,6 +46,9 @@ struct ConvArgs {
     // Kpad8 = conv8_kpad(C8) bfloat16.
     const uint16_t* wt8;
     int32_t C8, Kpad8;
+    // With the staged kernel: also the 2x2 average of the output (outA only,
+    // no accumulation) as [N][H/2][W/2][Cout] bfloat16, or null.
+    uint16_t* pool_out;
     const float* bias;      // [Cout] or null
     uint16_t* outA;
     uint16_t* outB;

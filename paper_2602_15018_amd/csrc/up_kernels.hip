@@ -221,7 +221,14 @@ __device__ __forceinline__ f4 mfma32(s8 a, s8 b, f4 c) {
 // read: eight channels of one tap at one pixel.  K runs chunk by chunk,
 // k = chunk KC + tap CW + c with KC = 9 CW rounded up to 32 (taps past the
 // ninth are zero); B is eight consecutive k of one output channel from the
-// packed weights (global memory, shared by the waves in the cache).
+// packed weights (global memory, shared by the waves in the cache).  When
+// every chunk lies in one source, chunks are loaded with 16-byte loads one
+// chunk ahead (into registers, while the matrix cores work on the current
+// one).  With pool_out the 2x2 average of the stored outputs is written
+// too, row pairs meeting in LDS.
+constexpr int kC8Units = (2 * (kConv8Rows + 2) * (kConv8Cols + 2) + kConvThreads - 1) /
+                         kConvThreads;   // 16-byte units per thread and chunk
+
 template <int NT>
 __global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
     extern __shared__ __align__(16) uint16_t s_in[];
@@ -241,6 +248,45 @@ __global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
     // C8 = Cin and no chunk reaches past a source's channels)
     const bool wide = (a.Ca % 16) == 0 && (a.Cb % 16) == 0 && CW == 16;
 
+    // chunk ch's 16-byte units of this thread (unit e = tid + 256 q: pixel
+    // e / 2 of the tile, channels 8 (e % 2) ..), zero outside the image
+    auto load_wide = [&](int ch, uint4* v) {
+        const int cbase = ch * CW;
+        const bool fromA = cbase < a.Ca;
+        const uint16_t* src = fromA ? a.inA : a.inB;
+        const int Cs = fromA ? a.Ca : a.Cb;
+        const int cofs = fromA ? cbase : cbase - a.Ca;
+        const bool half = !fromA && a.b_half;
+        const int Hs = half ? Hh : a.H, Ws = half ? Wh : a.W;
+#pragma unroll
+        for (int q = 0; q < kC8Units; ++q) {
+            const int e = tid + kConvThreads * q;
+            v[q] = make_uint4(0u, 0u, 0u, 0u);
+            if (e < 2 * TP) {
+                const int pp = e >> 1, u = e & 1;
+                const int hr = pp / HC, hc = pp - hr * HC;
+                const int yy = y0 - 1 + hr, xx = x0 - 1 + hc;
+                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
+                    const int sy = half ? yy >> 1 : yy, sx = half ? xx >> 1 : xx;
+                    const int64_t off = ((int64_t)(n * Hs + sy) * Ws + sx) * Cs + cofs + 8 * u;
+                    v[q] = *reinterpret_cast<const uint4*>(src + off);
+                    if (fromA && a.maskA) {
+                        const s8 mk = *reinterpret_cast<const s8*>(a.maskA + off);
+                        uint32_t m[4];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            m[t] = (bf_positive(mk[2 * t]) ? 0xFFFFu : 0u) |
+                                   (bf_positive(mk[2 * t + 1]) ? 0xFFFF0000u : 0u);
+                        v[q].x &= m[0];
+                        v[q].y &= m[1];
+                        v[q].z &= m[2];
+                        v[q].w &= m[3];
+                    }
+                }
+            }
+        }
+    };
+
     f4 acc[4][NT];
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -249,41 +295,18 @@ __global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
     const uint16_t* wrow = a.wt8 + (int64_t)r16 * a.Kpad8 + 8 * g;
     const int64_t wstride = (int64_t)16 * a.Kpad8;
 
+    uint4 nxt[kC8Units];
+    if (wide) load_wide(0, nxt);
     for (int ch = 0; ch < nchunks; ++ch) {
         const int cbase = ch * CW;
         if (ch) __syncthreads();   // the previous chunk's operands are read
         // 1. the chunk's input tile
         if (wide) {
-            // two units of eight channels per pixel, from one source
-            const bool fromA = cbase < a.Ca;
-            const uint16_t* src = fromA ? a.inA : a.inB;
-            const int Cs = fromA ? a.Ca : a.Cb;
-            const int cofs = fromA ? cbase : cbase - a.Ca;
-            const bool half = !fromA && a.b_half;
-            const int Hs = half ? Hh : a.H, Ws = half ? Wh : a.W;
-            for (int e = tid; e < 2 * TP; e += kConvThreads) {
-                const int pp = e >> 1, u = e & 1;
-                const int hr = pp / HC, hc = pp - hr * HC;
-                const int yy = y0 - 1 + hr, xx = x0 - 1 + hc;
-                uint4 v = make_uint4(0u, 0u, 0u, 0u);
-                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
-                    const int sy = half ? yy >> 1 : yy, sx = half ? xx >> 1 : xx;
-                    const int64_t off = ((int64_t)(n * Hs + sy) * Ws + sx) * Cs + cofs + 8 * u;
-                    v = *reinterpret_cast<const uint4*>(src + off);
-                    if (fromA && a.maskA) {
-                        const s8 mk = *reinterpret_cast<const s8*>(a.maskA + off);
-                        uint32_t m[4];
 #pragma unroll
-                        for (int q = 0; q < 4; ++q)
-                            m[q] = (bf_positive(mk[2 * q]) ? 0xFFFFu : 0u) |
-                                   (bf_positive(mk[2 * q + 1]) ? 0xFFFF0000u : 0u);
-                        v.x &= m[0];
-                        v.y &= m[1];
-                        v.z &= m[2];
-                        v.w &= m[3];
-                    }
-                }
-                *reinterpret_cast<uint4*>(s_in + pp * CS + 8 * u) = v;
+            for (int q = 0; q < kC8Units; ++q) {
+                const int e = tid + kConvThreads * q;
+                if (e < 2 * TP)
+                    *reinterpret_cast<uint4*>(s_in + (e >> 1) * CS + 8 * (e & 1)) = nxt[q];
             }
         } else {
             // units of four channels, each from A, B or zero padding
@@ -316,6 +339,8 @@ __global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
             }
         }
         __syncthreads();
+        // the next chunk's loads, in flight during this chunk's MFMAs
+        if (wide && ch + 1 < nchunks) load_wide(ch + 1, nxt);
 
         // 2. the chunk's K steps for the wave's row: pixels x0 + 16 i +
         //    (lane % 16), i = 0..3; lane group g takes k = 32 ks + 8 g of the
@@ -345,34 +370,67 @@ __global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
             }
         }
     }
-    if (!row_ok) return;
 
     // 3. bias, ReLU, bfloat16 NHWC output (element r of lane l: pixel
-    //    16 i + 4 (l / 16) + r, channel 16 j + l % 16)
+    //    16 i + 4 (l / 16) + r, channel 16 j + l % 16); with pool_out the
+    //    horizontal pair sums of the stored values of odd rows go to LDS for
+    //    the even rows, which add them as the pooling kernel does
+    const bool pool = a.pool_out != nullptr;
+    float* s_pool = reinterpret_cast<float*>(s_in);
+    if (pool) __syncthreads();   // every wave is done with the tile
     const int CoB = a.Cout - a.CoA;
     const int64_t mrow = (int64_t)(n * a.H + y) * a.W;
+    float hs[NT][4][2];
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int co = 16 * j + r16;
         const float b = a.bias ? a.bias[co] : 0.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
+            float st[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int x = x0 + 16 * i + 4 * g + r;
-                if (x >= a.W) continue;
+                st[r] = 0.f;
+                if (!row_ok || x >= a.W) continue;
                 const int64_t m = mrow + x;
                 float v = acc[i][j][r] + b;
                 if (a.relu) v = fmaxf(v, 0.f);
                 if (co < a.CoA) {
                     uint16_t* p = a.outA + m * a.CoA + co;
                     if (a.accumA) v += bf2f(*p);
-                    *p = f2bf(v);
+                    const uint16_t o = f2bf(v);
+                    *p = o;
+                    st[r] = bf2f(o);
                 } else {
                     a.outB[m * CoB + (co - a.CoA)] = f2bf(v);
                 }
             }
+            hs[j][i][0] = st[0] + st[1];
+            hs[j][i][1] = st[2] + st[3];
+            if (pool && (wv & 1)) {
+                s_pool[(((wv >> 1) * NT + j) * 8 + 2 * i) * kWave + lane] = hs[j][i][0];
+                s_pool[(((wv >> 1) * NT + j) * 8 + 2 * i + 1) * kWave + lane] = hs[j][i][1];
+            }
         }
+    }
+    if (!pool) return;
+    __syncthreads();
+    if ((wv & 1) || !row_ok) return;
+    const int64_t prow = (int64_t)(n * Hh + (y >> 1)) * Wh;
+#pragma unroll
+    for (int j = 0; j < NT; ++j) {
+        const int co = 16 * j + r16;
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const int x = x0 + 16 * i + 4 * g + 2 * q;
+                if (x >= a.W) continue;
+                const float sm =
+                    hs[j][i][q] + s_pool[(((wv >> 1) * NT + j) * 8 + 2 * i + q) * kWave + lane];
+                a.pool_out[(prow + (x >> 1)) * a.CoA + co] = f2bf(0.25f * sm);
+            }
     }
 }
 
@@ -836,6 +894,11 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
     if (a.wt8) {
         if (a.C8 < a.Cin || a.C8 % conv8_chunk(a.C8) || a.Kpad8 != conv8_kpad(a.C8) ||
             a.N > 65535 || (a.H + kConv8Rows - 1) / kConv8Rows > 65535)
+            return hipErrorInvalidValue;
+        // (the fused pooling: whole 2x2 windows, outA only, LDS for the
+        // exchanged sums of 2 x NT x 8 floats per lane)
+        if (a.pool_out && (a.H % 2 || a.W % 2 || a.CoA != a.Cout || a.accumA ||
+                           (int64_t)2 * (a.Cout / 16) * 8 * kWave * 4 > conv8_lds_bytes(a.C8)))
             return hipErrorInvalidValue;
         const dim3 grid((a.W + kConv8Cols - 1) / kConv8Cols,
                         (a.H + kConv8Rows - 1) / kConv8Rows, a.N);

@@ -188,20 +188,21 @@ int forward(nsim_up* h, const float* L0, const float* L8, int N, int H, int W,
     const int64_t M = (int64_t)N * H * W;
     const int H2 = H / 2, W2 = W / 2, H4 = H / 4, W4 = W / 4;
     auto conv = [&](int li, const uint16_t* inA, int Ca, const uint16_t* inB,
-                    int Cb, int b_half, uint16_t* o, int hh, int ww) -> int {
+                    int Cb, int b_half, uint16_t* o, int hh, int ww,
+                    uint16_t* pooled = nullptr) -> int {
         const Layer& l = h->L[li];
-        const nup::ConvArgs a = conv_args(l, inA, Ca, inB, Cb, b_half, o,
-                                          h->p + l.b_off, N, hh, ww);
+        nup::ConvArgs a = conv_args(l, inA, Ca, inB, Cb, b_half, o,
+                                    h->p + l.b_off, N, hh, ww);
+        a.pool_out = pooled;
         UP_HIP(h, nup::launch_conv(a, s));
         return NSIM_UP_OK;
     };
     UP_HIP(h, nup::launch_make_input(L0, L8, h->x, M, s));
     if ((rc = conv(E1A, h->x, 4, nullptr, 0, 0, h->a1, H, W))) return rc;
-    if ((rc = conv(E1B, h->a1, 16, nullptr, 0, 0, h->s1, H, W))) return rc;
-    UP_HIP(h, nup::launch_pool(h->s1, h->p1, N, H, W, 16, s));
+    // (the skip output and its pooled map in one kernel)
+    if ((rc = conv(E1B, h->a1, 16, nullptr, 0, 0, h->s1, H, W, h->p1))) return rc;
     if ((rc = conv(E2A, h->p1, 16, nullptr, 0, 0, h->a2, H2, W2))) return rc;
-    if ((rc = conv(E2B, h->a2, 32, nullptr, 0, 0, h->s2, H2, W2))) return rc;
-    UP_HIP(h, nup::launch_pool(h->s2, h->p2, N, H2, W2, 32, s));
+    if ((rc = conv(E2B, h->a2, 32, nullptr, 0, 0, h->s2, H2, W2, h->p2))) return rc;
     if ((rc = conv(E3A, h->p2, 32, nullptr, 0, 0, h->a3, H4, W4))) return rc;
     if ((rc = conv(E3B, h->a3, 64, nullptr, 0, 0, h->s3, H4, W4))) return rc;
     if ((rc = conv(D2A, h->s2, 32, h->s3, 64, 1, h->b2, H2, W2))) return rc;
