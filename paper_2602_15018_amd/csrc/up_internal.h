@@ -49,6 +49,15 @@ struct ConvArgs {
     // With the staged kernel: also the 2x2 average of the output (outA only,
     // no accumulation) as [N][H/2][W/2][Cout] bfloat16, or null.
     uint16_t* pool_out;
+    // With the staged kernel and Cout = kHeadIn: also the output head on the
+    // stored values, or null: per pixel and output j, pred = the linear
+    // interpolation (j + 1) / 8 of L0 and L8 plus bias j plus row j of head_w
+    // times the pixel's kHeadIn channels.
+    const float* head_w;   // [kHeadOut][kHeadIn]
+    const float* head_b;   // [kHeadOut]
+    const float* head_L0;  // [N][H][W]
+    const float* head_L8;
+    float* head_pred;      // [N][kHeadOut][H][W]
     const float* bias;      // [Cout] or null
     uint16_t* outA;
     uint16_t* outB;
@@ -93,8 +102,14 @@ __host__ __device__ constexpr int conv8_stride(int cw) { return ((cw / 8) & 1) ?
 __host__ __device__ constexpr int conv8_kpad(int c8) {
     return (c8 / conv8_chunk(c8)) * ((9 * conv8_chunk(c8) + 31) / 32 * 32);
 }
-constexpr int64_t conv8_lds_bytes(int c8) {
-    return (int64_t)(kConv8Rows + 2) * (kConv8Cols + 2) * conv8_stride(conv8_chunk(c8)) * 2;
+// pixel stride of the output tile for 16 nt channels (odd 16-byte units)
+__host__ __device__ constexpr int conv8_out_stride(int nt) { return 16 * nt + 8; }
+// LDS of a workgroup: the staged input tile, reused for the output tiles
+constexpr int64_t conv8_lds_bytes(int c8, int nt) {
+    const int64_t in = (int64_t)(kConv8Rows + 2) * (kConv8Cols + 2) *
+                       conv8_stride(conv8_chunk(c8)) * 2;
+    const int64_t out = (int64_t)kConv8Rows * kConv8Cols * conv8_out_stride(nt) * 2;
+    return in > out ? in : out;
 }
 hipError_t launch_wgrad(const WgradArgs& a, int n_row_blocks, hipStream_t s);
 // out[i] = sum over b of part[b * stride + src(i)], with src remapping the
@@ -110,9 +125,6 @@ hipError_t launch_pool_bwd_acc(uint16_t* ds, const uint16_t* dp, int N, int H,
                                int W, int C, hipStream_t s);
 hipError_t launch_up_bwd(const uint16_t* dfull, uint16_t* dlow, int N, int H,
                          int W, int C, hipStream_t s);
-hipError_t launch_head_fwd(const uint16_t* d1, const float* wh, const float* bh,
-                           const float* L0, const float* L8, float* pred,
-                           int N, int H, int W, hipStream_t s);
 hipError_t launch_loss_head_bwd(const float* pred, const float* target,
                                 const float* wh, float* g, uint16_t* dd1,
                                 float* part_loss, int N, int H, int W,

@@ -224,20 +224,30 @@ __device__ __forceinline__ f4 mfma32(s8 a, s8 b, f4 c) {
 // packed weights (global memory, shared by the waves in the cache).  When
 // every chunk lies in one source, chunks are loaded with 16-byte loads one
 // chunk ahead (into registers, while the matrix cores work on the current
-// one).  With pool_out the 2x2 average of the stored outputs is written
-// too, row pairs meeting in LDS.
+// one), each thread's pixels fixed for the whole tile.  The results go
+// through LDS as [pixel][channel] so that each lane writes whole 16-byte
+// runs of channels of the NHWC outputs; with pool_out the 2x2 averages of
+// the stored values are formed from the same tile.
 constexpr int kC8Units = (2 * (kConv8Rows + 2) * (kConv8Cols + 2) + kConvThreads - 1) /
                          kConvThreads;   // 16-byte units per thread and chunk
 
-template <int NT>
+// Round-to-nearest-even bfloat16 of two floats (one instruction on gfx950).
+typedef __bf16 bf2 __attribute__((ext_vector_type(2)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t f2bf2(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector((fl2){lo, hi}, bf2));
+}
+
+template <int NT, int CW>
 __global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
     extern __shared__ __align__(16) uint16_t s_in[];
+    __shared__ __align__(16) float s_head[kHeadOut * kHeadIn + kHeadOut];  // W, then b
     constexpr int HC = kConv8Cols + 2;
     constexpr int TP = (kConv8Rows + 2) * HC;    // pixels of a staged tile
-    const int C8 = a.C8;
-    const int CW = conv8_chunk(C8), CS = conv8_stride(CW);
-    const int KC = (9 * CW + 31) / 32 * 32;
-    const int nchunks = C8 / CW;
+    constexpr int CS = conv8_stride(CW);
+    constexpr int KC = (9 * CW + 31) / 32 * 32;
+    constexpr int ES = conv8_out_stride(NT);     // pixel stride of the output tile
+    const int nchunks = a.C8 / CW;
     const int tid = threadIdx.x, lane = tid & (kWave - 1), wv = tid / kWave;
     const int x0 = blockIdx.x * kConv8Cols, y0 = blockIdx.y * kConv8Rows, n = blockIdx.z;
     const int Hh = a.H >> 1, Wh = a.W >> 1;
@@ -246,42 +256,49 @@ __global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
     const int r16 = lane & 15, g = lane >> 4;
     // 16-byte staging units when every chunk lies in one source (then
     // C8 = Cin and no chunk reaches past a source's channels)
-    const bool wide = (a.Ca % 16) == 0 && (a.Cb % 16) == 0 && CW == 16;
+    const bool wide = CW == 16 && (a.Ca % 16) == 0 && (a.Cb % 16) == 0;
 
-    // chunk ch's 16-byte units of this thread (unit e = tid + 256 q: pixel
-    // e / 2 of the tile, channels 8 (e % 2) ..), zero outside the image
+    // this thread's units of a wide tile (unit e = tid + 256 q: pixel e / 2,
+    // channels 8 (e % 2) ..): pixel indices in A's and in B's image, or -1
+    // outside the image
+    int pixA[kC8Units], pixB[kC8Units];
+    if (wide) {
+#pragma unroll
+        for (int q = 0; q < kC8Units; ++q) {
+            const int e = tid + kConvThreads * q;
+            const int pp = e >> 1;
+            const int hr = pp / HC, hc = pp - hr * HC;
+            const int yy = y0 - 1 + hr, xx = x0 - 1 + hc;
+            const bool in = e < 2 * TP && yy >= 0 && yy < a.H && xx >= 0 && xx < a.W;
+            pixA[q] = in ? (n * a.H + yy) * a.W + xx : -1;
+            pixB[q] = in ? (a.b_half ? (n * Hh + (yy >> 1)) * Wh + (xx >> 1) : pixA[q]) : -1;
+        }
+    }
     auto load_wide = [&](int ch, uint4* v) {
         const int cbase = ch * CW;
         const bool fromA = cbase < a.Ca;
         const uint16_t* src = fromA ? a.inA : a.inB;
         const int Cs = fromA ? a.Ca : a.Cb;
         const int cofs = fromA ? cbase : cbase - a.Ca;
-        const bool half = !fromA && a.b_half;
-        const int Hs = half ? Hh : a.H, Ws = half ? Wh : a.W;
+        const bool mask = fromA && a.maskA;
 #pragma unroll
         for (int q = 0; q < kC8Units; ++q) {
-            const int e = tid + kConvThreads * q;
+            const int pix = fromA ? pixA[q] : pixB[q];
             v[q] = make_uint4(0u, 0u, 0u, 0u);
-            if (e < 2 * TP) {
-                const int pp = e >> 1, u = e & 1;
-                const int hr = pp / HC, hc = pp - hr * HC;
-                const int yy = y0 - 1 + hr, xx = x0 - 1 + hc;
-                if (yy >= 0 && yy < a.H && xx >= 0 && xx < a.W) {
-                    const int sy = half ? yy >> 1 : yy, sx = half ? xx >> 1 : xx;
-                    const int64_t off = ((int64_t)(n * Hs + sy) * Ws + sx) * Cs + cofs + 8 * u;
-                    v[q] = *reinterpret_cast<const uint4*>(src + off);
-                    if (fromA && a.maskA) {
-                        const s8 mk = *reinterpret_cast<const s8*>(a.maskA + off);
-                        uint32_t m[4];
+            if (pix >= 0) {
+                const int64_t off = (int64_t)pix * Cs + cofs + 8 * (tid & 1);
+                v[q] = *reinterpret_cast<const uint4*>(src + off);
+                if (mask) {
+                    const s8 mk = *reinterpret_cast<const s8*>(a.maskA + off);
+                    uint32_t m[4];
 #pragma unroll
-                        for (int t = 0; t < 4; ++t)
-                            m[t] = (bf_positive(mk[2 * t]) ? 0xFFFFu : 0u) |
-                                   (bf_positive(mk[2 * t + 1]) ? 0xFFFF0000u : 0u);
-                        v[q].x &= m[0];
-                        v[q].y &= m[1];
-                        v[q].z &= m[2];
-                        v[q].w &= m[3];
-                    }
+                    for (int t = 0; t < 4; ++t)
+                        m[t] = (bf_positive(mk[2 * t]) ? 0xFFFFu : 0u) |
+                               (bf_positive(mk[2 * t + 1]) ? 0xFFFF0000u : 0u);
+                    v[q].x &= m[0];
+                    v[q].y &= m[1];
+                    v[q].z &= m[2];
+                    v[q].w &= m[3];
                 }
             }
         }
@@ -295,6 +312,11 @@ __global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
     const uint16_t* wrow = a.wt8 + (int64_t)r16 * a.Kpad8 + 8 * g;
     const int64_t wstride = (int64_t)16 * a.Kpad8;
 
+    if (a.head_pred) {
+        // (read after the first barrier below)
+        if (tid < kHeadOut * kHeadIn) s_head[tid] = a.head_w[tid];
+        else if (tid < kHeadOut * kHeadIn + kHeadOut) s_head[tid] = a.head_b[tid - kHeadOut * kHeadIn];
+    }
     uint4 nxt[kC8Units];
     if (wide) load_wide(0, nxt);
     for (int ch = 0; ch < nchunks; ++ch) {
@@ -310,7 +332,7 @@ __global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
             }
         } else {
             // units of four channels, each from A, B or zero padding
-            const int U = CW >> 2;
+            constexpr int U = CW >> 2;
             for (int e = tid; e < U * TP; e += kConvThreads) {
                 const int pp = e / U, u = e - pp * U;
                 const int hr = pp / HC, hc = pp - hr * HC;
@@ -347,13 +369,15 @@ __global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
         //    chunk, i.e. tap (32 ks + 8 g) / CW, channels from (.. % CW)
         if (row_ok) {
             const uint16_t* wk = wrow + ch * KC;
+            const uint16_t* base = s_in + (wv * HC + r16) * CS;
+#pragma unroll
             for (int ks = 0; ks < KC / 32; ++ks) {
                 const int kl = 32 * ks + 8 * g;
                 const int tap = kl / CW, c = kl - tap * CW;
                 s8 af[4];
                 if (tap < 9) {
                     const int ky = tap / 3, kx = tap - 3 * ky;
-                    const uint16_t* p = s_in + ((wv + ky) * HC + kx + r16) * CS + c;
+                    const uint16_t* p = base + (ky * HC + kx) * CS + c;
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
                         af[i] = *reinterpret_cast<const s8*>(p + 16 * i * CS);
@@ -371,66 +395,111 @@ __global__ __launch_bounds__(kConvThreads) void conv8_kernel(const ConvArgs a) {
         }
     }
 
-    // 3. bias, ReLU, bfloat16 NHWC output (element r of lane l: pixel
-    //    16 i + 4 (l / 16) + r, channel 16 j + l % 16); with pool_out the
-    //    horizontal pair sums of the stored values of odd rows go to LDS for
-    //    the even rows, which add them as the pooling kernel does
-    const bool pool = a.pool_out != nullptr;
-    float* s_pool = reinterpret_cast<float*>(s_in);
-    if (pool) __syncthreads();   // every wave is done with the tile
-    const int CoB = a.Cout - a.CoA;
+    // 3. bias and ReLU on the accumulators (element r of lane l: pixel
+    //    16 i + 4 (l / 16) + r, channel 16 j + l % 16), then through the
+    //    output tile (wave wv: [64 pixels][ES]) so that lane p takes pixel p
+    //    and writes its channels in 16-byte runs
+    //    (accumulation into outA adds the old value before the one rounding)
+    __syncthreads();   // every wave is done with the staged input
+    uint16_t* s_out = s_in + wv * kConv8Cols * ES;
     const int64_t mrow = (int64_t)(n * a.H + y) * a.W;
-    float hs[NT][4][2];
 #pragma unroll
     for (int j = 0; j < NT; ++j) {
         const int co = 16 * j + r16;
         const float b = a.bias ? a.bias[co] : 0.f;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            float st[4];
+            float v[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int x = x0 + 16 * i + 4 * g + r;
-                st[r] = 0.f;
-                if (!row_ok || x >= a.W) continue;
-                const int64_t m = mrow + x;
-                float v = acc[i][j][r] + b;
-                if (a.relu) v = fmaxf(v, 0.f);
-                if (co < a.CoA) {
-                    uint16_t* p = a.outA + m * a.CoA + co;
-                    if (a.accumA) v += bf2f(*p);
-                    const uint16_t o = f2bf(v);
-                    *p = o;
-                    st[r] = bf2f(o);
-                } else {
-                    a.outB[m * CoB + (co - a.CoA)] = f2bf(v);
-                }
+                v[r] = acc[i][j][r] + b;
+                if (a.relu) v[r] = fmaxf(v[r], 0.f);
+                const int xr = x0 + 16 * i + 4 * g + r;
+                if (a.accumA && co < a.CoA && row_ok && xr < a.W)
+                    v[r] += bf2f(a.outA[(mrow + xr) * a.CoA + co]);
             }
-            hs[j][i][0] = st[0] + st[1];
-            hs[j][i][1] = st[2] + st[3];
-            if (pool && (wv & 1)) {
-                s_pool[(((wv >> 1) * NT + j) * 8 + 2 * i) * kWave + lane] = hs[j][i][0];
-                s_pool[(((wv >> 1) * NT + j) * 8 + 2 * i + 1) * kWave + lane] = hs[j][i][1];
+            const uint32_t p01 = f2bf2(v[0], v[1]), p23 = f2bf2(v[2], v[3]);
+            uint16_t* o = s_out + (16 * i + 4 * g) * ES + co;
+            o[0] = (uint16_t)p01;
+            o[ES] = (uint16_t)(p01 >> 16);
+            o[2 * ES] = (uint16_t)p23;
+            o[3 * ES] = (uint16_t)(p23 >> 16);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    const int x = x0 + lane;
+    const int CoB = a.Cout - a.CoA;
+    if (row_ok && x < a.W) {
+        const int64_t m = mrow + x;
+        const uint16_t* t = s_out + lane * ES;
+#pragma unroll
+        for (int c0 = 0; c0 < 16 * NT; c0 += 8) {
+            const uint4 w = *reinterpret_cast<const uint4*>(t + c0);
+            if (c0 < a.CoA) {
+                *reinterpret_cast<uint4*>(a.outA + m * a.CoA + c0) = w;
+            } else {
+                *reinterpret_cast<uint4*>(a.outB + m * CoB + (c0 - a.CoA)) = w;
             }
         }
     }
-    if (!pool) return;
+    if (a.head_pred && row_ok && x < a.W) {
+        // the output head on this pixel's stored channels, as the head
+        // kernel computes it
+        float hv[kHeadIn];
+        const uint16_t* t = s_out + lane * ES;
+#pragma unroll
+        for (int c0 = 0; c0 < kHeadIn; c0 += 8) {
+            const uint4 w = *reinterpret_cast<const uint4*>(t + c0);
+            const uint32_t w4[4] = {w.x, w.y, w.z, w.w};
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                hv[c0 + 2 * h] = bf2f((uint16_t)w4[h]);
+                hv[c0 + 2 * h + 1] = bf2f((uint16_t)(w4[h] >> 16));
+            }
+        }
+        const int64_t HW = (int64_t)a.H * a.W;
+        const int64_t m = mrow + x, pix = m - (int64_t)n * HW;
+        const float l0 = a.head_L0[m], l8 = a.head_L8[m];
+#pragma unroll
+        for (int jo = 0; jo < kHeadOut; ++jo) {
+            float d = s_head[kHeadOut * kHeadIn + jo];
+#pragma unroll
+            for (int c = 0; c < kHeadIn; ++c) d = fmaf(s_head[jo * kHeadIn + c], hv[c], d);
+            const float bt = (float)(jo + 1) * 0.125f;
+            a.head_pred[((int64_t)n * kHeadOut + jo) * HW + pix] = ((1.f - bt) * l0 + bt * l8) + d;
+        }
+    }
+    if (!a.pool_out) return;
+
+    // 4. pooled map: 2x2 windows of rows (y, y + 1), y even, from the tiles
+    //    of waves (wv, wv + 1); lane l: window l % 32, channels 8 (l / 32)
+    //    + 16 s; the sums in the pooling kernel's order
     __syncthreads();
     if ((wv & 1) || !row_ok) return;
-    const int64_t prow = (int64_t)(n * Hh + (y >> 1)) * Wh;
+    const uint16_t* top = s_out;
+    const uint16_t* bot = s_out + kConv8Cols * ES;
+    const int q = lane & 31, xp = (x0 >> 1) + q;
+    if (x0 + 2 * q >= a.W) return;
+    const int64_t mp = (int64_t)(n * Hh + (y >> 1)) * Wh + xp;
 #pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int co = 16 * j + r16;
+    for (int c0 = 8 * (lane >> 5); c0 < 16 * NT; c0 += 16) {
+        const uint4 tl = *reinterpret_cast<const uint4*>(top + (2 * q) * ES + c0);
+        const uint4 tr = *reinterpret_cast<const uint4*>(top + (2 * q + 1) * ES + c0);
+        const uint4 bl = *reinterpret_cast<const uint4*>(bot + (2 * q) * ES + c0);
+        const uint4 br = *reinterpret_cast<const uint4*>(bot + (2 * q + 1) * ES + c0);
+        const uint32_t a4[4] = {tl.x, tl.y, tl.z, tl.w}, b4[4] = {tr.x, tr.y, tr.z, tr.w};
+        const uint32_t c4[4] = {bl.x, bl.y, bl.z, bl.w}, d4[4] = {br.x, br.y, br.z, br.w};
+        uint32_t o4[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const int x = x0 + 16 * i + 4 * g + 2 * q;
-                if (x >= a.W) continue;
-                const float sm =
-                    hs[j][i][q] + s_pool[(((wv >> 1) * NT + j) * 8 + 2 * i + q) * kWave + lane];
-                a.pool_out[(prow + (x >> 1)) * a.CoA + co] = f2bf(0.25f * sm);
-            }
+        for (int h = 0; h < 4; ++h) {
+            const float slo = (bf2f((uint16_t)a4[h]) + bf2f((uint16_t)b4[h])) +
+                              (bf2f((uint16_t)c4[h]) + bf2f((uint16_t)d4[h]));
+            const float shi = (bf2f((uint16_t)(a4[h] >> 16)) + bf2f((uint16_t)(b4[h] >> 16))) +
+                              (bf2f((uint16_t)(c4[h] >> 16)) + bf2f((uint16_t)(d4[h] >> 16)));
+            o4[h] = f2bf2(0.25f * slo, 0.25f * shi);
+        }
+        *reinterpret_cast<uint4*>(a.pool_out + mp * a.CoA + c0) =
+            make_uint4(o4[0], o4[1], o4[2], o4[3]);
     }
 }
 
@@ -677,30 +746,6 @@ __global__ void up_bwd_kernel(const uint16_t* df, uint16_t* dl, int N, int H,
     dl[i] = f2bf(s);
 }
 
-// Head (1x1, FP32 weights) plus linear interpolation; planar FP32 output.
-__global__ void head_fwd_kernel(const uint16_t* d1, const float* wh,
-                                const float* bh, const float* L0,
-                                const float* L8, float* pred, int N, int H,
-                                int W) {
-    const int64_t HW = (int64_t)H * W;
-    const int64_t M = (int64_t)N * HW;
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (m >= M) return;
-    float h[kHeadIn];
-#pragma unroll
-    for (int c = 0; c < kHeadIn; ++c) h[c] = bf2f(d1[m * kHeadIn + c]);
-    const int64_t n = m / HW, pix = m - n * HW;
-    const float l0 = L0[m], l8 = L8[m];
-#pragma unroll
-    for (int j = 0; j < kHeadOut; ++j) {
-        float d = bh[j];
-#pragma unroll
-        for (int c = 0; c < kHeadIn; ++c) d = fmaf(wh[j * kHeadIn + c], h[c], d);
-        const float b = (float)(j + 1) * 0.125f;
-        pred[(n * kHeadOut + j) * HW + pix] = ((1.f - b) * l0 + b * l8) + d;
-    }
-}
-
 // L1 loss and the head's backward: g = sign(pred - target) / count (kept
 // for the head's weight gradient), dd1 = g . Wh (bfloat16), and one partial
 // loss sum per block.
@@ -895,23 +940,33 @@ hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
         if (a.C8 < a.Cin || a.C8 % conv8_chunk(a.C8) || a.Kpad8 != conv8_kpad(a.C8) ||
             a.N > 65535 || (a.H + kConv8Rows - 1) / kConv8Rows > 65535)
             return hipErrorInvalidValue;
-        // (the fused pooling: whole 2x2 windows, outA only, LDS for the
-        // exchanged sums of 2 x NT x 8 floats per lane)
-        if (a.pool_out && (a.H % 2 || a.W % 2 || a.CoA != a.Cout || a.accumA ||
-                           (int64_t)2 * (a.Cout / 16) * 8 * kWave * 4 > conv8_lds_bytes(a.C8)))
+        // (the fused pooling: whole 2x2 windows, outA only; CoA a multiple
+        // of 8 for the 16-byte runs of the output)
+        if ((a.pool_out && (a.H % 2 || a.W % 2 || a.CoA != a.Cout || a.accumA)) ||
+            (a.head_pred && (a.Cout != kHeadIn || a.CoA != a.Cout || a.accumA ||
+                             !a.head_w || !a.head_b || !a.head_L0 || !a.head_L8)) ||
+            a.CoA % 8)
             return hipErrorInvalidValue;
         const dim3 grid((a.W + kConv8Cols - 1) / kConv8Cols,
                         (a.H + kConv8Rows - 1) / kConv8Rows, a.N);
         const dim3 block(kConvThreads);
-        const size_t lds = (size_t)conv8_lds_bytes(a.C8);
+        const size_t lds = (size_t)conv8_lds_bytes(a.C8, a.Cout / 16);
+#define NUP_CONV8(NT)                                                                   \
+    do {                                                                                \
+        if (conv8_chunk(a.C8) == 16)                                                    \
+            hipLaunchKernelGGL((conv8_kernel<NT, 16>), grid, block, lds, s, a);          \
+        else                                                                            \
+            hipLaunchKernelGGL((conv8_kernel<NT, 8>), grid, block, lds, s, a);           \
+    } while (0)
         switch (a.Cout / 16) {
-        case 1: hipLaunchKernelGGL(conv8_kernel<1>, grid, block, lds, s, a); break;
-        case 2: hipLaunchKernelGGL(conv8_kernel<2>, grid, block, lds, s, a); break;
-        case 3: hipLaunchKernelGGL(conv8_kernel<3>, grid, block, lds, s, a); break;
-        case 4: hipLaunchKernelGGL(conv8_kernel<4>, grid, block, lds, s, a); break;
-        case 6: hipLaunchKernelGGL(conv8_kernel<6>, grid, block, lds, s, a); break;
+        case 1: NUP_CONV8(1); break;
+        case 2: NUP_CONV8(2); break;
+        case 3: NUP_CONV8(3); break;
+        case 4: NUP_CONV8(4); break;
+        case 6: NUP_CONV8(6); break;
         default: return hipErrorInvalidValue;
         }
+#undef NUP_CONV8
         return hipGetLastError();
     }
     const dim3 grid(blocks_for(M, 64 * (kConvThreads / kWave))), block(kConvThreads);
@@ -980,15 +1035,6 @@ hipError_t launch_up_bwd(const uint16_t* dfull, uint16_t* dlow, int N, int H,
     const int64_t n = (int64_t)N * (H / 2) * (W / 2) * C;
     hipLaunchKernelGGL(up_bwd_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s,
                        dfull, dlow, N, H, W, C);
-    return hipGetLastError();
-}
-
-hipError_t launch_head_fwd(const uint16_t* d1, const float* wh, const float* bh,
-                           const float* L0, const float* L8, float* pred, int N,
-                           int H, int W, hipStream_t s) {
-    const int64_t M = (int64_t)N * H * W;
-    hipLaunchKernelGGL(head_fwd_kernel, dim3(blocks_for(M, 256)), dim3(256), 0, s,
-                       d1, wh, bh, L0, L8, pred, N, H, W);
     return hipGetLastError();
 }
 

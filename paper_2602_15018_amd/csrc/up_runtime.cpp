@@ -208,9 +208,18 @@ int forward(nsim_up* h, const float* L0, const float* L8, int N, int H, int W,
     if ((rc = conv(D2A, h->s2, 32, h->s3, 64, 1, h->b2, H2, W2))) return rc;
     if ((rc = conv(D2B, h->b2, 32, nullptr, 0, 0, h->d2, H2, W2))) return rc;
     if ((rc = conv(D1A, h->s1, 16, h->d2, 32, 1, h->b1, H, W))) return rc;
-    if ((rc = conv(D1B, h->b1, 16, nullptr, 0, 0, h->d1, H, W))) return rc;
-    UP_HIP(h, nup::launch_head_fwd(h->d1, h->p + h->head_w_off, h->p + h->head_b_off,
-                                   L0, L8, out, N, H, W, s));
+    {
+        // the last layer with the output head in its epilogue (d1 is still
+        // written: the training backward reads it)
+        const Layer& l = h->L[D1B];
+        nup::ConvArgs a = conv_args(l, h->b1, 16, nullptr, 0, 0, h->d1, h->p + l.b_off, N, H, W);
+        a.head_w = h->p + h->head_w_off;
+        a.head_b = h->p + h->head_b_off;
+        a.head_L0 = L0;
+        a.head_L8 = L8;
+        a.head_pred = out;
+        UP_HIP(h, nup::launch_conv(a, s));
+    }
     return NSIM_UP_OK;
 }
 
