@@ -407,8 +407,9 @@ def bench_learned(args):
     dev = torch.device("cuda", 0)
     w = scene.WORKLOADS[scene.UPSAMPLER_SCENE]
     H, W = w.height, w.width
-    up = Upsampler(max(16 * 256 * 256, 8 * H * W), seed=1)
-    lin = Upsampler(8 * H * W, seed=1)
+    # (one forward call holds 16 pairs of the evaluation size)
+    up = Upsampler(max(16 * 256 * 256, 16 * H * W), seed=1)
+    lin = Upsampler(16 * H * W, seed=1)
     log("training on %d sequences, %d epochs" % (args.train_sequences,
                                                  args.train_epochs))
     held = learned.training_batch(scene.EVAL_SEED0 + 1000 + np.arange(16),
@@ -474,16 +475,16 @@ def bench_learned(args):
     t_render_low = timed(lambda: render(t_low), 2)
     t_events_plain = timed(lambda: events_of(frames_full, False), 2)
     Llow = log_frames(frames_low)
-    t_upsample = timed(lambda: learned.upsampled_log_frames(up, log_frames(frames_low)), 2)
-    Lf = learned.upsampled_log_frames(up, Llow)
+    t_upsample = timed(lambda: learned.upsampled_log_frames(up, log_frames(frames_low), max_pairs=16), 2)
+    Lf = learned.upsampled_log_frames(up, Llow, max_pairs=16)
     t_events_learned = timed(lambda: events_of(Lf, True), 2)
     steps = max(1, args.steps)
     t_learned_step = timed(lambda: events_of(
-        learned.upsampled_log_frames(up, log_frames(render(t_low))), True), steps)
+        learned.upsampled_log_frames(up, log_frames(render(t_low)), max_pairs=16), True), steps)
     t_plain_step = t_render_full + t_events_plain
-    # the upsampler forward alone, 8 pairs per call
-    L8 = torch.randn(8, H, W, device=dev) * 0.1 - 1.0
-    t_fwd = timed(lambda: up.forward(L8, L8), 5) / 8
+    # the upsampler forward alone, 16 pairs per call (as the path calls it)
+    L8 = torch.randn(16, H, W, device=dev) * 0.1 - 1.0
+    t_fwd = timed(lambda: up.forward(L8, L8), 5) / 16
     flop_pair = 2.0 * unet.macs_per_pixel() * H * W
     # paper's renderer rate as context: Habitat at VGA about 3000 FPS
     r_ctx = 1.0 / 3000.0
