@@ -3,9 +3,10 @@
 //
 // Activations and activation gradients are bfloat16 (uint16 storage) in
 // NHWC order; weights used by the convolutions are bfloat16 copies of the
-// FP32 master weights, laid out as GEMM operands [out channel][K] with
-// K = tap * C_in + c (tap = 3 ky + kx), zero-padded to Kpad (a multiple of
-// 16).  All accumulation is FP32.
+// FP32 master weights, laid out as GEMM operands [out channel][K] in chunks
+// of input channels (ConvArgs::wt8).  The weight gradient is FP32 in the
+// layout [out channel][K] with K = tap * C_in + c (tap = 3 ky + kx),
+// zero-padded to Kpad (a multiple of 16).  All accumulation is FP32.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -39,20 +40,19 @@ struct ConvArgs {
     const uint16_t* inA;
     const uint16_t* inB;
     const uint16_t* maskA;
-    const uint16_t* wt;     // [Cout][Kpad]
-    // The same weights for the LDS-staged kernel (used when set): input
-    // channels padded to C8 (8, or a multiple of 16), K in chunks of
-    // conv8_chunk(C8) channels (k = chunk KC + tap CW + c), rows of
+    // The weights [Cout][Kpad8]: input channels padded to C8 (8, or a
+    // multiple of 16), K in chunks of CW = conv8_chunk(C8) channels
+    // (k = chunk KC + tap CW + c, KC = round32(9 CW)), rows of
     // Kpad8 = conv8_kpad(C8) bfloat16.
     const uint16_t* wt8;
     int32_t C8, Kpad8;
-    // With the staged kernel: also the 2x2 average of the output (outA only,
-    // no accumulation) as [N][H/2][W/2][Cout] bfloat16, or null.
+    // Also the 2x2 average of the output (outA only, no accumulation) as
+    // [N][H/2][W/2][Cout] bfloat16, or null.
     uint16_t* pool_out;
-    // With the staged kernel and Cout = kHeadIn: also the output head on the
-    // stored values, or null: per pixel and output j, pred = the linear
-    // interpolation (j + 1) / 8 of L0 and L8 plus bias j plus row j of head_w
-    // times the pixel's kHeadIn channels.
+    // With Cout = kHeadIn: also the output head on the stored values, or
+    // null: per pixel and output j, pred = the linear interpolation
+    // (j + 1) / 8 of L0 and L8 plus bias j plus row j of head_w times the
+    // pixel's kHeadIn channels.
     const float* head_w;   // [kHeadOut][kHeadIn]
     const float* head_b;   // [kHeadOut]
     const float* head_L0;  // [N][H][W]
@@ -64,7 +64,6 @@ struct ConvArgs {
     int32_t N, H, W;
     int32_t Ca, Cb, Cin;
     int32_t Cout, CoA;
-    int32_t K, Kpad;
     int32_t b_half;
     int32_t relu;
     int32_t accumA;
@@ -119,8 +118,6 @@ hipError_t launch_reduce(const float* part, int nblk, int64_t stride,
                          float* out, hipStream_t s);
 hipError_t launch_make_input(const float* L0, const float* L8, uint16_t* x,
                              int64_t M, hipStream_t s);
-hipError_t launch_pool(const uint16_t* x, uint16_t* y, int N, int H, int W,
-                       int C, hipStream_t s);
 hipError_t launch_pool_bwd_acc(uint16_t* ds, const uint16_t* dp, int N, int H,
                                int W, int C, hipStream_t s);
 hipError_t launch_up_bwd(const uint16_t* dfull, uint16_t* dlow, int N, int H,
@@ -133,9 +130,6 @@ hipError_t launch_head_wgrad(const float* g, const uint16_t* d1, float* part,
                              int64_t M, int nblk, hipStream_t s);
 hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n,
                        float lr, float c1, float c2, hipStream_t s);
-hipError_t launch_pack_weights(const float* w, uint16_t* fwd, uint16_t* bwd,
-                               int Cout, int Ci, int Cpad, int Kpad,
-                               int KpadB, hipStream_t s);
 hipError_t launch_log_frames(const float* I, float* L, int64_t n, float eps,
                              hipStream_t s);
 hipError_t launch_mfma32_probe(const uint16_t* A, const uint16_t* B, float* C,

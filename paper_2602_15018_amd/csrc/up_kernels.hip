@@ -6,13 +6,15 @@
 // for 1000+ FPS frames without rendering them all (Sec. 1, contribution on
 // efficient high-fidelity event simulation; Sec. 2, event-camera paragraph).
 //
-// Convolutions are implicit GEMMs on the matrix cores: one wave computes a
-// 64-pixel x C_out tile with v_mfma_f32_16x16x16_bf16 (bfloat16 operands,
+// Convolutions are implicit GEMMs on the matrix cores: a workgroup stages a
+// tile of input rows (with the halo) in LDS one channel chunk at a time and
+// its waves multiply it with v_mfma_f32_16x16x32_bf16 (bfloat16 operands,
 // FP32 accumulation).  The same kernel runs the forward pass and the
 // backward-data pass (weights flipped and transposed, the ReLU derivative
-// folded into the operand read); the weight gradient is a second MFMA
-// kernel that reduces over pixels in fixed-size blocks, with a fixed-order
-// reduction of the block partials (deterministic).
+// folded into the staging); it can also write the 2x2 average of its output
+// and apply the 1x1 output head.  The weight gradient is a second MFMA
+// kernel (16x16x16) that reduces over pixels in fixed-size blocks, with a
+// fixed-order reduction of the block partials (deterministic).
 #include <math.h>
 #include <stdint.h>
 
@@ -39,162 +41,11 @@ __device__ __forceinline__ bool bf_positive(short b) {
     return b > 0;  // sign bit clear and not +0
 }
 
-// The concatenated input of a convolution: channels [0, Ca) from A, the
-// next Cb from B (at half resolution with b_half), NHWC bfloat16.
-struct Src {
-    const uint16_t* A;
-    const uint16_t* B;
-    const uint16_t* maskA;
-    int Ca, Cb, H, W, b_half;
-};
-
-// One element (channel c) of the concatenated input at (n, yy, xx).
-__device__ __forceinline__ short load1(const Src& s, int n, int yy, int xx, int c) {
-    if (yy < 0 || yy >= s.H || xx < 0 || xx >= s.W) return 0;
-    if (c < s.Ca) return (short)s.A[(int64_t)((n * s.H + yy) * s.W + xx) * s.Ca + c];
-    const int cb = c - s.Ca;
-    if (s.b_half) {
-        const int Hh = s.H >> 1, Wh = s.W >> 1;
-        return (short)s.B[(int64_t)((n * Hh + (yy >> 1)) * Wh + (xx >> 1)) * s.Cb + cb];
-    }
-    return (short)s.B[(int64_t)((n * s.H + yy) * s.W + xx) * s.Cb + cb];
-}
-
 // MFMA 16x16x16 operand layout (per lane l, 4 elements e):
 //   A[row = l % 16][k = 4 (l / 16) + e],  B[k = 4 (l / 16) + e][col = l % 16],
 //   D: element r of lane l is D[row = 4 (l / 16) + r][col = l % 16].
 __device__ __forceinline__ f4 mfma(s4 a, s4 b, f4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
-}
-
-template <int NT>
-__global__ __launch_bounds__(kConvThreads) void conv_kernel(const ConvArgs a) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int wv = threadIdx.x / kWave;
-    // Pixel indices fit in 32 bits (the launcher rejects 2^31 pixels or
-    // more); element offsets are formed in 64 bits.
-    const int HW = a.H * a.W;
-    const int M = a.N * HW;
-    const int base = (blockIdx.x * (kConvThreads / kWave) + wv) * 64;
-    if (base >= M) return;
-    const int r16 = lane & 15, g4 = lane >> 4;
-
-    // Per pixel i (index m, coordinates n, y, x): the set of taps (ky, kx)
-    // whose source pixel (y + ky - 1, x + kx - 1) lies in the image, as bit
-    // 3 ky + kx of tv (empty past the last pixel), and m Ca.  Tap (ky, kx),
-    // channel c < Ca of pixel i is then element m Ca + ((ky - 1) W + kx - 1)
-    // Ca + c of inA: one add per operand load, the rest once per K step.
-    int pm[4], pn[4], py[4], px[4];
-    uint32_t tv[4];
-    int64_t mA[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int m = base + 16 * i + r16;
-        const bool pv = m < M;
-        const int mm = pv ? m : 0;
-        pm[i] = mm;
-        pn[i] = mm / HW;
-        const int rem = mm - pn[i] * HW;
-        py[i] = rem / a.W;
-        px[i] = rem - py[i] * a.W;
-        mA[i] = (int64_t)mm * a.Ca;
-        const uint32_t rows = (py[i] > 0 ? 1u : 0u) | 2u | (py[i] + 1 < a.H ? 4u : 0u);
-        const uint32_t cols = (px[i] > 0 ? 1u : 0u) | 2u | (px[i] + 1 < a.W ? 4u : 0u);
-        uint32_t bits = 0;
-#pragma unroll
-        for (int ky = 0; ky < 3; ++ky)
-            if ((rows >> ky) & 1u) bits |= cols << (3 * ky);
-        tv[i] = pv ? bits : 0u;
-    }
-    f4 acc[4][NT];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < NT; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
-
-    // Column k0 = 16 ks + 4 g4 of the im2col operand is channel c of tap
-    // (ky, kx): one division at the start, then each K step of 16 moves
-    // (tap, c) on by (16 / Cin, 16 % Cin) with one carry.
-    const int ksteps = a.Kpad / 16;
-    const int dtap = 16 / a.Cin, dc = 16 - dtap * a.Cin;
-    const int Hh = a.H >> 1, Wh = a.W >> 1;
-    int k0 = g4 * 4;
-    int tap = k0 / a.Cin;
-    int c = k0 - tap * a.Cin;
-    for (int ks = 0; ks < ksteps; ++ks) {
-        const int ky = tap / 3, kx = tap - 3 * ky;
-        const uint32_t tbit = k0 < a.K ? 1u << (tap & 31) : 0u;
-        s4 af[4];
-        if (c < a.Ca) {
-            const int d = ((ky - 1) * a.W + (kx - 1)) * a.Ca + c;
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                af[i] = s4{0, 0, 0, 0};
-                if (tv[i] & tbit) {
-                    const int64_t off = mA[i] + d;
-                    af[i] = *reinterpret_cast<const s4*>(a.inA + off);
-                    if (a.maskA) {
-                        const s4 mk = *reinterpret_cast<const s4*>(a.maskA + off);
-#pragma unroll
-                        for (int e = 0; e < 4; ++e)
-                            af[i][e] = bf_positive(mk[e]) ? af[i][e] : (short)0;
-                    }
-                }
-            }
-        } else {
-            // inB: pixel m + (ky - 1) W + kx - 1 at full resolution, else
-            // (n, (y + ky - 1) / 2, (x + kx - 1) / 2) of the half-size image.
-            const int cb = c - a.Ca;
-            const int dpix = (ky - 1) * a.W + (kx - 1);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                af[i] = s4{0, 0, 0, 0};
-                if (tv[i] & tbit) {
-                    const int pix = a.b_half ? (pn[i] * Hh + ((py[i] + ky - 1) >> 1)) * Wh +
-                                                   ((px[i] + kx - 1) >> 1)
-                                             : pm[i] + dpix;
-                    af[i] = *reinterpret_cast<const s4*>(a.inB + (int64_t)pix * a.Cb + cb);
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < NT; ++j) {
-            const s4 bf = *reinterpret_cast<const s4*>(
-                a.wt + (int64_t)(16 * j + r16) * a.Kpad + ks * 16 + g4 * 4);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) acc[i][j] = mfma(af[i], bf, acc[i][j]);
-        }
-        k0 += 16;
-        tap += dtap;
-        c += dc;
-        if (c >= a.Cin) {
-            c -= a.Cin;
-            ++tap;
-        }
-    }
-    const int CoB = a.Cout - a.CoA;
-#pragma unroll
-    for (int j = 0; j < NT; ++j) {
-        const int co = 16 * j + r16;
-        const float b = a.bias ? a.bias[co] : 0.f;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int m = base + 16 * i + 4 * g4 + r;
-                if (m >= M) continue;
-                float v = acc[i][j][r] + b;
-                if (a.relu) v = fmaxf(v, 0.f);
-                if (co < a.CoA) {
-                    uint16_t* p = a.outA + (int64_t)m * a.CoA + co;
-                    if (a.accumA) v += bf2f(*p);
-                    *p = f2bf(v);
-                } else {
-                    a.outB[(int64_t)m * CoB + (co - a.CoA)] = f2bf(v);
-                }
-            }
-        }
-    }
 }
 
 // 16x16x32 MFMA (gfx950): per lane l, 8 elements e:
@@ -695,24 +546,6 @@ __global__ void make_input_kernel(const float* L0, const float* L8, uint16_t* x,
     p[3] = 0;
 }
 
-__global__ void pool_kernel(const uint16_t* x, uint16_t* y, int N, int H, int W,
-                            int C) {
-    const int Ho = H / 2, Wo = W / 2;
-    const int64_t n_out = (int64_t)N * Ho * Wo * C;
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_out) return;
-    const int c = (int)(i % C);
-    const int64_t pix = i / C;
-    const int xo = (int)(pix % Wo);
-    const int64_t t = pix / Wo;
-    const int yo = (int)(t % Ho);
-    const int n = (int)(t / Ho);
-    const int64_t r0 = (((int64_t)n * H + 2 * yo) * W + 2 * xo) * C + c;
-    const int64_t r1 = r0 + (int64_t)W * C;
-    const float s = (bf2f(x[r0]) + bf2f(x[r0 + C])) + (bf2f(x[r1]) + bf2f(x[r1 + C]));
-    y[i] = f2bf(0.25f * s);
-}
-
 __global__ void pool_bwd_acc_kernel(uint16_t* ds, const uint16_t* dp, int N,
                                     int H, int W, int C) {
     const int64_t n_all = (int64_t)N * H * W * C;
@@ -826,30 +659,6 @@ __global__ void adam_kernel(float* p, const float* g, float* m, float* v,
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + 1e-8f);
 }
 
-// Master [Cout][3][3][Ci] FP32 -> forward operand [Cout][Kpad] bfloat16
-// (input channels padded to Cpad) and, if bwd is set, the backward-data
-// operand [Ci][KpadB] with K = tap' * Cout + co, tap' = 8 - tap (weights
-// flipped in both directions and transposed).
-__global__ void pack_weights_kernel(const float* w, uint16_t* fwd, uint16_t* bwd,
-                                    int Cout, int Ci, int Cpad, int Kpad,
-                                    int KpadB) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < Cout * Kpad) {
-        const int co = i / Kpad, k = i - co * Kpad;
-        const int tap = k / Cpad, c = k - tap * Cpad;
-        float v = 0.f;
-        if (tap < 9 && c < Ci) v = w[(co * 9 + tap) * Ci + c];
-        fwd[i] = f2bf(v);
-    }
-    if (bwd && i < Ci * KpadB) {
-        const int ci = i / KpadB, k = i - ci * KpadB;
-        const int tp = k / Cout, co = k - tp * Cout;
-        float v = 0.f;
-        if (tp < 9) v = w[(co * 9 + (8 - tp)) * Ci + ci];
-        bwd[i] = f2bf(v);
-    }
-}
-
 __global__ void log_frames_kernel(const float* I, float* L, int64_t n, float eps) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) L[i] = logf(I[i] + eps);
@@ -932,52 +741,39 @@ int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 hipError_t launch_conv(const ConvArgs& a, hipStream_t s) {
     const int64_t M = (int64_t)a.N * a.H * a.W;
-    if (a.Cin <= 0 || a.Cin % 4 || a.Ca % 4 || a.Cb % 4 || a.Kpad % 16 || a.K > a.Kpad ||
-        a.Cout % 16 || a.CoA > a.Cout || a.CoA < 0 || M <= 0 || M > kConvMaxPixels ||
-        (a.b_half && (a.H % 2 || a.W % 2)))
+    if (!a.wt8 || a.Cin <= 0 || a.Cin % 4 || a.Ca % 4 || a.Cb % 4 || a.Cout % 16 ||
+        a.CoA > a.Cout || a.CoA < 0 || M <= 0 || M > kConvMaxPixels ||
+        (a.b_half && (a.H % 2 || a.W % 2)) || a.C8 < a.Cin || a.C8 % conv8_chunk(a.C8) ||
+        a.Kpad8 != conv8_kpad(a.C8) || a.N > 65535 ||
+        (a.H + kConv8Rows - 1) / kConv8Rows > 65535)
         return hipErrorInvalidValue;
-    if (a.wt8) {
-        if (a.C8 < a.Cin || a.C8 % conv8_chunk(a.C8) || a.Kpad8 != conv8_kpad(a.C8) ||
-            a.N > 65535 || (a.H + kConv8Rows - 1) / kConv8Rows > 65535)
-            return hipErrorInvalidValue;
-        // (the fused pooling: whole 2x2 windows, outA only; CoA a multiple
-        // of 8 for the 16-byte runs of the output)
-        if ((a.pool_out && (a.H % 2 || a.W % 2 || a.CoA != a.Cout || a.accumA)) ||
-            (a.head_pred && (a.Cout != kHeadIn || a.CoA != a.Cout || a.accumA ||
-                             !a.head_w || !a.head_b || !a.head_L0 || !a.head_L8)) ||
-            a.CoA % 8)
-            return hipErrorInvalidValue;
-        const dim3 grid((a.W + kConv8Cols - 1) / kConv8Cols,
-                        (a.H + kConv8Rows - 1) / kConv8Rows, a.N);
-        const dim3 block(kConvThreads);
-        const size_t lds = (size_t)conv8_lds_bytes(a.C8, a.Cout / 16);
-#define NUP_CONV8(NT)                                                                   \
-    do {                                                                                \
-        if (conv8_chunk(a.C8) == 16)                                                    \
-            hipLaunchKernelGGL((conv8_kernel<NT, 16>), grid, block, lds, s, a);          \
-        else                                                                            \
-            hipLaunchKernelGGL((conv8_kernel<NT, 8>), grid, block, lds, s, a);           \
+    // (the fused pooling: whole 2x2 windows, outA only; CoA a multiple of 8
+    // for the 16-byte runs of the output)
+    if ((a.pool_out && (a.H % 2 || a.W % 2 || a.CoA != a.Cout || a.accumA)) ||
+        (a.head_pred && (a.Cout != kHeadIn || a.CoA != a.Cout || a.accumA || !a.head_w ||
+                         !a.head_b || !a.head_L0 || !a.head_L8)) ||
+        a.CoA % 8)
+        return hipErrorInvalidValue;
+    const dim3 grid((a.W + kConv8Cols - 1) / kConv8Cols, (a.H + kConv8Rows - 1) / kConv8Rows,
+                    a.N);
+    const dim3 block(kConvThreads);
+    const size_t lds = (size_t)conv8_lds_bytes(a.C8, a.Cout / 16);
+#define NUP_CONV8(NT)                                                               \
+    do {                                                                            \
+        if (conv8_chunk(a.C8) == 16)                                                \
+            hipLaunchKernelGGL((conv8_kernel<NT, 16>), grid, block, lds, s, a);      \
+        else                                                                        \
+            hipLaunchKernelGGL((conv8_kernel<NT, 8>), grid, block, lds, s, a);       \
     } while (0)
-        switch (a.Cout / 16) {
-        case 1: NUP_CONV8(1); break;
-        case 2: NUP_CONV8(2); break;
-        case 3: NUP_CONV8(3); break;
-        case 4: NUP_CONV8(4); break;
-        case 6: NUP_CONV8(6); break;
-        default: return hipErrorInvalidValue;
-        }
-#undef NUP_CONV8
-        return hipGetLastError();
-    }
-    const dim3 grid(blocks_for(M, 64 * (kConvThreads / kWave))), block(kConvThreads);
     switch (a.Cout / 16) {
-    case 1: hipLaunchKernelGGL(conv_kernel<1>, grid, block, 0, s, a); break;
-    case 2: hipLaunchKernelGGL(conv_kernel<2>, grid, block, 0, s, a); break;
-    case 3: hipLaunchKernelGGL(conv_kernel<3>, grid, block, 0, s, a); break;
-    case 4: hipLaunchKernelGGL(conv_kernel<4>, grid, block, 0, s, a); break;
-    case 6: hipLaunchKernelGGL(conv_kernel<6>, grid, block, 0, s, a); break;
+    case 1: NUP_CONV8(1); break;
+    case 2: NUP_CONV8(2); break;
+    case 3: NUP_CONV8(3); break;
+    case 4: NUP_CONV8(4); break;
+    case 6: NUP_CONV8(6); break;
     default: return hipErrorInvalidValue;
     }
+#undef NUP_CONV8
     return hipGetLastError();
 }
 
@@ -1011,14 +807,6 @@ hipError_t launch_make_input(const float* L0, const float* L8, uint16_t* x,
                              int64_t M, hipStream_t s) {
     hipLaunchKernelGGL(make_input_kernel, dim3(blocks_for(M, 256)), dim3(256), 0,
                        s, L0, L8, x, M);
-    return hipGetLastError();
-}
-
-hipError_t launch_pool(const uint16_t* x, uint16_t* y, int N, int H, int W,
-                       int C, hipStream_t s) {
-    const int64_t n = (int64_t)N * (H / 2) * (W / 2) * C;
-    hipLaunchKernelGGL(pool_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, x,
-                       y, N, H, W, C);
     return hipGetLastError();
 }
 
@@ -1059,15 +847,6 @@ hipError_t launch_adam(float* p, const float* g, float* m, float* v, int64_t n,
                        float lr, float c1, float c2, hipStream_t s) {
     hipLaunchKernelGGL(adam_kernel, dim3(blocks_for(n, 256)), dim3(256), 0, s, p, g,
                        m, v, n, lr, c1, c2);
-    return hipGetLastError();
-}
-
-hipError_t launch_pack_weights(const float* w, uint16_t* fwd, uint16_t* bwd,
-                               int Cout, int Ci, int Cpad, int Kpad, int KpadB,
-                               hipStream_t s) {
-    const int n = Cout * Kpad > Ci * KpadB ? Cout * Kpad : Ci * KpadB;
-    hipLaunchKernelGGL(pack_weights_kernel, dim3(blocks_for(n, 256)), dim3(256), 0,
-                       s, w, fwd, bwd, Cout, Ci, Cpad, Kpad, KpadB);
     return hipGetLastError();
 }
 

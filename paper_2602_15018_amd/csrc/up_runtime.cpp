@@ -35,11 +35,9 @@ int round16(int k) { return (k + 15) / 16 * 16; }
 
 struct Layer {
     int ci, cpad, co;
-    int K, Kpad, KB, KpadB;
+    int K, Kpad;                 // the weight gradient's [co][Kpad] layout
     int c8, Kpad8, KpadB8;       // the staged kernel's layout (see nup::conv8_kpad)
     int64_t w_off, b_off;        // into the flat FP32 parameters
-    uint16_t* wf = nullptr;      // forward operand [co][Kpad]
-    uint16_t* wb = nullptr;      // backward-data operand [ci][KpadB]
     uint16_t* wf8 = nullptr;     // forward operand [co][Kpad8]
     uint16_t* wb8 = nullptr;     // backward-data operand [ci][KpadB8]
 };
@@ -133,8 +131,6 @@ int pack(nsim_up* h) {
     if (h->packed) return NSIM_UP_OK;
     for (int i = 0; i < kNumLayers; ++i) {
         Layer& l = h->L[i];
-        UP_HIP(h, nup::launch_pack_weights(h->p + l.w_off, l.wf, l.wb, l.co, l.ci,
-                                           l.cpad, l.Kpad, l.KpadB, h->stream));
         UP_HIP(h, nup::launch_pack_weights8(h->p + l.w_off, l.wf8, l.wb8, l.co, l.ci,
                                             l.c8, l.Kpad8, l.KpadB8, h->stream));
     }
@@ -158,7 +154,6 @@ nup::ConvArgs conv_args(const Layer& l, const uint16_t* inA, int Ca,
     nup::ConvArgs a{};
     a.inA = inA;
     a.inB = inB;
-    a.wt = l.wf;
     a.bias = bias;
     a.outA = out;
     a.N = N;
@@ -169,9 +164,6 @@ nup::ConvArgs conv_args(const Layer& l, const uint16_t* inA, int Ca,
     a.Cin = Ca + Cb;
     a.Cout = l.co;
     a.CoA = l.co;
-    a.K = l.K;
-    a.Kpad = l.Kpad;
-    // the LDS-staged kernel
     a.wt8 = l.wf8;
     a.C8 = l.c8;
     a.Kpad8 = l.Kpad8;
@@ -278,7 +270,6 @@ int bwd_data(nsim_up* h, int li, const uint16_t* dy, const uint16_t* y,
     nup::ConvArgs a{};
     a.inA = dy;
     a.maskA = y;
-    a.wt = l.wb;
     a.outA = outA;
     a.outB = outB;
     a.N = N;
@@ -288,8 +279,6 @@ int bwd_data(nsim_up* h, int li, const uint16_t* dy, const uint16_t* y,
     a.Cin = l.co;
     a.Cout = l.cpad;
     a.CoA = CoA;
-    a.K = l.KB;
-    a.Kpad = l.KpadB;
     a.wt8 = l.wb8;
     a.C8 = l.co;
     a.Kpad8 = l.KpadB8;
@@ -390,8 +379,6 @@ int nsim_up_create(const nsim_up_config* cfg, void* stream, nsim_up_t** out) {
         l.co = kLayers[i].co;
         l.K = 9 * l.cpad;
         l.Kpad = round16(l.K);
-        l.KB = 9 * l.co;
-        l.KpadB = round16(l.KB);
         l.c8 = l.cpad <= 8 ? 8 : round16(l.cpad);
         l.Kpad8 = nup::conv8_kpad(l.c8);
         l.KpadB8 = nup::conv8_kpad(l.co);
@@ -417,8 +404,6 @@ int nsim_up_create(const nsim_up_config* cfg, void* stream, nsim_up_t** out) {
     chk(alloc(h, &h->v, h->n_params));
     for (int i = 0; i < kNumLayers; ++i) {
         Layer& l = h->L[i];
-        chk(alloc(h, &l.wf, (int64_t)l.co * l.Kpad));
-        chk(alloc(h, &l.wb, (int64_t)l.cpad * l.KpadB));
         chk(alloc(h, &l.wf8, (int64_t)l.co * l.Kpad8));
         chk(alloc(h, &l.wb8, (int64_t)l.cpad * l.KpadB8));
     }
