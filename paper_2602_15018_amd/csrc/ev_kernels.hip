@@ -185,9 +185,13 @@ struct Px {
     float prev;      // previous sample (I, or L for log input)
     float cp, cn;    // thresholds (FP32 values of the definition)
     float Ep2f, En2f; // level-2 factors with the guard folded in (intensity)
+    float Ep2g, En2g; // the same with the guard on the other side
+    float Ep3f, En3f; // level-3 factors, guard as for level 2
     float Ahi, Bhi, Chi;  // I > Ahi: maybe up; I >= Bhi: surely >= 1 up;
                           // I <= Chi: surely < 2 up
+    float Dhi, Ehi;       // I >= Dhi: surely >= 2 up; I <= Ehi: surely < 3 up
     float Alo, Blo, Clo;  // mirrored for down crossings
+    float Dlo, Elo;
 };
 
 template <bool LOGIN>
@@ -206,13 +210,14 @@ __device__ __forceinline__ double lvl_above(double X, double g, double eps) {
     return LOGIN ? X + g * (1.0 + fabs(X)) : (X - eps) + g * (X + eps);
 }
 
-// The six FP32 sample thresholds of the current levels.  For intensity
-// input each is one FP32 FMA on the level rounded once to FP32:
-// x (1 -/+ g) - eps (1 +/- g), with the level-2 factors Ep (1 - g),
-// En (1 + g) precomputed per pixel in FP32.  The three roundings (level,
-// factor or constant, FMA) move a threshold by at most 3 * 2^-24 (X + eps),
-// inside the guard g (X + eps) = 2^-22 (X + eps), with room left for the
-// FP64 level's own error (~1e-11 relative); 1 -/+ g are exact in FP32.
+// The ten FP32 sample thresholds of the current levels (the first three
+// levels in each direction).  For intensity input each is one FP32 FMA on
+// the level rounded once to FP32: x (1 -/+ g) - eps (1 +/- g), with the
+// factors of levels 2 and 3 (Ep (1 -/+ g), Ep^2 (1 - g) and their mirrors)
+// precomputed per pixel in FP32.  The three roundings (level, factor or
+// constant, FMA) move a threshold by at most 3 * 2^-24 (X + eps), inside
+// the guard g (X + eps) = 2^-22 (X + eps), with room left for the FP64
+// level's own error (~1e-11 relative); 1 -/+ g are exact in FP32.
 template <bool LOGIN>
 __device__ __forceinline__ void refresh_thresholds(Px& q, double eps) {
     if (LOGIN) {
@@ -222,6 +227,11 @@ __device__ __forceinline__ void refresh_thresholds(Px& q, double eps) {
         q.Alo = (float)lvl_above<LOGIN>(q.Xl, kG32, eps);
         q.Blo = (float)lvl_below<LOGIN>(q.Xl, kG32, eps);
         q.Clo = (float)lvl_above<LOGIN>(lvl_step<LOGIN>(q.Xl, q.En), kG32, eps);
+        const double xh2 = lvl_step<LOGIN>(q.Xh, q.Ep), xl2 = lvl_step<LOGIN>(q.Xl, q.En);
+        q.Dhi = (float)lvl_above<LOGIN>(xh2, kG32, eps);
+        q.Ehi = (float)lvl_below<LOGIN>(lvl_step<LOGIN>(xh2, q.Ep), kG32, eps);
+        q.Dlo = (float)lvl_below<LOGIN>(xl2, kG32, eps);
+        q.Elo = (float)lvl_above<LOGIN>(lvl_step<LOGIN>(xl2, q.En), kG32, eps);
     } else {
         const float eb = (float)(-eps * (1.0 + kG32));
         const float ea = (float)(-eps * (1.0 - kG32));
@@ -233,6 +243,10 @@ __device__ __forceinline__ void refresh_thresholds(Px& q, double eps) {
         q.Alo = fmaf(xl, gp, ea);
         q.Blo = fmaf(xl, gm, eb);
         q.Clo = fmaf(xl, q.En2f, ea);
+        q.Dhi = fmaf(xh, q.Ep2g, ea);
+        q.Ehi = fmaf(xh, q.Ep3f, eb);
+        q.Dlo = fmaf(xl, q.En2g, eb);
+        q.Elo = fmaf(xl, q.En3f, ea);
     }
 }
 
@@ -331,6 +345,10 @@ __device__ __forceinline__ void pixel_levels(Px& q, bool valid, double eps) {
     }
     q.Ep2f = (float)(q.Ep * (1.0 - kG32));
     q.En2f = (float)(q.En * (1.0 + kG32));
+    q.Ep2g = (float)(q.Ep * (1.0 + kG32));
+    q.En2g = (float)(q.En * (1.0 - kG32));
+    q.Ep3f = (float)(q.Ep * q.Ep * (1.0 - kG32));
+    q.En3f = (float)(q.En * q.En * (1.0 + kG32));
     exact_levels<LOGIN>(q, eps);
     if (!valid) {
         // padding lanes never become candidates
@@ -484,22 +502,30 @@ __device__ __forceinline__ int wave_max_small(int v) {
 }
 
 // Crossing count of one frame for the candidate lanes: FP32 certainty for
-// exactly one crossing, an FP64 level walk with a small guard otherwise, the
-// FP64 replica of the definition when even that cannot decide.
-template <bool LOGIN>
+// exactly one crossing (with TWO also for exactly two), an FP64 level walk
+// with a small guard otherwise, the FP64 replica of the definition when even
+// that cannot decide.  (TWO costs ten registers of thresholds and factors,
+// which the walk kernel has and the fused kernel has not.)
+template <bool LOGIN, bool TWO>
 __device__ __forceinline__ void count_frame(const Px& q, float I, float Ip,
                                             bool cand, bool force64, double eps,
                                             int& n, bool& up, bool& f64, int& bad,
                                             int* dg) {
-    // one crossing for sure: up: Bhi <= I <= Chi, down: Clo <= I <= Blo
+    // one crossing for sure: up: Bhi <= I <= Chi, down: Clo <= I <= Blo;
+    // two: up: Dhi <= I <= Ehi, down: Elo <= I <= Dlo (the ranges are
+    // disjoint: Chi < Dhi and Dlo < Clo)
     up = I > q.Ahi;
     const float lo = up ? q.Bhi : q.Clo;
     const float hi = up ? q.Chi : q.Blo;
-    const bool one = cand & (I >= lo) & (I <= hi) & !force64;
-    n = one ? 1 : 0;
+    const float lo2 = up ? q.Dhi : q.Elo;
+    const float hi2 = up ? q.Ehi : q.Dlo;
+    const bool one = (I >= lo) & (I <= hi);
+    const bool two = TWO & (I >= lo2) & (I <= hi2);
+    const bool fast = cand & (one | two) & !force64;
+    n = fast ? (one ? 1 : 2) : 0;
     f64 = cand & force64;
-    bool slow = cand & !one & !force64;
-    if (__ballot(slow)) {
+    bool slow = cand & !fast & !force64;
+    {
         if (slow) {
             const double s = LOGIN ? (double)I : (double)I + eps;
             double X = up ? q.Xh : q.Xl;
@@ -524,8 +550,10 @@ __device__ __forceinline__ void count_frame(const Px& q, float I, float Ip,
             if (f64) n = 0;
         }
     }
-    if (__ballot(f64)) {
-        ++dg[4];
+#ifdef NSIM_STEP_DIAG
+    if (__ballot(f64)) ++dg[4];
+#endif
+    {
         if (f64) {
             ++dg[0];
             const LogPair lp = log_pair64<LOGIN>(Ip, I, eps);
@@ -925,7 +953,7 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
                 const float Ip = u > 0 ? fslab[(u - 1) * kWave + lane] : prev0;
                 int n;
                 bool up, f64;
-                count_frame<LOGIN>(q, I, Ip, go, force64, eps, n, up, f64, bad, dg);
+                count_frame<LOGIN, false>(q, I, Ip, go, force64, eps, n, up, f64, bad, dg);
                 if (go) cm &= ~((2u << u) - 1u);
                 if (bad) {
                     // a lane past the supported range takes no further part
@@ -1012,6 +1040,8 @@ constexpr uint32_t kRmUp = 1u << 14, kRmF64 = 1u << 15;
 
 // Phase A of one lane's pixel over the launch's frames, records to `seg`
 // (the wave's segment), `nrec` the wave's record count (wave-uniform).
+// The slab holds kChunk + 1 samples per lane: the one before the chunk,
+// then the chunk's frames.
 // `fb` is the wave's first sample of frame 0 (wave-uniform), `loff` the
 // lane's pixel from there (0 .. 63); padding lanes read the wave's first
 // pixel (in bounds), which their thresholds keep out of every candidate set.
@@ -1027,6 +1057,12 @@ __device__ __forceinline__ void walk_append(const StepArgs& a, Px& q,
     const uint64_t lt = lanemask_lt();
     int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     constexpr int U = kChunk;
+    // The wave's record segment: uniform bases and 32-bit byte offsets
+    // (a segment holds at most 64 kMaxFramesPerLaunch records).
+    char* const rm = reinterpret_cast<char*>(a.rec_meta + seg);
+    char* const ri = reinterpret_cast<char*>(a.rec_I + seg);
+    char* const rp = reinterpret_cast<char*>(a.rec_prev + seg);
+    char* const rx = reinterpret_cast<char*>(a.rec_X1 + seg);
     // frames are loaded a chunk ahead; full chunks without per-frame tests
     float r[U];
 #pragma unroll
@@ -1036,16 +1072,17 @@ __device__ __forceinline__ void walk_append(const StepArgs& a, Px& q,
     for (int kc = 0; kc < K; kc += U) {
         const int cnt = (K - kc) < U ? (K - kc) : U;
         uint32_t cm = 0;
+        fslab[lane] = q.prev;
         if (cnt == U) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                fslab[u * kWave + lane] = r[u];
+                fslab[(u + 1) * kWave + lane] = r[u];
                 cm |= ((r[u] > q.Ahi) | (r[u] < q.Alo)) ? (1u << u) : 0u;
             }
         } else {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                fslab[u * kWave + lane] = r[u];
+                fslab[(u + 1) * kWave + lane] = r[u];
                 if (u < cnt && ((r[u] > q.Ahi) | (r[u] < q.Alo))) cm |= 1u << u;
             }
         }
@@ -1059,17 +1096,17 @@ __device__ __forceinline__ void walk_append(const StepArgs& a, Px& q,
                 r[u] = kc + U + u < K ? __builtin_nontemporal_load(fk + (int64_t)u * P + loff)
                                       : 1.0f;
         }
-        const float prev0 = q.prev;
         // passes while some lane has a candidate frame left in the chunk
         for (;;) {
             const bool go = cm != 0u;
             if (!__ballot(go)) break;
             const int u = go ? __builtin_ctz(cm) : 0;
-            const float I = fslab[u * kWave + lane];
-            const float Ip = u > 0 ? fslab[(u - 1) * kWave + lane] : prev0;
+            const float* const su = fslab + u * kWave + lane;
+            const float Ip = su[0];
+            const float I = su[kWave];
             int n;
             bool up, f64;
-            count_frame<LOGIN>(q, I, Ip, go, force64, eps, n, up, f64, bad, dg);
+            count_frame<LOGIN, true>(q, I, Ip, go, force64, eps, n, up, f64, bad, dg);
             if (go) cm &= ~((2u << u) - 1u);
             if (bad) {
                 // a lane past the supported range takes no further part
@@ -1079,14 +1116,14 @@ __device__ __forceinline__ void walk_append(const StepArgs& a, Px& q,
             }
             const uint64_t wm = __ballot(n > 0);
             if (n > 0) {
-                const int64_t at = seg + nrec + __popcll(wm & lt);
+                const uint32_t at = nrec + (uint32_t)__popcll(wm & lt);
                 const double X1 = up ? q.Xh : q.Xl;
-                a.rec_meta[at] = (uint32_t)lane | ((uint32_t)(kc + u) << 6) |
-                                 (up ? kRmUp : 0u) | (f64 ? kRmF64 : 0u) |
-                                 ((uint32_t)(f64 ? 0 : n) << 16);
-                a.rec_I[at] = I;
-                a.rec_prev[at] = Ip;
-                a.rec_X1[at] = f64 ? __hiloint2double(0, n) : X1;
+                *reinterpret_cast<uint32_t*>(rm + 4u * at) =
+                    (uint32_t)lane | ((uint32_t)(kc + u) << 6) | (up ? kRmUp : 0u) |
+                    (f64 ? kRmF64 : 0u) | ((uint32_t)(f64 ? 0 : n) << 16);
+                *reinterpret_cast<float*>(ri + 4u * at) = I;
+                *reinterpret_cast<float*>(rp + 4u * at) = Ip;
+                *reinterpret_cast<double*>(rx + 8u * at) = f64 ? __hiloint2double(0, n) : X1;
                 // move the reference by the n crossings
                 if (up)
                     q.nup += n;
@@ -1109,7 +1146,7 @@ __device__ __forceinline__ void walk_append(const StepArgs& a, Px& q,
                 if (u + 1 < cnt) {
 #pragma unroll
                     for (int v = 0; v < U; ++v) {
-                        const float J = fslab[v * kWave + lane];
+                        const float J = fslab[(v + 1) * kWave + lane];
                         nm |= ((J > q.Ahi) | (J < q.Alo)) ? (1u << v) : 0u;
                     }
                 }
@@ -1117,12 +1154,12 @@ __device__ __forceinline__ void walk_append(const StepArgs& a, Px& q,
             }
             nrec += (uint32_t)__popcll(wm);
         }
-        q.prev = fslab[(cnt - 1) * kWave + lane];
+        q.prev = fslab[cnt * kWave + lane];
     }
 }
 
 // LDS of the walk kernel per wave: the frame slab.
-constexpr int kWalkLdsPerWave = kChunk * kWave * (int)sizeof(float);
+constexpr int kWalkLdsPerWave = (kChunk + 1) * kWave * (int)sizeof(float);
 
 template <bool LOGIN, bool MAP>
 __global__ __launch_bounds__(kStepMaxThreads) void walk_kernel(const StepArgs a) {
@@ -2008,7 +2045,7 @@ struct LaneFrame {
         have_d = false;
         L0d = L1d = 0.0;
         int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-        count_frame<LOGIN>(q, I, Ip, cand, force64, a.log_eps, n, up, f64, bad, dg);
+        count_frame<LOGIN, false>(q, I, Ip, cand, force64, a.log_eps, n, up, f64, bad, dg);
         ts = TsSetup{};
         if (n > 0 && !f64) {
             Rec rc;
