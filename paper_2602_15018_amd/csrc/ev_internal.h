@@ -46,6 +46,7 @@ struct EnvRec {
     int32_t npix;
     int32_t width;
     int32_t height;
+    double inv_width;   // 1 / width rounded to FP64 (row of a pixel index)
 };
 
 // Device-resident stream header.  Written by kernels, read by the host only

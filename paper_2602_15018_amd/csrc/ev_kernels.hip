@@ -37,6 +37,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "ev_internal.h"
 
 namespace nsim {
@@ -1740,6 +1742,7 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const GatherArgs
 }
 
 // One stable LSD radix pass over the packed events (onesweep scheme).
+template <bool FINAL>
 __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
     __shared__ uint32_t s_key[kSortTile];
     __shared__ uint32_t s_val[kSortTile];
@@ -1792,10 +1795,13 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
         uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
 #pragma unroll
         for (int i = 0; i < kSortItems; ++i) {
+            // (past the end: item 0 is read, which always exists, and dropped)
             const int64_t e = base + w * (kWave * kSortItems) + i * kWave + lane;
             const bool v = e < n;
-            key[i] = v ? a.kin[e] : 0u;
-            val[i] = v ? a.vin[e] : 0u;
+            const int64_t ec = v ? e : 0;
+            const uint32_t k = a.kin[ec], x = a.vin[ec];
+            key[i] = v ? k : 0u;
+            val[i] = v ? x : 0u;
         }
 #pragma unroll
         for (int i = 0; i < kDigits / kWave; ++i) s_wcnt[w][lane + i * kWave] = 0u;
@@ -1918,40 +1924,98 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
             const uint32_t d = (sk[i] >> shift) & dmask;
             return j < cnt ? (int64_t)s_gbase[d] + (j - (int)s_lstart[d]) : -1;
         };
-        if (a.final_pass) {
+        if (FINAL) {
             // an environment index outside the table can only come from a
             // corrupt key: the item is dropped and the step fails
-            uint32_t ew0[kSortItems], ewd[kSortItems];
-            bool bad = false;
+            // (a launch that does not wrap the queue, with fewer than 2^29
+            // events, writes through uniform bases at the tail with 32-bit
+            // byte offsets)
+            const bool flat = tailm + n <= a.qcap && n < ((int64_t)1 << 29);
+            char* const tb = reinterpret_cast<char*>(a.t_out + tailm);
+            char* const xb = reinterpret_cast<char*>(a.x_out + tailm);
+            char* const yb = reinterpret_cast<char*>(a.y_out + tailm);
+            char* const pb = reinterpret_cast<char*>(a.p_out + tailm);
+            auto put = [&](auto flat_c, int64_t gpos, uint32_t skey, uint32_t sval,
+                           uint32_t y, uint32_t x) {
+                const uint32_t toff = a.key_pbits ? (skey >> a.key_pbits)
+                                                  : (skey & ((1u << a.key_tbits) - 1u));
+                const int64_t t = a.T0 + (int64_t)toff;
+                const int8_t p = (sval & 1u) ? (int8_t)1 : (int8_t)-1;
+                if constexpr (decltype(flat_c)::value) {
+                    const uint32_t g = (uint32_t)gpos;
+                    *reinterpret_cast<int64_t*>(tb + 8u * g) = t;
+                    *reinterpret_cast<uint16_t*>(xb + 2u * g) = (uint16_t)x;
+                    *reinterpret_cast<uint16_t*>(yb + 2u * g) = (uint16_t)y;
+                    *reinterpret_cast<int8_t*>(pb + g) = p;
+                } else {
+                    int64_t r = tailm + gpos;
+                    if (r >= a.qcap) r -= a.qcap;
+                    a.t_out[r] = t;
+                    a.x_out[r] = (uint16_t)x;
+                    a.y_out[r] = (uint16_t)y;
+                    a.p_out[r] = p;
+                }
+            };
+            if (a.n_env == 1 && !a.key_pbits) {
+                // one environment: its record once, and the row of a pixel
+                // index from the reciprocal of the width: px * RN(1/width)
+                // in FP64 is within 2^-20 of px / width (px < 2^32, two
+                // roundings of 2^-53), and a quotient that is not an integer
+                // is at least 1/width >= 2^-16 below the next one, so the
+                // truncation is the quotient or, for an exact one, one less
+                const EnvRec er = a.envs[0];
+                const uint32_t wd = (uint32_t)er.width;
+                const uint32_t px0 = (uint32_t)er.wave0 * kWave;
+                bool bad = false;
+                auto items = [&](auto flat_c) {
 #pragma unroll
-            for (int i = 0; i < kSortItems; ++i) {
-                const uint32_t env = a.key_pbits ? 0u : (sk[i] >> a.key_tbits);
-                const bool v = tid + i * kSortThreads < cnt;
-                const bool ok = env < (uint32_t)a.n_env;
-                bad = bad || (v && !ok);
-                ew0[i] = (v && ok) ? (uint32_t)a.envs[env].wave0 : 0xFFFFFFFFu;
-                ewd[i] = (v && ok) ? (uint32_t)a.envs[env].width : 1u;
-            }
-            if (bad) atomicOr(&a.hdr->internal_err, kErrWait);
+                    for (int i = 0; i < kSortItems; ++i) {
+                        const int64_t gpos = dest(i);
+                        if (gpos < 0 || gpos >= n) continue;  // tail, or a corrupt histogram
+                        if ((sk[i] >> a.key_tbits) != 0u) {   // corrupt key
+                            bad = true;
+                            continue;
+                        }
+                        const uint32_t px = (sv[i] >> 1) - px0;
+                        uint32_t y = (uint32_t)((double)px * er.inv_width);
+                        uint32_t x = px - y * wd;
+                        if (x >= wd) {
+                            ++y;
+                            x -= wd;
+                        }
+                        put(flat_c, gpos, sk[i], sv[i], y, x);
+                    }
+                };
+                if (flat)
+                    items(std::true_type{});
+                else
+                    items(std::false_type{});
+                if (bad) atomicOr(&a.hdr->internal_err, kErrWait);
+            } else {
+                uint32_t ew0[kSortItems], ewd[kSortItems];
+                bool bad = false;
 #pragma unroll
-            for (int i = 0; i < kSortItems; ++i) {
-                const int64_t gpos = dest(i);
-                if (gpos < 0 || gpos >= n) continue;  // tail, or a corrupt histogram
-                if (ew0[i] == 0xFFFFFFFFu) continue;  // corrupt key
-                int64_t r = tailm + gpos;
-                if (r >= a.qcap) r -= a.qcap;
-                const uint32_t toff = a.key_pbits ? (sk[i] >> a.key_pbits)
-                                                  : (sk[i] & ((1u << a.key_tbits) - 1u));
-                const uint32_t px = (sv[i] >> 1) - ew0[i] * kWave;
-                // px < 2^32 and width <= 65535: the FP64 quotient's floor is
-                // the integer quotient (its distance to the next integer,
-                // >= 1/width, exceeds the rounding error)
-                const uint32_t y = (uint32_t)((double)px / (double)ewd[i]);
-                const uint32_t x = px - y * ewd[i];
-                a.t_out[r] = a.T0 + (int64_t)toff;
-                a.x_out[r] = (uint16_t)x;
-                a.y_out[r] = (uint16_t)y;
-                a.p_out[r] = (sv[i] & 1u) ? (int8_t)1 : (int8_t)-1;
+                for (int i = 0; i < kSortItems; ++i) {
+                    const uint32_t env = a.key_pbits ? 0u : (sk[i] >> a.key_tbits);
+                    const bool v = tid + i * kSortThreads < cnt;
+                    const bool ok = env < (uint32_t)a.n_env;
+                    bad = bad || (v && !ok);
+                    ew0[i] = (v && ok) ? (uint32_t)a.envs[env].wave0 : 0xFFFFFFFFu;
+                    ewd[i] = (v && ok) ? (uint32_t)a.envs[env].width : 1u;
+                }
+                if (bad) atomicOr(&a.hdr->internal_err, kErrWait);
+#pragma unroll
+                for (int i = 0; i < kSortItems; ++i) {
+                    const int64_t gpos = dest(i);
+                    if (gpos < 0 || gpos >= n) continue;  // tail, or a corrupt histogram
+                    if (ew0[i] == 0xFFFFFFFFu) continue;  // corrupt key
+                    const uint32_t px = (sv[i] >> 1) - ew0[i] * kWave;
+                    // px < 2^32 and width <= 65535: the FP64 quotient's floor
+                    // is the integer quotient (its distance to the next
+                    // integer, >= 1/width, exceeds the rounding error)
+                    const uint32_t y = (uint32_t)((double)px / (double)ewd[i]);
+                    put(std::false_type{}, gpos, sk[i], sv[i], y, px - y * ewd[i]);
+                }
             }
         } else {
 #pragma unroll
@@ -2499,7 +2563,10 @@ hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_pass(const PassArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(pass_kernel, dim3(1024), dim3(kSortThreads), 0, s, a);
+    if (a.final_pass)
+        hipLaunchKernelGGL(pass_kernel<true>, dim3(1024), dim3(kSortThreads), 0, s, a);
+    else
+        hipLaunchKernelGGL(pass_kernel<false>, dim3(1024), dim3(kSortThreads), 0, s, a);
     return hipGetLastError();
 }
 

@@ -1047,6 +1047,7 @@ int create_core(nsim_ev* h, const std::vector<EnvDesc>& envs, double log_eps,
         r.npix = d.width * d.height;
         r.width = d.width;
         r.height = d.height;
+        r.inv_width = 1.0 / (double)d.width;
         h->env_host.push_back(r);
         off += r.npix;
         wave += (r.npix + nsim::kWave - 1) / nsim::kWave;
