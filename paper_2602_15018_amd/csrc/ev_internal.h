@@ -162,7 +162,7 @@ struct GatherArgs {
     const uint32_t* skey;    // staging (packed entries)
     const int32_t* wave_env;
     int32_t key_tbits;
-    int32_t pad;
+    int32_t long_segments;   // the launch has several frames: long segments
     uint32_t* dkey;          // dense, pixel order
     uint32_t* dval;
     Header* hdr;

@@ -1672,18 +1672,19 @@ __device__ __forceinline__ bool step_fits(const Header* hdr, int64_t scap,
 // Copy every wave's segment to its pixel-order position and count the
 // radix digits of all passes; also clears the passes' look-back words.
 // Each 16-lane group of a wave walks its own segments (a segment of a one-
-// frame call holds a handful of entries), four slots per lane per round so
-// that the loads of a round are in flight together.
+// frame call holds a handful of entries), U slots per lane per round so
+// that the loads of a round are in flight together: 4 for launches of a
+// frame or a few, 16 for the long segments of many frames (fewer rounds,
+// each waiting once for its loads).
 // Every workgroup adds its digit counts to the global histogram with
 // atomics on the same few hundred words; when segments are many and short
 // (one-frame batches) wide workgroups keep those flushes few, otherwise
 // 256-thread workgroups keep the chip full.
 constexpr int kGatherGroup = 16;
-constexpr int kGatherUnroll = 4;
 constexpr int kGatherMaxBlocks = 2048;    // 256-thread workgroups
 constexpr int kGatherWideBlocks = 512;    // 1024-thread workgroups
 
-template <int kGatherThreads>
+template <int kGatherThreads, int U>
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const GatherArgs a) {
     __shared__ uint32_t s_h[kMaxPasses * kDigits];
     int64_t n;
@@ -1712,15 +1713,15 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const GatherArgs
         int64_t dst = a.pref[wv];
         const uint32_t key_hi = (uint32_t)a.wave_env[wv] << a.key_tbits;
         const uint32_t pix0 = (uint32_t)(wv * kWave);
-        for (uint32_t j0 = 0; j0 < ns; j0 += kGatherUnroll * kGatherGroup) {
-            uint32_t e[kGatherUnroll];
+        for (uint32_t j0 = 0; j0 < ns; j0 += U * kGatherGroup) {
+            uint32_t e[U];
 #pragma unroll
-            for (int u = 0; u < kGatherUnroll; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const uint32_t j = j0 + u * kGatherGroup + gl;
                 e[u] = j < ns ? a.skey[sb + j] : kEntryHole;
             }
 #pragma unroll
-            for (int u = 0; u < kGatherUnroll; ++u) {
+            for (int u = 0; u < U; ++u) {
                 const bool v = e[u] != kEntryHole;
                 const uint64_t m = __ballot(v) & gmask;
                 if (v) {
@@ -2554,10 +2555,13 @@ hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
     if (want > kGatherMaxBlocks) {
         const int64_t wide = (a.nwaves + 4 * kGroups - 1) / (4 * kGroups);
         const int blocks = (int)std::min<int64_t>(kGatherWideBlocks, wide);
-        hipLaunchKernelGGL(gather_kernel<1024>, dim3(blocks), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL((gather_kernel<1024, 4>), dim3(blocks), dim3(1024), 0, s, a);
     } else {
         const int blocks = (int)std::max<int64_t>(1, want);
-        hipLaunchKernelGGL(gather_kernel<256>, dim3(blocks), dim3(256), 0, s, a);
+        if (a.long_segments)
+            hipLaunchKernelGGL((gather_kernel<256, 16>), dim3(blocks), dim3(256), 0, s, a);
+        else
+            hipLaunchKernelGGL((gather_kernel<256, 4>), dim3(blocks), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }

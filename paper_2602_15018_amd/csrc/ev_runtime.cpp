@@ -410,6 +410,7 @@ void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
     ga.skey = sc.stage_key;
     ga.wave_env = h->wave_env;
     ga.key_tbits = tbits;
+    ga.long_segments = kl >= 8 ? 1 : 0;
     ga.dkey = sc.skey[0];
     ga.dval = sc.sval[0];
     ga.hdr = h->hdr;
