@@ -28,6 +28,10 @@ constexpr int kSplitMinFrames = 16;           // launches of at least this many 
 constexpr int kSortThreads = 256;
 constexpr int kSortItems = 24;               // items per thread per tile
 constexpr int kSortTile = kSortThreads * kSortItems;
+// small tiles for launches of at most kSmallSortMax events
+constexpr int kSmallSortItems = 4;
+constexpr int kSmallSortTile = kSortThreads * kSmallSortItems;
+constexpr int64_t kSmallSortMax = 1 << 17;
 constexpr int kDigitBits = 8;
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kMaxPasses = 4;
@@ -215,6 +219,7 @@ struct PassArgs {
     uint32_t* tile_ctr;
     Header* hdr;
     int64_t scratch_cap;
+    int64_t max_tiles;
 };
 
 // The paper's kernel design (Sec. 2, kernel paragraph), kept as an A/B of

@@ -1669,6 +1669,15 @@ __device__ __forceinline__ bool step_fits(const Header* hdr, int64_t scap,
            n <= scap && (hdr->tail - hdr->head) + n <= qcap;
 }
 
+// Tile size of a sort: small tiles for a launch of few events, so that
+// more workgroups share its passes, as long as their look-back words fit
+// the status arrays (max_tiles per pass, sized for large tiles).
+__device__ __forceinline__ int sort_tile(int64_t n, int64_t max_tiles) {
+    return (n <= kSmallSortMax && (n + kSmallSortTile - 1) / kSmallSortTile < max_tiles)
+               ? kSmallSortTile
+               : kSortTile;
+}
+
 // Copy every wave's segment to its pixel-order position and count the
 // radix digits of all passes; also clears the passes' look-back words.
 // Each 16-lane group of a wave walks its own segments (a segment of a one-
@@ -1691,7 +1700,8 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const GatherArgs
     const bool ok = step_fits(a.hdr, a.scratch_cap, a.qcap, &n);
     if (blockIdx.x == 0 && threadIdx.x < kMaxPasses) a.pass_ctr[threadIdx.x] = 0u;
     if (!ok || n == 0) return;
-    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    const int tsz = sort_tile(n, a.max_tiles);
+    const int64_t ntiles = (n + tsz - 1) / tsz;
     const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int p = 0; p < a.npass; ++p) {
@@ -1742,24 +1752,26 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const GatherArgs
         if (s_h[i]) atomicAdd(&a.hist[i], s_h[i]);
 }
 
-// One stable LSD radix pass over the packed events (onesweep scheme).
-template <bool FINAL>
-__global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
-    __shared__ uint32_t s_key[kSortTile];
-    __shared__ uint32_t s_val[kSortTile];
-    __shared__ uint32_t s_wcnt[kSortThreads / kWave][kDigits];
+// LDS of a radix pass workgroup (sized for the large tiles).
+struct PassLds {
+    uint32_t key[kSortTile];
+    uint32_t val[kSortTile];
+    uint32_t wcnt[kSortThreads / kWave][kDigits];
     // per wave and digit: the lanes holding that digit in the current item
     // (OR-ed in, read back, cleared; a wave's LDS operations run in order)
-    __shared__ unsigned long long s_peer[kSortThreads / kWave][kDigits];
-    __shared__ uint32_t s_lstart[kDigits];
-    __shared__ uint32_t s_gbase[kDigits];
-    __shared__ uint32_t s_doff[kDigits];
-    __shared__ uint32_t s_wsum[kSortThreads / kWave];
-    __shared__ int64_t s_tile;
+    unsigned long long peer[kSortThreads / kWave][kDigits];
+    uint32_t lstart[kDigits];
+    uint32_t gbase[kDigits];
+    uint32_t doff[kDigits];
+    uint32_t wsum[kSortThreads / kWave];
+    int64_t tile;
+};
 
-    int64_t n;
-    if (!step_fits(a.hdr, a.scratch_cap, a.qcap, &n) || n == 0) return;
-    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+// The tiles of one pass, ITEMS items per thread.
+template <bool FINAL, int ITEMS>
+__device__ __forceinline__ void pass_tiles(const PassArgs& a, int64_t n, PassLds& L) {
+    constexpr int TILE = kSortThreads * ITEMS;
+    const int64_t ntiles = (n + TILE - 1) / TILE;
     // tiles go to workgroups by ticket, so any number of them covers every
     // tile: workgroups past the tile count leave at once (small launches,
     // e.g. one frame, then do not pay for a full grid)
@@ -1771,33 +1783,33 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
     const uint32_t shift = (uint32_t)a.shift;
     const uint32_t dmask = kDigits - 1;
     const int64_t tailm = a.hdr->tail % a.qcap;
-    for (int i = lane; i < kDigits; i += kWave) s_peer[w][i] = 0ull;
+    for (int i = lane; i < kDigits; i += kWave) L.peer[w][i] = 0ull;
 
     // exclusive scan of the global digit counts: each digit's first slot
     {
         const uint32_t c = a.hist[tid];
         const int incl = wave_incl_scan((int)c);
-        if (lane == kWave - 1) s_wsum[w] = (uint32_t)incl;
+        if (lane == kWave - 1) L.wsum[w] = (uint32_t)incl;
         __syncthreads();
         uint32_t off = 0;
-        for (int i = 0; i < w; ++i) off += s_wsum[i];
-        s_doff[tid] = off + (uint32_t)incl - c;
+        for (int i = 0; i < w; ++i) off += L.wsum[i];
+        L.doff[tid] = off + (uint32_t)incl - c;
         __syncthreads();
     }
 
     for (;;) {
-        if (tid == 0) s_tile = (int64_t)atomicAdd(a.tile_ctr, 1u);
+        if (tid == 0) L.tile = (int64_t)atomicAdd(a.tile_ctr, 1u);
         __syncthreads();
-        const int64_t tile = s_tile;
+        const int64_t tile = L.tile;
         __syncthreads();
         if (tile >= ntiles) break;
-        const int64_t base = tile * kSortTile;
+        const int64_t base = tile * TILE;
 
-        uint32_t key[kSortItems], val[kSortItems], rank[kSortItems];
+        uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
+        for (int i = 0; i < ITEMS; ++i) {
             // (past the end: item 0 is read, which always exists, and dropped)
-            const int64_t e = base + w * (kWave * kSortItems) + i * kWave + lane;
+            const int64_t e = base + w * (kWave * ITEMS) + i * kWave + lane;
             const bool v = e < n;
             const int64_t ec = v ? e : 0;
             const uint32_t k = a.kin[ec], x = a.vin[ec];
@@ -1805,26 +1817,26 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
             val[i] = v ? x : 0u;
         }
 #pragma unroll
-        for (int i = 0; i < kDigits / kWave; ++i) s_wcnt[w][lane + i * kWave] = 0u;
+        for (int i = 0; i < kDigits / kWave; ++i) L.wcnt[w][lane + i * kWave] = 0u;
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
-            const int64_t e = base + w * (kWave * kSortItems) + i * kWave + lane;
+        for (int i = 0; i < ITEMS; ++i) {
+            const int64_t e = base + w * (kWave * ITEMS) + i * kWave + lane;
             const bool v = e < n;
             const uint32_t d = (key[i] >> shift) & dmask;
             // lanes holding the same digit
-            if (v) atomicOr(&s_peer[w][d], 1ull << lane);
+            if (v) atomicOr(&L.peer[w][d], 1ull << lane);
             __builtin_amdgcn_wave_barrier();
-            const uint64_t peers = v ? s_peer[w][d] : 0ull;
+            const uint64_t peers = v ? L.peer[w][d] : 0ull;
             __builtin_amdgcn_wave_barrier();
-            if (v) s_peer[w][d] = 0ull;
+            if (v) L.peer[w][d] = 0ull;
             uint32_t prior = 0;
-            if (v) prior = s_wcnt[w][d];
+            if (v) prior = L.wcnt[w][d];
             __builtin_amdgcn_wave_barrier();
             rank[i] = prior + (uint32_t)__popcll(peers & lt);
             if (v && lane == 63 - __clzll((long long)peers))
-                s_wcnt[w][d] = prior + (uint32_t)__popcll(peers);
+                L.wcnt[w][d] = prior + (uint32_t)__popcll(peers);
             __builtin_amdgcn_wave_barrier();
         }
         __syncthreads();
@@ -1835,19 +1847,19 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
             uint32_t tot = 0;
 #pragma unroll
             for (int i = 0; i < kSortThreads / kWave; ++i) {
-                c[i] = s_wcnt[i][d];
-                s_wcnt[i][d] = tot;
+                c[i] = L.wcnt[i][d];
+                L.wcnt[i][d] = tot;
                 tot += c[i];
             }
             uint32_t* st = a.status + tile * kDigits + d;
             atomic_store_u32(st, ((tile == 0 ? kInc : kAgg) << 30) | tot);
             // local exclusive start of digit d within the tile
             const int incl = wave_incl_scan((int)tot);
-            if (lane == kWave - 1) s_wsum[w] = (uint32_t)incl;
+            if (lane == kWave - 1) L.wsum[w] = (uint32_t)incl;
             __syncthreads();
             uint32_t off = 0;
-            for (int i = 0; i < w; ++i) off += s_wsum[i];
-            s_lstart[d] = off + (uint32_t)incl - tot;
+            for (int i = 0; i < w; ++i) off += L.wsum[i];
+            L.lstart[d] = off + (uint32_t)incl - tot;
             // look back over earlier tiles for digit d
             uint32_t excl = 0;
             if (tile > 0) {
@@ -1893,37 +1905,37 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
                 }
                 atomic_store_u32(st, (kInc << 30) | (excl + tot));
             }
-            s_gbase[d] = s_doff[d] + excl;
+            L.gbase[d] = L.doff[d] + excl;
         }
         __syncthreads();
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
-            const int64_t e = base + w * (kWave * kSortItems) + i * kWave + lane;
+        for (int i = 0; i < ITEMS; ++i) {
+            const int64_t e = base + w * (kWave * ITEMS) + i * kWave + lane;
             if (e < n) {
                 const uint32_t d = (key[i] >> shift) & dmask;
-                const uint32_t pos = s_lstart[d] + s_wcnt[w][d] + rank[i];
-                if (pos < (uint32_t)kSortTile) {
-                    s_key[pos] = key[i];
-                    s_val[pos] = val[i];
+                const uint32_t pos = L.lstart[d] + L.wcnt[w][d] + rank[i];
+                if (pos < (uint32_t)TILE) {
+                    L.key[pos] = key[i];
+                    L.val[pos] = val[i];
                 }
             }
         }
         __syncthreads();
-        const int cnt = (int)((n - base) < kSortTile ? (n - base) : kSortTile);
+        const int cnt = (int)((n - base) < TILE ? (n - base) : TILE);
         // every item of the thread is read first (and, in the last pass, its
         // environment's record), so that the loads overlap; stores follow
-        uint32_t sk[kSortItems], sv[kSortItems];
+        uint32_t sk[ITEMS], sv[ITEMS];
 #pragma unroll
-        for (int i = 0; i < kSortItems; ++i) {
+        for (int i = 0; i < ITEMS; ++i) {
             const int j = tid + i * kSortThreads;
-            sk[i] = j < cnt ? s_key[j] : 0u;
-            sv[i] = j < cnt ? s_val[j] : 0u;
+            sk[i] = j < cnt ? L.key[j] : 0u;
+            sv[i] = j < cnt ? L.val[j] : 0u;
         }
         // destination of item i (-1 past the tile's end)
         auto dest = [&](int i) -> int64_t {
             const int j = tid + i * kSortThreads;
             const uint32_t d = (sk[i] >> shift) & dmask;
-            return j < cnt ? (int64_t)s_gbase[d] + (j - (int)s_lstart[d]) : -1;
+            return j < cnt ? (int64_t)L.gbase[d] + (j - (int)L.lstart[d]) : -1;
         };
         if (FINAL) {
             // an environment index outside the table can only come from a
@@ -1970,7 +1982,7 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
                 bool bad = false;
                 auto items = [&](auto flat_c) {
 #pragma unroll
-                    for (int i = 0; i < kSortItems; ++i) {
+                    for (int i = 0; i < ITEMS; ++i) {
                         const int64_t gpos = dest(i);
                         if (gpos < 0 || gpos >= n) continue;  // tail, or a corrupt histogram
                         if ((sk[i] >> a.key_tbits) != 0u) {   // corrupt key
@@ -1993,10 +2005,10 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
                     items(std::false_type{});
                 if (bad) atomicOr(&a.hdr->internal_err, kErrWait);
             } else {
-                uint32_t ew0[kSortItems], ewd[kSortItems];
+                uint32_t ew0[ITEMS], ewd[ITEMS];
                 bool bad = false;
 #pragma unroll
-                for (int i = 0; i < kSortItems; ++i) {
+                for (int i = 0; i < ITEMS; ++i) {
                     const uint32_t env = a.key_pbits ? 0u : (sk[i] >> a.key_tbits);
                     const bool v = tid + i * kSortThreads < cnt;
                     const bool ok = env < (uint32_t)a.n_env;
@@ -2006,7 +2018,7 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
                 }
                 if (bad) atomicOr(&a.hdr->internal_err, kErrWait);
 #pragma unroll
-                for (int i = 0; i < kSortItems; ++i) {
+                for (int i = 0; i < ITEMS; ++i) {
                     const int64_t gpos = dest(i);
                     if (gpos < 0 || gpos >= n) continue;  // tail, or a corrupt histogram
                     if (ew0[i] == 0xFFFFFFFFu) continue;  // corrupt key
@@ -2020,7 +2032,7 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < kSortItems; ++i) {
+            for (int i = 0; i < ITEMS; ++i) {
                 const int64_t gpos = dest(i);
                 if (gpos < 0 || gpos >= n) continue;
                 a.kout[gpos] = sk[i];
@@ -2029,6 +2041,20 @@ __global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
         }
         __syncthreads();
     }
+}
+
+// One stable LSD radix pass over the packed events (onesweep scheme).  A
+// launch of few events (a frame or two) is cut into small tiles, so that
+// more workgroups share it (see sort_tile).
+template <bool FINAL>
+__global__ __launch_bounds__(kSortThreads) void pass_kernel(const PassArgs a) {
+    __shared__ PassLds L;
+    int64_t n;
+    if (!step_fits(a.hdr, a.scratch_cap, a.qcap, &n) || n == 0) return;
+    if (sort_tile(n, a.max_tiles) == kSmallSortTile)
+        pass_tiles<FINAL, kSmallSortItems>(a, n, L);
+    else
+        pass_tiles<FINAL, kSortItems>(a, n, L);
 }
 
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC 2011): ten rounds, each two
@@ -2314,7 +2340,8 @@ __global__ void prep_kernel(const PrepArgs a) {
     const bool ok = step_fits(a.hdr, a.scratch_cap, a.qcap, &n);
     if (blockIdx.x == 0 && threadIdx.x < kMaxPasses) a.pass_ctr[threadIdx.x] = 0u;
     if (!ok || n == 0) return;
-    const int64_t ntiles = (n + kSortTile - 1) / kSortTile;
+    const int tsz = sort_tile(n, a.max_tiles);
+    const int64_t ntiles = (n + tsz - 1) / tsz;
     const int64_t gsz = (int64_t)gridDim.x * blockDim.x;
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (int p = 0; p < a.npass; ++p) {

@@ -443,6 +443,7 @@ void build_launch(nsim_ev* h, LaunchSet& L, const float* frames,
         pa.status = sc.pass_status + (int64_t)p * sc.max_tiles * nsim::kDigits;
         pa.tile_ctr = sc.pass_ctr + p;
         pa.hdr = h->hdr;
+        pa.max_tiles = sc.max_tiles;
         pa.scratch_cap = sc.scap;
     }
 
@@ -877,6 +878,7 @@ int enqueue_atomic(nsim_ev* h, const float* frame, const int64_t* t_us, int64_t 
             pa.hist = h->hist + p * nsim::kDigits;
             pa.status = h->pass_status + (int64_t)p * h->max_sort_tiles * nsim::kDigits;
             pa.tile_ctr = h->pass_ctr + p;
+            pa.max_tiles = h->max_sort_tiles;
             NSIM_HIP(h, nsim::launch_pass(pa, h->stream));
         }
     }
