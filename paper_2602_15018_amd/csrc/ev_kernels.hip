@@ -1686,12 +1686,15 @@ __device__ __forceinline__ int sort_tile(int64_t n, int64_t max_tiles) {
 // frame or a few, 16 for the long segments of many frames (fewer rounds,
 // each waiting once for its loads).
 // Every workgroup adds its digit counts to the global histogram with
-// atomics on the same few hundred words; when segments are many and short
-// (one-frame batches) wide workgroups keep those flushes few, otherwise
-// 256-thread workgroups keep the chip full.
+// atomics on the same few hundred words: short segments (launches of a few
+// frames) go to at most kGatherShortBlocks wide workgroups, very many
+// segments to at most kGatherWideBlocks, which keeps those flushes few;
+// long segments go to 256-thread workgroups, one segment per group, which
+// keep the chip full.
 constexpr int kGatherGroup = 16;
 constexpr int kGatherMaxBlocks = 2048;    // 256-thread workgroups
 constexpr int kGatherWideBlocks = 512;    // 1024-thread workgroups
+constexpr int kGatherShortBlocks = 128;   // 1024-thread workgroups, short segments
 
 template <int kGatherThreads, int U>
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const GatherArgs a) {
@@ -2579,16 +2582,14 @@ hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
 hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
     constexpr int64_t kGroups = 256 / kGatherGroup;
     const int64_t want = (a.nwaves + kGroups - 1) / kGroups;
-    if (want > kGatherMaxBlocks) {
+    if (want > kGatherMaxBlocks || !a.long_segments) {
         const int64_t wide = (a.nwaves + 4 * kGroups - 1) / (4 * kGroups);
-        const int blocks = (int)std::min<int64_t>(kGatherWideBlocks, wide);
+        const int cap = want > kGatherMaxBlocks ? kGatherWideBlocks : kGatherShortBlocks;
+        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(cap, wide));
         hipLaunchKernelGGL((gather_kernel<1024, 4>), dim3(blocks), dim3(1024), 0, s, a);
     } else {
         const int blocks = (int)std::max<int64_t>(1, want);
-        if (a.long_segments)
-            hipLaunchKernelGGL((gather_kernel<256, 16>), dim3(blocks), dim3(256), 0, s, a);
-        else
-            hipLaunchKernelGGL((gather_kernel<256, 4>), dim3(blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((gather_kernel<256, 16>), dim3(blocks), dim3(256), 0, s, a);
     }
     return hipGetLastError();
 }
