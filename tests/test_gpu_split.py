@@ -8,8 +8,10 @@ set; both must give the same stream, entry for entry, and match the oracle
 output in (t, y, x) order).  The cases exercise what is particular to the
 split: record windows of a wave larger than one round of the timestamp
 kernel (256 records), records whose count needed FP64, staging segments
-given from the pool, launches of 16, 17 and 100 frames, and refractory
-suppression across the windows of a pixel.
+given from the pool, launches of 16, 17 and 100 frames, refractory
+suppression across the windows of a pixel, and samples a few ulps from the
+levels that decide one, two or three crossings (the walk's FP32 decision for
+exactly two crossings against the fused kernel's FP64 level walk).
 """
 import numpy as np
 import pytest
@@ -153,3 +155,62 @@ def test_split_equals_fused_full_hd_stream():
     assert out[0][0].numel() > 10 ** 8
     for a, b in zip(out[0], out[1]):
         assert torch.equal(a, b)
+
+
+def _boundary_frames(F, H, W, seed):
+    """Frames whose every sample sits within a few float32 ulps of a lattice
+    level: each frame moves the pixel by one, two or three thresholds up or
+    down from its reference and lands just above the last level crossed or
+    just below the next one, so the walk's FP32 decisions for one and for
+    two crossings meet the guard band on both sides of levels 1, 2 and 3."""
+    rng = np.random.default_rng(seed)
+    eps = 1e-3
+    cp = rng.uniform(0.1, 0.3, size=(H, W)).astype(np.float32)
+    cn = rng.uniform(0.1, 0.3, size=(H, W)).astype(np.float32)
+    fr = np.empty((F, H, W), np.float32)
+    fr[0] = rng.uniform(0.2, 0.6, size=(H, W)).astype(np.float32)
+    R = np.log(fr[0].astype(np.float64) + eps)   # the reference level (log domain)
+    c_up, c_dn = cp.astype(np.float64), cn.astype(np.float64)
+    for k in range(1, F):
+        up = rng.random((H, W)) < 0.5
+        # keep intensities inside (0, 1.5): turn round near the ends
+        up = np.where(R > np.log(0.9), False, np.where(R < np.log(0.05), True, up))
+        m = rng.choice([1, 2, 2, 3, 3], size=(H, W))
+        below_next = rng.random((H, W)) < 0.5      # just below level m + 1, else just above level m
+        step = np.where(up, c_up, -c_dn)
+        lv = R + np.where(below_next, m + 1, m) * step
+        x = (np.exp(lv) - eps).astype(np.float32)
+        j = rng.integers(0, 4, size=(H, W)).astype(np.float32)
+        # ulps towards the side of the boundary the frame is meant to land on
+        inward = np.where(up == below_next, -np.inf, np.inf).astype(np.float32)
+        for _ in range(3):
+            x = np.where(j > 0, np.nextafter(x, inward), x)
+            j -= 1
+        fr[k] = x
+        R = R + m * step        # (the oracle's own reference may differ by a level)
+    return fr, cp, cn
+
+
+@pytest.mark.parametrize("log_input", [False, True])
+def test_split_two_crossings_at_level_boundaries(log_input):
+    """The walk decides frames with exactly two crossings in FP32 from the
+    guarded thresholds of levels 2 and 3; the fused kernel takes them to the
+    FP64 level walk.  With samples a few ulps from levels 1 to 4 both must
+    give the oracle's stream, and the same stream."""
+    _dev()
+    F, H, W = 48, 4, 128
+    fr, cp, cn = _boundary_frames(F, H, W, seed=77 + log_input)
+    if log_input:
+        fr = np.log(fr.astype(np.float64) + 1e-3).astype(np.float32)
+    t = 11 + 700 * np.arange(F)
+    kw = dict(c_pos=cp, c_neg=cn, refractory_us=0, input_is_log=log_input)
+    rep, got, ref, st = check_parity(fr, t, W, **kw)
+    assert rep["ok"], rep
+    # the case is exercised: many pixel-frames with exactly two crossings
+    ev = ref["events"]
+    f = np.searchsorted(t, ev.t, side="left")
+    key = (f.astype(np.int64) * H + ev.y.astype(np.int64)) * W + ev.x
+    per = np.bincount(np.unique(key, return_counts=True)[1])
+    assert len(per) > 3 and per[2] > 2000 and per[3] > 1000, per
+    fused, _ = gpu_run(fr, t, fused_step=True, **kw)
+    assert exact_equal(got, fused)
