@@ -1808,240 +1808,248 @@ __device__ __forceinline__ void pass_tiles(const PassArgs& a, int64_t n, PassLds
         if (tile >= ntiles) break;
         const int64_t base = tile * TILE;
 
-        uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            // (past the end: item 0 is read, which always exists, and dropped)
-            const int64_t e = base + w * (kWave * ITEMS) + i * kWave + lane;
-            const bool v = e < n;
-            const int64_t ec = v ? e : 0;
-            const uint32_t k = a.kin[ec], x = a.vin[ec];
-            key[i] = v ? k : 0u;
-            val[i] = v ? x : 0u;
-        }
-#pragma unroll
-        for (int i = 0; i < kDigits / kWave; ++i) L.wcnt[w][lane + i * kWave] = 0u;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-        __builtin_amdgcn_wave_barrier();
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const int64_t e = base + w * (kWave * ITEMS) + i * kWave + lane;
-            const bool v = e < n;
-            const uint32_t d = (key[i] >> shift) & dmask;
-            // lanes holding the same digit
-            if (v) atomicOr(&L.peer[w][d], 1ull << lane);
-            __builtin_amdgcn_wave_barrier();
-            const uint64_t peers = v ? L.peer[w][d] : 0ull;
-            __builtin_amdgcn_wave_barrier();
-            if (v) L.peer[w][d] = 0ull;
-            uint32_t prior = 0;
-            if (v) prior = L.wcnt[w][d];
-            __builtin_amdgcn_wave_barrier();
-            rank[i] = prior + (uint32_t)__popcll(peers & lt);
-            if (v && lane == 63 - __clzll((long long)peers))
-                L.wcnt[w][d] = prior + (uint32_t)__popcll(peers);
-            __builtin_amdgcn_wave_barrier();
-        }
-        __syncthreads();
-        // per digit: tile count, wave prefixes, local start, look-back
-        {
-            const int d = tid;
-            uint32_t c[kSortThreads / kWave];
-            uint32_t tot = 0;
-#pragma unroll
-            for (int i = 0; i < kSortThreads / kWave; ++i) {
-                c[i] = L.wcnt[i][d];
-                L.wcnt[i][d] = tot;
-                tot += c[i];
+        // (a full tile, as all but the last are, needs no per-item bounds tests)
+        auto tile_body = [&](auto full_c) {
+            constexpr bool FULL = decltype(full_c)::value;
+            uint32_t key[ITEMS], val[ITEMS], rank[ITEMS];
+    #pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                // (past the end: item 0 is read, which always exists, and dropped)
+                const int64_t e = base + w * (kWave * ITEMS) + i * kWave + lane;
+                const bool v = FULL || e < n;
+                const int64_t ec = v ? e : 0;
+                const uint32_t k = a.kin[ec], x = a.vin[ec];
+                key[i] = v ? k : 0u;
+                val[i] = v ? x : 0u;
             }
-            uint32_t* st = a.status + tile * kDigits + d;
-            atomic_store_u32(st, ((tile == 0 ? kInc : kAgg) << 30) | tot);
-            // local exclusive start of digit d within the tile
-            const int incl = wave_incl_scan((int)tot);
-            if (lane == kWave - 1) L.wsum[w] = (uint32_t)incl;
+    #pragma unroll
+            for (int i = 0; i < kDigits / kWave; ++i) L.wcnt[w][lane + i * kWave] = 0u;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            __builtin_amdgcn_wave_barrier();
+    #pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int64_t e = base + w * (kWave * ITEMS) + i * kWave + lane;
+                const bool v = FULL || e < n;
+                const uint32_t d = (key[i] >> shift) & dmask;
+                // lanes holding the same digit
+                if (v) atomicOr(&L.peer[w][d], 1ull << lane);
+                __builtin_amdgcn_wave_barrier();
+                const uint64_t peers = v ? L.peer[w][d] : 0ull;
+                __builtin_amdgcn_wave_barrier();
+                if (v) L.peer[w][d] = 0ull;
+                uint32_t prior = 0;
+                if (v) prior = L.wcnt[w][d];
+                __builtin_amdgcn_wave_barrier();
+                rank[i] = prior + (uint32_t)__popcll(peers & lt);
+                if (v && lane == 63 - __clzll((long long)peers))
+                    L.wcnt[w][d] = prior + (uint32_t)__popcll(peers);
+                __builtin_amdgcn_wave_barrier();
+            }
             __syncthreads();
-            uint32_t off = 0;
-            for (int i = 0; i < w; ++i) off += L.wsum[i];
-            L.lstart[d] = off + (uint32_t)incl - tot;
-            // look back over earlier tiles for digit d
-            uint32_t excl = 0;
-            if (tile > 0) {
-                // a window of kLookBack predecessors is read at once and
-                // walked newest first; tile 0 always publishes an inclusive
-                // prefix, so every walk ends there at the latest
-                int64_t j = tile - 1;
-                uint32_t spins = 0;
-                for (;;) {
-                    uint32_t sw[kLookBack];
-#pragma unroll
-                    for (int i = 0; i < kLookBack; ++i)
-                        sw[i] = (j - i >= 0)
-                                    ? atomic_load_u32(a.status + (j - i) * kDigits + d)
-                                    : (kInc << 30);
-                    bool live = true, done = false;
-                    int adv = kLookBack;
-#pragma unroll
-                    for (int i = 0; i < kLookBack; ++i) {
-                        if (live) {
-                            const uint32_t flag = sw[i] >> 30;
-                            if (flag == 0u) {
-                                adv = i;
-                                live = false;
-                            } else {
-                                excl += sw[i] & 0x3FFFFFFFu;
-                                if (flag == kInc) {
-                                    done = true;
+            // per digit: tile count, wave prefixes, local start, look-back
+            {
+                const int d = tid;
+                uint32_t c[kSortThreads / kWave];
+                uint32_t tot = 0;
+    #pragma unroll
+                for (int i = 0; i < kSortThreads / kWave; ++i) {
+                    c[i] = L.wcnt[i][d];
+                    L.wcnt[i][d] = tot;
+                    tot += c[i];
+                }
+                uint32_t* st = a.status + tile * kDigits + d;
+                atomic_store_u32(st, ((tile == 0 ? kInc : kAgg) << 30) | tot);
+                // local exclusive start of digit d within the tile
+                const int incl = wave_incl_scan((int)tot);
+                if (lane == kWave - 1) L.wsum[w] = (uint32_t)incl;
+                __syncthreads();
+                uint32_t off = 0;
+                for (int i = 0; i < w; ++i) off += L.wsum[i];
+                L.lstart[d] = off + (uint32_t)incl - tot;
+                // look back over earlier tiles for digit d
+                uint32_t excl = 0;
+                if (tile > 0) {
+                    // a window of kLookBack predecessors is read at once and
+                    // walked newest first; tile 0 always publishes an inclusive
+                    // prefix, so every walk ends there at the latest
+                    int64_t j = tile - 1;
+                    uint32_t spins = 0;
+                    for (;;) {
+                        uint32_t sw[kLookBack];
+    #pragma unroll
+                        for (int i = 0; i < kLookBack; ++i)
+                            sw[i] = (j - i >= 0)
+                                        ? atomic_load_u32(a.status + (j - i) * kDigits + d)
+                                        : (kInc << 30);
+                        bool live = true, done = false;
+                        int adv = kLookBack;
+    #pragma unroll
+                        for (int i = 0; i < kLookBack; ++i) {
+                            if (live) {
+                                const uint32_t flag = sw[i] >> 30;
+                                if (flag == 0u) {
+                                    adv = i;
                                     live = false;
+                                } else {
+                                    excl += sw[i] & 0x3FFFFFFFu;
+                                    if (flag == kInc) {
+                                        done = true;
+                                        live = false;
+                                    }
                                 }
                             }
                         }
-                    }
-                    if (done) break;
-                    j -= adv;
-                    if (adv < kLookBack) {   // predecessor j not published yet
-                        if (++spins > kSpinLimit) {
-                            atomicOr(&a.hdr->internal_err, kErrWait);
-                            break;
+                        if (done) break;
+                        j -= adv;
+                        if (adv < kLookBack) {   // predecessor j not published yet
+                            if (++spins > kSpinLimit) {
+                                atomicOr(&a.hdr->internal_err, kErrWait);
+                                break;
+                            }
+                            __builtin_amdgcn_s_sleep(1);
                         }
-                        __builtin_amdgcn_s_sleep(1);
+                    }
+                    atomic_store_u32(st, (kInc << 30) | (excl + tot));
+                }
+                L.gbase[d] = L.doff[d] + excl;
+            }
+            __syncthreads();
+    #pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int64_t e = base + w * (kWave * ITEMS) + i * kWave + lane;
+                if (FULL || e < n) {
+                    const uint32_t d = (key[i] >> shift) & dmask;
+                    const uint32_t pos = L.lstart[d] + L.wcnt[w][d] + rank[i];
+                    if (pos < (uint32_t)TILE) {
+                        L.key[pos] = key[i];
+                        L.val[pos] = val[i];
                     }
                 }
-                atomic_store_u32(st, (kInc << 30) | (excl + tot));
             }
-            L.gbase[d] = L.doff[d] + excl;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const int64_t e = base + w * (kWave * ITEMS) + i * kWave + lane;
-            if (e < n) {
-                const uint32_t d = (key[i] >> shift) & dmask;
-                const uint32_t pos = L.lstart[d] + L.wcnt[w][d] + rank[i];
-                if (pos < (uint32_t)TILE) {
-                    L.key[pos] = key[i];
-                    L.val[pos] = val[i];
-                }
+            __syncthreads();
+            const int cnt = FULL ? TILE : (int)((n - base) < TILE ? (n - base) : TILE);
+            // every item of the thread is read first (and, in the last pass, its
+            // environment's record), so that the loads overlap; stores follow
+            uint32_t sk[ITEMS], sv[ITEMS];
+    #pragma unroll
+            for (int i = 0; i < ITEMS; ++i) {
+                const int j = tid + i * kSortThreads;
+                sk[i] = j < cnt ? L.key[j] : 0u;
+                sv[i] = j < cnt ? L.val[j] : 0u;
             }
-        }
-        __syncthreads();
-        const int cnt = (int)((n - base) < TILE ? (n - base) : TILE);
-        // every item of the thread is read first (and, in the last pass, its
-        // environment's record), so that the loads overlap; stores follow
-        uint32_t sk[ITEMS], sv[ITEMS];
-#pragma unroll
-        for (int i = 0; i < ITEMS; ++i) {
-            const int j = tid + i * kSortThreads;
-            sk[i] = j < cnt ? L.key[j] : 0u;
-            sv[i] = j < cnt ? L.val[j] : 0u;
-        }
-        // destination of item i (-1 past the tile's end)
-        auto dest = [&](int i) -> int64_t {
-            const int j = tid + i * kSortThreads;
-            const uint32_t d = (sk[i] >> shift) & dmask;
-            return j < cnt ? (int64_t)L.gbase[d] + (j - (int)L.lstart[d]) : -1;
-        };
-        if (FINAL) {
-            // an environment index outside the table can only come from a
-            // corrupt key: the item is dropped and the step fails
-            // (a launch that does not wrap the queue, with fewer than 2^29
-            // events, writes through uniform bases at the tail with 32-bit
-            // byte offsets)
-            const bool flat = tailm + n <= a.qcap && n < ((int64_t)1 << 29);
-            char* const tb = reinterpret_cast<char*>(a.t_out + tailm);
-            char* const xb = reinterpret_cast<char*>(a.x_out + tailm);
-            char* const yb = reinterpret_cast<char*>(a.y_out + tailm);
-            char* const pb = reinterpret_cast<char*>(a.p_out + tailm);
-            auto put = [&](auto flat_c, int64_t gpos, uint32_t skey, uint32_t sval,
-                           uint32_t y, uint32_t x) {
-                const uint32_t toff = a.key_pbits ? (skey >> a.key_pbits)
-                                                  : (skey & ((1u << a.key_tbits) - 1u));
-                const int64_t t = a.T0 + (int64_t)toff;
-                const int8_t p = (sval & 1u) ? (int8_t)1 : (int8_t)-1;
-                if constexpr (decltype(flat_c)::value) {
-                    const uint32_t g = (uint32_t)gpos;
-                    *reinterpret_cast<int64_t*>(tb + 8u * g) = t;
-                    *reinterpret_cast<uint16_t*>(xb + 2u * g) = (uint16_t)x;
-                    *reinterpret_cast<uint16_t*>(yb + 2u * g) = (uint16_t)y;
-                    *reinterpret_cast<int8_t*>(pb + g) = p;
-                } else {
-                    int64_t r = tailm + gpos;
-                    if (r >= a.qcap) r -= a.qcap;
-                    a.t_out[r] = t;
-                    a.x_out[r] = (uint16_t)x;
-                    a.y_out[r] = (uint16_t)y;
-                    a.p_out[r] = p;
-                }
+            // destination of item i (-1 past the tile's end)
+            auto dest = [&](int i) -> int64_t {
+                const int j = tid + i * kSortThreads;
+                const uint32_t d = (sk[i] >> shift) & dmask;
+                return j < cnt ? (int64_t)L.gbase[d] + (j - (int)L.lstart[d]) : -1;
             };
-            if (a.n_env == 1 && !a.key_pbits) {
-                // one environment: its record once, and the row of a pixel
-                // index from the reciprocal of the width: px * RN(1/width)
-                // in FP64 is within 2^-20 of px / width (px < 2^32, two
-                // roundings of 2^-53), and a quotient that is not an integer
-                // is at least 1/width >= 2^-16 below the next one, so the
-                // truncation is the quotient or, for an exact one, one less
-                const EnvRec er = a.envs[0];
-                const uint32_t wd = (uint32_t)er.width;
-                const uint32_t px0 = (uint32_t)er.wave0 * kWave;
-                bool bad = false;
-                auto items = [&](auto flat_c) {
-#pragma unroll
+            if (FINAL) {
+                // an environment index outside the table can only come from a
+                // corrupt key: the item is dropped and the step fails
+                // (a launch that does not wrap the queue, with fewer than 2^29
+                // events, writes through uniform bases at the tail with 32-bit
+                // byte offsets)
+                const bool flat = tailm + n <= a.qcap && n < ((int64_t)1 << 29);
+                char* const tb = reinterpret_cast<char*>(a.t_out + tailm);
+                char* const xb = reinterpret_cast<char*>(a.x_out + tailm);
+                char* const yb = reinterpret_cast<char*>(a.y_out + tailm);
+                char* const pb = reinterpret_cast<char*>(a.p_out + tailm);
+                auto put = [&](auto flat_c, int64_t gpos, uint32_t skey, uint32_t sval,
+                               uint32_t y, uint32_t x) {
+                    const uint32_t toff = a.key_pbits ? (skey >> a.key_pbits)
+                                                      : (skey & ((1u << a.key_tbits) - 1u));
+                    const int64_t t = a.T0 + (int64_t)toff;
+                    const int8_t p = (sval & 1u) ? (int8_t)1 : (int8_t)-1;
+                    if constexpr (decltype(flat_c)::value) {
+                        const uint32_t g = (uint32_t)gpos;
+                        *reinterpret_cast<int64_t*>(tb + 8u * g) = t;
+                        *reinterpret_cast<uint16_t*>(xb + 2u * g) = (uint16_t)x;
+                        *reinterpret_cast<uint16_t*>(yb + 2u * g) = (uint16_t)y;
+                        *reinterpret_cast<int8_t*>(pb + g) = p;
+                    } else {
+                        int64_t r = tailm + gpos;
+                        if (r >= a.qcap) r -= a.qcap;
+                        a.t_out[r] = t;
+                        a.x_out[r] = (uint16_t)x;
+                        a.y_out[r] = (uint16_t)y;
+                        a.p_out[r] = p;
+                    }
+                };
+                if (a.n_env == 1 && !a.key_pbits) {
+                    // one environment: its record once, and the row of a pixel
+                    // index from the reciprocal of the width: px * RN(1/width)
+                    // in FP64 is within 2^-20 of px / width (px < 2^32, two
+                    // roundings of 2^-53), and a quotient that is not an integer
+                    // is at least 1/width >= 2^-16 below the next one, so the
+                    // truncation is the quotient or, for an exact one, one less
+                    const EnvRec er = a.envs[0];
+                    const uint32_t wd = (uint32_t)er.width;
+                    const uint32_t px0 = (uint32_t)er.wave0 * kWave;
+                    bool bad = false;
+                    auto items = [&](auto flat_c) {
+    #pragma unroll
+                        for (int i = 0; i < ITEMS; ++i) {
+                            const int64_t gpos = dest(i);
+                            if (gpos < 0 || gpos >= n) continue;  // tail, or a corrupt histogram
+                            if ((sk[i] >> a.key_tbits) != 0u) {   // corrupt key
+                                bad = true;
+                                continue;
+                            }
+                            const uint32_t px = (sv[i] >> 1) - px0;
+                            uint32_t y = (uint32_t)((double)px * er.inv_width);
+                            uint32_t x = px - y * wd;
+                            if (x >= wd) {
+                                ++y;
+                                x -= wd;
+                            }
+                            put(flat_c, gpos, sk[i], sv[i], y, x);
+                        }
+                    };
+                    if (flat)
+                        items(std::true_type{});
+                    else
+                        items(std::false_type{});
+                    if (bad) atomicOr(&a.hdr->internal_err, kErrWait);
+                } else {
+                    uint32_t ew0[ITEMS], ewd[ITEMS];
+                    bool bad = false;
+    #pragma unroll
+                    for (int i = 0; i < ITEMS; ++i) {
+                        const uint32_t env = a.key_pbits ? 0u : (sk[i] >> a.key_tbits);
+                        const bool v = tid + i * kSortThreads < cnt;
+                        const bool ok = env < (uint32_t)a.n_env;
+                        bad = bad || (v && !ok);
+                        ew0[i] = (v && ok) ? (uint32_t)a.envs[env].wave0 : 0xFFFFFFFFu;
+                        ewd[i] = (v && ok) ? (uint32_t)a.envs[env].width : 1u;
+                    }
+                    if (bad) atomicOr(&a.hdr->internal_err, kErrWait);
+    #pragma unroll
                     for (int i = 0; i < ITEMS; ++i) {
                         const int64_t gpos = dest(i);
                         if (gpos < 0 || gpos >= n) continue;  // tail, or a corrupt histogram
-                        if ((sk[i] >> a.key_tbits) != 0u) {   // corrupt key
-                            bad = true;
-                            continue;
-                        }
-                        const uint32_t px = (sv[i] >> 1) - px0;
-                        uint32_t y = (uint32_t)((double)px * er.inv_width);
-                        uint32_t x = px - y * wd;
-                        if (x >= wd) {
-                            ++y;
-                            x -= wd;
-                        }
-                        put(flat_c, gpos, sk[i], sv[i], y, x);
+                        if (ew0[i] == 0xFFFFFFFFu) continue;  // corrupt key
+                        const uint32_t px = (sv[i] >> 1) - ew0[i] * kWave;
+                        // px < 2^32 and width <= 65535: the FP64 quotient's floor
+                        // is the integer quotient (its distance to the next
+                        // integer, >= 1/width, exceeds the rounding error)
+                        const uint32_t y = (uint32_t)((double)px / (double)ewd[i]);
+                        put(std::false_type{}, gpos, sk[i], sv[i], y, px - y * ewd[i]);
                     }
-                };
-                if (flat)
-                    items(std::true_type{});
-                else
-                    items(std::false_type{});
-                if (bad) atomicOr(&a.hdr->internal_err, kErrWait);
-            } else {
-                uint32_t ew0[ITEMS], ewd[ITEMS];
-                bool bad = false;
-#pragma unroll
-                for (int i = 0; i < ITEMS; ++i) {
-                    const uint32_t env = a.key_pbits ? 0u : (sk[i] >> a.key_tbits);
-                    const bool v = tid + i * kSortThreads < cnt;
-                    const bool ok = env < (uint32_t)a.n_env;
-                    bad = bad || (v && !ok);
-                    ew0[i] = (v && ok) ? (uint32_t)a.envs[env].wave0 : 0xFFFFFFFFu;
-                    ewd[i] = (v && ok) ? (uint32_t)a.envs[env].width : 1u;
                 }
-                if (bad) atomicOr(&a.hdr->internal_err, kErrWait);
-#pragma unroll
+            } else {
+    #pragma unroll
                 for (int i = 0; i < ITEMS; ++i) {
                     const int64_t gpos = dest(i);
-                    if (gpos < 0 || gpos >= n) continue;  // tail, or a corrupt histogram
-                    if (ew0[i] == 0xFFFFFFFFu) continue;  // corrupt key
-                    const uint32_t px = (sv[i] >> 1) - ew0[i] * kWave;
-                    // px < 2^32 and width <= 65535: the FP64 quotient's floor
-                    // is the integer quotient (its distance to the next
-                    // integer, >= 1/width, exceeds the rounding error)
-                    const uint32_t y = (uint32_t)((double)px / (double)ewd[i]);
-                    put(std::false_type{}, gpos, sk[i], sv[i], y, px - y * ewd[i]);
+                    if (gpos < 0 || gpos >= n) continue;
+                    a.kout[gpos] = sk[i];
+                    a.vout[gpos] = sv[i];
                 }
             }
-        } else {
-#pragma unroll
-            for (int i = 0; i < ITEMS; ++i) {
-                const int64_t gpos = dest(i);
-                if (gpos < 0 || gpos >= n) continue;
-                a.kout[gpos] = sk[i];
-                a.vout[gpos] = sv[i];
-            }
-        }
+        };
+        if (base + TILE <= n)
+            tile_body(std::true_type{});
+        else
+            tile_body(std::false_type{});
         __syncthreads();
     }
 }
