@@ -128,6 +128,9 @@ struct StepArgs {
     // lane leaves at most one record per frame, so rec_cap = 64 * K always
     // suffices.  NULL in fused launches.
     uint32_t* rec_meta;    // lane | frame << 6 | up << 14 | f64 << 15 | n << 16
+                           // | ordinal << 24 (n < 256 when counted in FP32,
+                           // 0 for FP64 records; ordinal: the lane's records
+                           // before this one in the launch, < 256)
     float* rec_I;          // the frame's sample
     float* rec_prev;       // the sample before it
     double* rec_X1;        // level of the first crossing (FP64 records: the

@@ -1039,6 +1039,8 @@ __device__ __forceinline__ void walk_split(const StepArgs& a, Px& q, int& tlast,
 
 // Record meta of the split step (see StepArgs::rec_meta).
 constexpr uint32_t kRmUp = 1u << 14, kRmF64 = 1u << 15;
+static_assert(kFastMaxCross <= 255 && kMaxFramesPerLaunch <= 256,
+              "a record's FP32 count and its lane ordinal take 8 bits each");
 
 // Phase A of one lane's pixel over the launch's frames, records to `seg`
 // (the wave's segment), `nrec` the wave's record count (wave-uniform).
@@ -1059,6 +1061,7 @@ __device__ __forceinline__ void walk_append(const StepArgs& a, Px& q,
     const uint64_t lt = lanemask_lt();
     int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     constexpr int U = kChunk;
+    uint32_t ordinal = 0;   // the lane's records so far (one per frame at most)
     // The wave's record segment: uniform bases and 32-bit byte offsets
     // (a segment holds at most 64 kMaxFramesPerLaunch records).
     char* const rm = reinterpret_cast<char*>(a.rec_meta + seg);
@@ -1120,9 +1123,11 @@ __device__ __forceinline__ void walk_append(const StepArgs& a, Px& q,
             if (n > 0) {
                 const uint32_t at = nrec + (uint32_t)__popcll(wm & lt);
                 const double X1 = up ? q.Xh : q.Xl;
+                // (a count decided in FP32 is below kFastMaxCross: 8 bits)
                 *reinterpret_cast<uint32_t*>(rm + 4u * at) =
                     (uint32_t)lane | ((uint32_t)(kc + u) << 6) | (up ? kRmUp : 0u) |
-                    (f64 ? kRmF64 : 0u) | ((uint32_t)(f64 ? 0 : n) << 16);
+                    (f64 ? kRmF64 : 0u) | ((uint32_t)(f64 ? 0 : n) << 16) | (ordinal << 24);
+                ++ordinal;
                 *reinterpret_cast<float*>(ri + 4u * at) = I;
                 *reinterpret_cast<float*>(rp + 4u * at) = Ip;
                 *reinterpret_cast<double*>(rx + 8u * at) = f64 ? __hiloint2double(0, n) : X1;
@@ -1278,9 +1283,9 @@ __global__ __launch_bounds__(kWave) void stamp_kernel(const StepArgs a) {
     const int64_t cap = slots;
     uint32_t run = (uint32_t)(incl - cross);
     const uint32_t lane_bits = ((uint32_t)lane) << 1;
-    const uint64_t lt = lanemask_lt();
     const int64_t seg = (int64_t)wid * a.rec_cap;
     const int nrec = (int)a.rec_count[wid];
+    int obase = 0;   // the lane's records in earlier windows
     int emitted = 0, f64count = 0;
     int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     constexpr int C = kStampWin / kWave;
@@ -1299,7 +1304,7 @@ __global__ __launch_bounds__(kWave) void stamp_kernel(const StepArgs a) {
                 m = a.rec_meta[at];
                 const double X1 = a.rec_X1[at];
                 const bool f64 = (m & kRmF64) != 0;
-                const uint32_t n = f64 ? (uint32_t)__double2loint(X1) : (m >> 16);
+                const uint32_t n = f64 ? (uint32_t)__double2loint(X1) : ((m >> 16) & 0xFFu);
                 rc.meta = n | (((m >> 6) & 0xFFu) << 21) | ((m & kRmUp) ? (1u << 29) : 0u) |
                           (f64 ? kRecF64 : 0u);
                 rc.w0 = __float_as_uint(a.rec_I[at]);
@@ -1315,22 +1320,18 @@ __global__ __launch_bounds__(kWave) void stamp_kernel(const StepArgs a) {
                 interp_record<LOGIN>(a, rc, up ? cp_o : -cn_o, s_toff);
             }
             if (act) s_rec[i] = rc;
-            uint64_t peers = __ballot(act);
-#pragma unroll
-            for (int b = 0; b < 6; ++b) {
-                const bool bit = ((owner >> b) & 1) != 0;
-                const uint64_t bb = __ballot(bit);
-                peers &= bit ? bb : ~bb;
-            }
-            const int r_in = __popcll(peers & lt);
+            // rank among the pixel's records of the window: the record's
+            // ordinal among its lane's records (the walk's) less the lane's
+            // records in earlier windows (a window is a run of walk order)
+            const int ob = __shfl(obase, owner, kWave);
             own[c] = owner;
-            rk[c] = act ? s_cnt[owner] + r_in : 0;
-            __builtin_amdgcn_wave_barrier();
-            if (act && r_in == 0) s_cnt[owner] += __popcll(peers);
-            __builtin_amdgcn_wave_barrier();
+            rk[c] = act ? (int)(m >> 24) - ob : 0;
+            if (act) atomicAdd(&s_cnt[owner], 1);
         }
+        __builtin_amdgcn_wave_barrier();
         // 2. pixel order
         const int cnt = s_cnt[lane];
+        obase += cnt;
         const int coff = wave_incl_scan(cnt) - cnt;
 #pragma unroll
         for (int c = 0; c < C; ++c) {
