@@ -1286,6 +1286,11 @@ __global__ __launch_bounds__(kWave) void stamp_kernel(const StepArgs a) {
     const int64_t seg = (int64_t)wid * a.rec_cap;
     const int nrec = (int)a.rec_count[wid];
     int obase = 0;   // the lane's records in earlier windows
+    // the wave's record segment: uniform bases, 32-bit byte offsets
+    const char* const rm = reinterpret_cast<const char*>(a.rec_meta + seg);
+    const char* const ri = reinterpret_cast<const char*>(a.rec_I + seg);
+    const char* const rp = reinterpret_cast<const char*>(a.rec_prev + seg);
+    const char* const rx = reinterpret_cast<const char*>(a.rec_X1 + seg);
     int emitted = 0, f64count = 0;
     int dg[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     constexpr int C = kStampWin / kWave;
@@ -1300,15 +1305,15 @@ __global__ __launch_bounds__(kWave) void stamp_kernel(const StepArgs a) {
             uint32_t m = 0u;
             Rec rc{0u, 0u, 0u, 0u, 0u};
             if (act) {
-                const int64_t at = seg + w0 + i;
-                m = a.rec_meta[at];
-                const double X1 = a.rec_X1[at];
+                const uint32_t at = (uint32_t)(w0 + i);
+                m = *reinterpret_cast<const uint32_t*>(rm + 4u * at);
+                const double X1 = *reinterpret_cast<const double*>(rx + 8u * at);
                 const bool f64 = (m & kRmF64) != 0;
                 const uint32_t n = f64 ? (uint32_t)__double2loint(X1) : ((m >> 16) & 0xFFu);
                 rc.meta = n | (((m >> 6) & 0xFFu) << 21) | ((m & kRmUp) ? (1u << 29) : 0u) |
                           (f64 ? kRecF64 : 0u);
-                rc.w0 = __float_as_uint(a.rec_I[at]);
-                rc.w1 = __float_as_uint(a.rec_prev[at]);
+                rc.w0 = *reinterpret_cast<const uint32_t*>(ri + 4u * at);
+                rc.w1 = *reinterpret_cast<const uint32_t*>(rp + 4u * at);
                 rc.w2 = (uint32_t)__double2loint(X1);
                 rc.w3 = (uint32_t)__double2hiint(X1);
             }
