@@ -14,10 +14,12 @@ constexpr int kStepWaves = 1;                // default waves per workgroup: a w
 constexpr int kStepLdsEntries = 2048;        // staging slots per wave: single streams
                                               // take 32 per frame of a launch, at least this
 constexpr int kStepMaxLdsEntries = 1 << 20;  // (4 B each, global memory)
-constexpr int kScanTile = 1024;              // per-wave counts per scan block
+constexpr int kScanTile = 1024;              // threads of a scan block
+constexpr int kScanItems = 4;                // per-wave counts per thread
+constexpr int kScanTileCounts = kScanTile * kScanItems;
 // status words of the scan for n waves: one per tile plus the tile counter
 constexpr int64_t scan_words(int64_t nwaves) {
-    return (nwaves + kScanTile - 1) / kScanTile + 1;
+    return (nwaves + kScanTileCounts - 1) / kScanTileCounts + 1;
 }
 constexpr int kMaxEnvs = 4096;
 constexpr int kChunk = 8;                     // frames prefetched per chunk
@@ -141,10 +143,10 @@ struct StepArgs {
 };
 
 // Exclusive scan of the per-wave event counts (wave order = pixel order) in
-// one pass: tiles of kScanTile counts taken in the order workgroups start
+// one pass: tiles of kScanTileCounts counts taken in the order workgroups start
 // (dynamic tile ids), each publishing its sum and then its inclusive prefix
 // in a status word that later tiles look back on (decoupled look-back).
-// status: [ceil(nwaves / kScanTile)] words (flag << 62 | value), then one
+// status: [ceil(nwaves / kScanTileCounts)] words (flag << 62 | value), then one
 // word whose low half counts the tiles handed out; all zero at launch (the
 // step kernel clears them).
 struct ScanArgs {

@@ -1576,12 +1576,14 @@ __attribute__((amdgpu_waves_per_eu(4))) void step_kernel(const StepArgs a) {
 
 // Exclusive scan of the per-wave counts in wave (= pixel) order, in one
 // pass (decoupled look-back, Merrill & Garland): each workgroup takes the
-// next tile id, scans its kScanTile counts with wave scans, publishes the
-// tile's sum (flag AGG) -- or, for tile 0, its inclusive prefix (flag INC)
-// -- then its first thread walks back over the predecessors' words, adding
-// sums until it meets an inclusive prefix, and publishes its own.  Tiles
-// are handed out in start order, so every predecessor is already running
-// and each wait ends; a bounded spin turns a lost wait into an error.
+// next tile id, scans its kScanTileCounts counts (kScanItems consecutive
+// ones per thread) with wave scans, publishes the tile's sum (flag AGG) --
+// or, for tile 0, its inclusive prefix (flag INC) -- then its first wave
+// looks back over 64 predecessors' words at a time, adding sums up to the
+// nearest inclusive prefix (or up to the nearest word not yet published,
+// on which it waits), and publishes its own.  Tiles are handed out in
+// start order, so every predecessor is already running and each wait
+// ends; a bounded spin turns a lost wait into an error.
 constexpr uint64_t kScanAgg = 1ull << 62, kScanInc = 2ull << 62;
 constexpr uint64_t kScanVal = (1ull << 62) - 1ull;
 
@@ -1590,15 +1592,21 @@ __global__ __launch_bounds__(kScanTile) void scan_kernel(const ScanArgs a) {
     __shared__ uint64_t s_w[kScanTile / kWave];
     __shared__ uint64_t s_excl;
     const int tid = threadIdx.x, lane = lane_id(), w = tid / kWave;
-    const int64_t ntiles = (a.nwaves + kScanTile - 1) / kScanTile;
+    const int64_t ntiles = (a.nwaves + kScanTileCounts - 1) / kScanTileCounts;
     uint32_t* ctr = reinterpret_cast<uint32_t*>(a.status + ntiles);
     if (tid == 0) s_tile = atomicAdd(ctr, 1u);
     __syncthreads();
     const int64_t tile = s_tile;
     if (tile >= ntiles) return;
-    const int64_t i = tile * kScanTile + tid;
-    const uint32_t c = i < a.nwaves ? a.seg_count[i] : 0u;
-    const uint64_t incl = wave_incl_scan_u64(c);
+    const int64_t i0 = tile * kScanTileCounts + (int64_t)tid * kScanItems;
+    uint32_t c[kScanItems];
+    uint64_t csum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        c[k] = i0 + k < a.nwaves ? a.seg_count[i0 + k] : 0u;
+        csum += c[k];
+    }
+    const uint64_t incl = wave_incl_scan_u64(csum);
     if (lane == kWave - 1) s_w[w] = incl;
     __syncthreads();
     uint64_t before_w = 0, total = 0;
@@ -1606,39 +1614,55 @@ __global__ __launch_bounds__(kScanTile) void scan_kernel(const ScanArgs a) {
         if (k < w) before_w += s_w[k];
         total += s_w[k];
     }
-    if (tid == 0) {
+    if (w == 0) {
         uint64_t* st = a.status + tile;
         uint64_t excl = 0;
         if (tile == 0) {
-            atomic_store_u64(st, kScanInc | total);
+            if (lane == 0) atomic_store_u64(st, kScanInc | total);
         } else {
-            atomic_store_u64(st, kScanAgg | total);
+            if (lane == 0) atomic_store_u64(st, kScanAgg | total);
             int64_t j = tile - 1;
             uint32_t spins = 0;
             for (;;) {
-                const uint64_t v = atomic_load_u64(a.status + j);
+                // lane l reads predecessor j - l (before tile 0: an
+                // inclusive zero, so every walk ends)
+                const int64_t jj = j - lane;
+                const uint64_t v = jj >= 0 ? atomic_load_u64(a.status + jj) : kScanInc;
                 const uint64_t flag = v & ~kScanVal;
-                if (flag == 0) {
-                    if (++spins > kSpinLimit) {
-                        atomicOr(&a.hdr->internal_err, kErrWait);
-                        break;
+                const uint64_t im = __ballot(flag == kScanInc);
+                const uint64_t zm = __ballot(flag == 0);
+                const int fi = im ? __builtin_ctzll(im) : kWave;   // nearest inclusive
+                const int fz = zm ? __builtin_ctzll(zm) : kWave;   // nearest unpublished
+                if (fz < fi) {
+                    // the sums before the unpublished word, then wait on it
+                    excl += (uint64_t)wave_sum64((int64_t)(lane < fz ? (v & kScanVal) : 0));
+                    j -= fz;
+                    if (fz == 0) {
+                        if (++spins > kSpinLimit) {
+                            if (lane == 0) atomicOr(&a.hdr->internal_err, kErrWait);
+                            break;
+                        }
+                        __builtin_amdgcn_s_sleep(1);
                     }
-                    __builtin_amdgcn_s_sleep(1);
                     continue;
                 }
-                excl += v & kScanVal;
-                if (flag == kScanInc) break;
-                --j;
+                excl += (uint64_t)wave_sum64((int64_t)(lane <= fi ? (v & kScanVal) : 0));
+                if (fi < kWave) break;
+                j -= kWave;   // 64 sums and no inclusive prefix yet
             }
-            atomic_store_u64(st, kScanInc | (excl + total));
+            if (lane == 0) atomic_store_u64(st, kScanInc | (excl + total));
         }
-        s_excl = excl;
+        if (lane == 0) s_excl = excl;
     }
     __syncthreads();
-    const uint64_t ex = s_excl + before_w + (incl - c);
-    if (i < a.nwaves) a.pref[i] = (uint32_t)(ex < 0xFFFFFFFFull ? ex : 0xFFFFFFFFull);
-    if (tile == ntiles - 1 && tid == kScanTile - 1) {
-        a.hdr->n_step = (int64_t)(ex + c);
+    uint64_t ex = s_excl + before_w + (incl - csum);
+#pragma unroll
+    for (int k = 0; k < kScanItems; ++k) {
+        if (i0 + k < a.nwaves) a.pref[i0 + k] = (uint32_t)(ex < 0xFFFFFFFFull ? ex : 0xFFFFFFFFull);
+        ex += c[k];
+    }
+    if (tile == ntiles - 1 && tid == 0) {
+        a.hdr->n_step = (int64_t)(s_excl + total);
         if (a.restart_queue) {
             a.hdr->head = 0;
             a.hdr->tail = 0;
@@ -2588,7 +2612,7 @@ hipError_t launch_stamp(const StepArgs& a, bool log_input, bool has_map,
 }
 
 hipError_t launch_scan(const ScanArgs& a, hipStream_t s) {
-    const int tiles = (a.nwaves + kScanTile - 1) / kScanTile;
+    const int tiles = (a.nwaves + kScanTileCounts - 1) / kScanTileCounts;
     hipLaunchKernelGGL(scan_kernel, dim3(tiles), dim3(kScanTile), 0, s, a);
     return hipGetLastError();
 }
