@@ -1710,23 +1710,23 @@ __device__ __forceinline__ int sort_tile(int64_t n, int64_t max_tiles) {
 
 // Copy every wave's segment to its pixel-order position and count the
 // radix digits of all passes; also clears the passes' look-back words.
-// Each 16-lane group of a wave walks its own segments (a segment of a one-
-// frame call holds a handful of entries), U slots per lane per round so
-// that the loads of a round are in flight together: 4 for launches of a
-// frame or a few, 16 for the long segments of many frames (fewer rounds,
-// each waiting once for its loads).
+// A group of G lanes walks its own segments, U slots per lane per round so
+// that the loads of a round are in flight together: for launches of a frame
+// or a few, 16-lane groups and 4 slots (a segment of a one-frame call holds
+// a handful of entries); for the long segments of many frames, a whole wave
+// per segment and 16 slots (a 125-frame segment of about 700 slots in one
+// round, and one wave per segment keeps enough waves in flight).
 // Every workgroup adds its digit counts to the global histogram with
-// atomics on the same few hundred words: short segments (launches of a few
-// frames) go to at most kGatherShortBlocks wide workgroups, very many
-// segments to at most kGatherWideBlocks, which keeps those flushes few;
-// long segments go to 256-thread workgroups, one segment per group, which
-// keep the chip full.
-constexpr int kGatherGroup = 16;
-constexpr int kGatherMaxBlocks = 2048;    // 256-thread workgroups
+// atomics on the same few hundred words, so workgroups are 1024 threads
+// wide: short segments (launches of a few frames) go to at most
+// kGatherShortBlocks of them, very many segments to at most
+// kGatherWideBlocks, and long segments to one workgroup per 16 segments.
+constexpr int kGatherGroup = 16;          // lanes per segment, short segments
+constexpr int kGatherMaxBlocks = 2048;    // segments / 16 above this: the wide path
 constexpr int kGatherWideBlocks = 512;    // 1024-thread workgroups
 constexpr int kGatherShortBlocks = 128;   // 1024-thread workgroups, short segments
 
-template <int kGatherThreads, int U>
+template <int kGatherThreads, int U, int G>
 __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const GatherArgs a) {
     __shared__ uint32_t s_h[kMaxPasses * kDigits];
     int64_t n;
@@ -1744,23 +1744,23 @@ __global__ __launch_bounds__(kGatherThreads) void gather_kernel(const GatherArgs
     for (int i = threadIdx.x; i < kMaxPasses * kDigits; i += blockDim.x) s_h[i] = 0u;
     __syncthreads();
     const int lane = lane_id();
-    const int gl = lane % kGatherGroup;
-    const uint64_t gmask = 0xFFFFull << (lane - gl);
+    const int gl = lane % G;
+    const uint64_t gmask = G == kWave ? ~0ull : ((1ull << (G % kWave)) - 1ull) << (lane - gl);
     const uint64_t lt = lanemask_lt() & gmask;
-    constexpr int kGroupsPerBlock = kGatherThreads / kGatherGroup;
+    constexpr int kGroupsPerBlock = kGatherThreads / G;
     const int64_t gstride = (int64_t)gridDim.x * kGroupsPerBlock;
-    for (int64_t wv = (int64_t)blockIdx.x * kGroupsPerBlock + threadIdx.x / kGatherGroup;
+    for (int64_t wv = (int64_t)blockIdx.x * kGroupsPerBlock + threadIdx.x / G;
          wv < a.nwaves; wv += gstride) {
         const int64_t sb = a.seg_base[wv];
         const uint32_t ns = a.seg_slots[wv];
         int64_t dst = a.pref[wv];
         const uint32_t key_hi = (uint32_t)a.wave_env[wv] << a.key_tbits;
         const uint32_t pix0 = (uint32_t)(wv * kWave);
-        for (uint32_t j0 = 0; j0 < ns; j0 += U * kGatherGroup) {
+        for (uint32_t j0 = 0; j0 < ns; j0 += U * G) {
             uint32_t e[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const uint32_t j = j0 + u * kGatherGroup + gl;
+                const uint32_t j = j0 + u * G + gl;
                 e[u] = j < ns ? a.skey[sb + j] : kEntryHole;
             }
 #pragma unroll
@@ -2624,10 +2624,12 @@ hipError_t launch_gather(const GatherArgs& a, hipStream_t s) {
         const int64_t wide = (a.nwaves + 4 * kGroups - 1) / (4 * kGroups);
         const int cap = want > kGatherMaxBlocks ? kGatherWideBlocks : kGatherShortBlocks;
         const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(cap, wide));
-        hipLaunchKernelGGL((gather_kernel<1024, 4>), dim3(blocks), dim3(1024), 0, s, a);
+        hipLaunchKernelGGL((gather_kernel<1024, 4, kGatherGroup>), dim3(blocks), dim3(1024), 0,
+                           s, a);
     } else {
-        const int blocks = (int)std::max<int64_t>(1, want);
-        hipLaunchKernelGGL((gather_kernel<256, 16>), dim3(blocks), dim3(256), 0, s, a);
+        const int64_t per_wave = (a.nwaves + 1024 / kWave - 1) / (1024 / kWave);
+        const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(kGatherMaxBlocks, per_wave));
+        hipLaunchKernelGGL((gather_kernel<1024, 16, kWave>), dim3(blocks), dim3(1024), 0, s, a);
     }
     return hipGetLastError();
 }
