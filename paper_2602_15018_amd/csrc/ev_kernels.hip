@@ -1296,24 +1296,37 @@ __global__ __launch_bounds__(kWave) void stamp_kernel(const StepArgs a) {
     constexpr int C = kStampWin / kWave;
     for (int w0 = 0; w0 < nrec; w0 += kStampWin) {
         const int wn = min(kStampWin, nrec - w0);
-        // 1. interpolation and ranks, walk order
+        // 1. interpolation and ranks, walk order; each group of 64 records
+        // is loaded while the one before is interpolated (past the window's
+        // end the last record is read again, always in the segment, and
+        // dropped)
         int own[C], rk[C];
+        uint32_t lm, li, lp;
+        double lx;
+        auto load_group = [&](int c) {
+            const uint32_t at = (uint32_t)(w0 + min(c * kWave + lane, wn - 1));
+            lm = *reinterpret_cast<const uint32_t*>(rm + 4u * at);
+            lx = *reinterpret_cast<const double*>(rx + 8u * at);
+            li = *reinterpret_cast<const uint32_t*>(ri + 4u * at);
+            lp = *reinterpret_cast<const uint32_t*>(rp + 4u * at);
+        };
+        load_group(0);
 #pragma unroll
         for (int c = 0; c < C; ++c) {
             const int i = c * kWave + lane;
             const bool act = i < wn;
-            uint32_t m = 0u;
+            const uint32_t m = act ? lm : 0u;
+            const double X1 = lx;
+            const uint32_t rI = li, rP = lp;
+            if (c + 1 < C && (c + 1) * kWave < wn) load_group(c + 1);
             Rec rc{0u, 0u, 0u, 0u, 0u};
             if (act) {
-                const uint32_t at = (uint32_t)(w0 + i);
-                m = *reinterpret_cast<const uint32_t*>(rm + 4u * at);
-                const double X1 = *reinterpret_cast<const double*>(rx + 8u * at);
                 const bool f64 = (m & kRmF64) != 0;
                 const uint32_t n = f64 ? (uint32_t)__double2loint(X1) : ((m >> 16) & 0xFFu);
                 rc.meta = n | (((m >> 6) & 0xFFu) << 21) | ((m & kRmUp) ? (1u << 29) : 0u) |
                           (f64 ? kRecF64 : 0u);
-                rc.w0 = *reinterpret_cast<const uint32_t*>(ri + 4u * at);
-                rc.w1 = *reinterpret_cast<const uint32_t*>(rp + 4u * at);
+                rc.w0 = rI;
+                rc.w1 = rP;
                 rc.w2 = (uint32_t)__double2loint(X1);
                 rc.w3 = (uint32_t)__double2hiint(X1);
             }
