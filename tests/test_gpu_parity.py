@@ -500,3 +500,27 @@ def test_invalid_arguments():
     with pytest.raises(NsimError):
         sim.step(fr[:1], [10])
     sim.close()
+
+
+@pytest.mark.parametrize("n_events", [(1 << 17) - 1, 1 << 17, (1 << 17) + 1, 6 * 6144 + 1])
+def test_sort_tile_size_boundary(n_events):
+    """One-frame launches with exactly n events: at most 2^17 take the radix
+    passes' 1024-item tiles, more take the 6144-item tiles (and the gather
+    clears the look-back words by the same rule).  Each chosen pixel moves
+    1.5 thresholds up or down (one crossing, far from any level), the others
+    not at all; the stream must equal the oracle's."""
+    _dev()
+    H, W = 384, 512
+    rng = np.random.default_rng(n_events)
+    I0 = rng.uniform(0.2, 0.8, size=(H, W))
+    pick = np.zeros(H * W, bool)
+    pick[rng.choice(H * W, size=n_events, replace=False)] = True
+    sgn = np.where(rng.random(H * W) < 0.5, 1.0, -1.0)
+    L0 = np.log(I0 + 1e-3).reshape(-1)
+    L1 = L0 + np.where(pick, 1.5 * 0.2 * sgn, 0.0)
+    fr = np.stack([I0.reshape(-1), np.exp(L1) - 1e-3]).reshape(2, H, W).astype(np.float32)
+    t = np.array([1000, 1500], np.int64)
+    rep, got, ref, st = check_parity(fr, t, W, c_pos=0.2, c_neg=0.2, refractory_us=0,
+                                     max_frames=1)
+    assert len(ref["events"].t) == n_events
+    assert rep["exact"], rep
