@@ -214,3 +214,29 @@ def test_split_two_crossings_at_level_boundaries(log_input):
     assert len(per) > 3 and per[2] > 2000 and per[3] > 1000, per
     fused, _ = gpu_run(fr, t, fused_step=True, **kw)
     assert exact_equal(got, fused)
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_full_launches_with_a_record_every_frame(fused):
+    """Launches of the most frames one takes (256), with pixels that cross
+    several levels in every frame: a record's frame index and the record's
+    ordinal among its pixel's records both reach 255, the top of their 8-bit
+    fields; refractory holes in the staging segments as well."""
+    _dev()
+    F, H, W = 1 + 2 * 256, 2, 70
+    rng = np.random.default_rng(77)
+    k = np.arange(F)[:, None, None]
+    n = np.arange(H * W).reshape(H, W)[None]
+    base = rng.uniform(0.2, 0.8, size=(1, H, W))
+    amp = np.where(n % 3 == 0, 0.45, rng.uniform(0.0, 0.1, size=(1, H, W)))
+    fr = np.exp(np.log(base) + amp * (2 * (k % 2) - 1)).astype(np.float32)
+    t = 3 + 500 * np.arange(F)
+    rep, got, ref, st = check_parity(fr, t, W, c_pos=0.2, c_neg=0.25, refractory_us=120,
+                                     chunks=[0, 1, 257, F], max_frames=256,
+                                     fused_step=fused)
+    ev = ref["events"]
+    # pixel (0, 0) alternates: events in every one of the 512 intervals
+    mine = (ev.x == 0) & (ev.y == 0)
+    assert np.array_equal(np.unique((ev.t[mine] - 3 + 499) // 500), np.arange(1, F))
+    assert rep["n_oracle"] > 50_000
+    assert rep["exact"], rep
