@@ -240,3 +240,29 @@ def test_full_launches_with_a_record_every_frame(fused):
     assert np.array_equal(np.unique((ev.t[mine] - 3 + 499) // 500), np.arange(1, F))
     assert rep["n_oracle"] > 50_000
     assert rep["exact"], rep
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_counts_around_the_fast_count_limit(fused):
+    """Log frames that move each pixel by m + 1/2 thresholds, m = 28..36, up
+    and then down again, every frame: runs of up to 31 crossings are walked
+    on the FP64 levels and carried in a record's 8-bit count, runs of 32 and
+    more are recounted by the FP64 replica and carried in the record's level
+    word.  Samples sit half a threshold from the nearest level."""
+    _dev()
+    H, W, F, C = 3, 21, 21, 0.1   # one launch of 21 frames: the split step
+    rng = np.random.default_rng(5)
+    B = rng.uniform(-2.0, 0.0, size=(H, W))
+    m = 28 + np.arange(H * W).reshape(H, W) % 9
+    k = np.arange(F)[:, None, None]
+    L = np.where(k % 2 == 1, B + (m + 0.5) * C, B - 0.5 * C)
+    L[0] = B
+    L = L.astype(np.float32)
+    t = 1000 * np.arange(F)
+    rep, got, ref, st = check_parity(L, t, W, c_pos=C, c_neg=C, input_is_log=True,
+                                     refractory_us=0, fused_step=fused)
+    ev = ref["events"]
+    cnt = np.bincount((ev.y.astype(np.int64) * W + ev.x) * F + (ev.t + 999) // 1000,
+                      minlength=H * W * F).reshape(H, W, F)
+    assert np.array_equal(cnt[:, :, 1:], np.broadcast_to(m[:, :, None], (H, W, F - 1)))
+    assert rep["exact"], rep
