@@ -110,7 +110,8 @@ int nsim_ev_create(const nsim_ev_config* cfg, void* stream, nsim_ev_t** out);
 
 /* Enqueue K frames (device, [K][height][width] float32, caller-owned, valid
  * until the stream has executed the step) with their timestamps (host,
- * int64 microseconds [K], strictly increasing across all calls, gaps < 2^25).
+ * int64 microseconds [K], strictly increasing across all calls, each gap at
+ * most 2^25 - 2; a larger gap returns NSIM_EINVAL with nothing enqueued).
  * The very first frame of the stream (or after nsim_ev_reset) only
  * initialises the pixel state.  Asynchronous: no host synchronisation.
  * Intensities must be finite with I + log_eps > 0.

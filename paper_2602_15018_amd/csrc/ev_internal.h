@@ -38,7 +38,10 @@ constexpr int kDigitBits = 8;
 constexpr int kDigits = 1 << kDigitBits;
 constexpr int kMaxPasses = 4;
 constexpr int32_t kTlastNone = -(1 << 30);   // no emitted event that matters
-constexpr int64_t kMaxLaunchSpan = (int64_t(1) << 25) - 2;  // us per launch
+// us per launch, and the largest frame gap: a staged entry packs the time
+// offset above 7 bits of lane and polarity, and an offset of 2^25 - 1 with
+// lane 63 and p = +1 would read as the hole marker 0xFFFFFFFF
+constexpr int64_t kMaxLaunchSpan = (int64_t(1) << 25) - 2;
 constexpr int32_t kErrWait = 1;              // Header::internal_err bits
 constexpr int32_t kErrRange = 2;
 

@@ -726,7 +726,7 @@ int check_times(nsim_ev* h, const int64_t* t_us, int32_t K) {
             if (t_us[i] <= prev_t)
                 return fail(h, NSIM_EINVAL, "timestamps must strictly increase");
             if (gap > nsim::kMaxLaunchSpan)
-                return fail(h, NSIM_EINVAL, "frame gap must be below 2^25 us");
+                return fail(h, NSIM_EINVAL, "frame gap must be at most 2^25 - 2 us");
         }
         prev_t = t_us[i];
     }
@@ -935,7 +935,7 @@ int do_step(nsim_ev* h, const float* frames, const int64_t* t_us, int32_t K) {
             if (h->max_frames == 0 && kl >= 8 && span > 65535) break;
             ++kl;
         }
-        if (kl == 0) kl = 1;  // a single frame always fits (gap < 2^25)
+        if (kl == 0) kl = 1;  // a single frame always fits (gap <= kMaxLaunchSpan)
         const float* fr = frames + (int64_t)k * P;
         if (h->fe) {
             NSIM_HIP(h, enqueue_frontend(h, fr, t_us + k, kl, T0, false));

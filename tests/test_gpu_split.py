@@ -266,3 +266,26 @@ def test_counts_around_the_fast_count_limit(fused):
                       minlength=H * W * F).reshape(H, W, F)
     assert np.array_equal(cnt[:, :, 1:], np.broadcast_to(m[:, :, None], (H, W, F - 1)))
     assert rep["exact"], rep
+
+
+@pytest.mark.parametrize("max_frames", [0, 256])
+def test_long_frame_gaps_and_launch_spans(max_frames):
+    """Frame gaps up to the largest allowed (2^25 - 2 us, the launch limit)
+    and launches whose time span comes within a few microseconds of it: time
+    offsets of 25 bits in the packed staging entries and a fourth radix pass;
+    with explicit launches of up to 256 frames, one of 16 frames (the split
+    step) spanning 25 bits.  A gap of 2^25 - 1 is refused."""
+    from paper_2602_15018_amd.ev import NsimError
+    dev = _dev()
+    H, W = 6, 40
+    gaps = ([2**25 - 2, 3, 2**23, 2**23, 2**23, 2**23, 1000, 2**24 + 7, 2**24 - 9, 2**24 - 2,
+             500, 17, 2**25 - 2] + [2**21 - 1000] * 16 + [2**22])
+    t = np.concatenate([[12345], 12345 + np.cumsum(gaps)]).astype(np.int64)
+    fr = scene.random_frames(8, len(t), H, W, jump=1.0)
+    rep, got, ref, st = check_parity(fr, t, W, c_pos=0.15, c_neg=0.15,
+                                     refractory_us=100, max_frames=max_frames)
+    assert rep["n_oracle"] > 500
+    assert rep["exact"], rep
+    assert st["sort_passes"] >= 6 * 4
+    with pytest.raises(NsimError):
+        gpu_run(fr[:2], np.array([0, 2**25 - 1]), max_frames=max_frames)
