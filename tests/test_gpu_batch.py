@@ -266,3 +266,37 @@ def test_batch_full_size_sampled():
         np.testing.assert_array_equal(gp, ref.p)
         n_checked += len(ref)
     assert n_checked > 1000
+
+
+def test_batch_many_envs_span_at_the_key_limit():
+    """200 environments, so 8 bits of environment index in the sort key:
+    calls that span the most the other 24 bits allow (2^24 - 2 us), four
+    radix passes per call, every environment against the oracle; a call
+    spanning 2^24 - 1 us is refused."""
+    from paper_2602_15018_amd.ev import EventBatch, NsimError
+    dev = _dev()
+    sizes = [(3 + i % 5, 1 + i % 3) for i in range(200)]
+    g = [2**23, 2**22, 2**24 - 2 - 2**23 - 2**22, 5, 2**24 - 7, 1000, 2**23, 3]
+    t = np.concatenate([[77], 77 + np.cumsum(g)]).astype(np.int64)
+    F = len(t)
+    envs, frames = _case(11, F, sizes)
+    for i, env in enumerate(envs):      # scalar thresholds kept in 0.1 .. 0.3
+        if "c_pos" in env:
+            env["c_pos"] = 0.1 + 0.002 * ((37 * i) % 100)
+            env["c_neg"] = 0.1 + 0.002 * ((53 * i) % 100)
+    got, tun, st = _run_batch(envs, frames, t, [0, 1, 4, 6, F], 50,
+                              autotune=False, use_graph=0)
+    n = 0
+    for e, env in enumerate(envs):
+        ref = _oracle_env(env, frames[e], t, 50)
+        _check_equal(got[e], ref)
+        n += len(ref)
+    assert n > 1000
+    assert st["sort_passes"] == 3 * 4
+    flat = torch.from_numpy(np.concatenate(
+        [f.reshape(F, -1) for f in frames], axis=1)).to(dev)
+    b = EventBatch(envs, capacity_events=1 << 16, autotune=False, use_graph=0)
+    b.step(flat[:1], t[:1])
+    with pytest.raises(NsimError):
+        b.step(flat[1:2], np.array([t[0] + 2**24 - 1], np.int64))
+    b.close()
