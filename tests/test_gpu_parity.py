@@ -249,8 +249,12 @@ def test_determinism_and_sortedness():
     assert is_sorted_tyx(a[0], a[1], a[2])
 
 
-@pytest.mark.parametrize("H,W", [(1, 1), (1, 300), (37, 29), (3, 257)])
+@pytest.mark.parametrize("H,W", [(1, 1), (1, 300), (37, 29), (3, 257), (2, 65535),
+                                 (65535, 2)])
 def test_ragged_sizes(H, W):
+    """Sizes that leave padding lanes, single rows and columns, and the
+    largest width and height (x and y up to 65534, the row of a pixel index
+    recovered from the reciprocal of a 65535-pixel width)."""
     fr = scene.random_frames(3, 9, H, W)
     t = 5 + 1000 * np.arange(9)
     rng = np.random.default_rng(3)
