@@ -119,10 +119,11 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2602_15018_amd", "csrc",
                           "ev_kernels.hip")
 
 
-def traffic_file(workload):
+def traffic_file(workload, kernel):
     short = {STREAMS["hd"]: "hd1280x720", STREAMS["vga"]: "vga640x480",
              STREAMS["dvs"]: "dvs240x180"}.get(workload, workload)
-    return os.path.join(ROOT, "profiles", "step_kernel_%s_traffic.json" % short)
+    name = {"walk_kernel + stamp_kernel": "walk_stamp_kernels"}.get(kernel, kernel)
+    return os.path.join(ROOT, "profiles", "%s_%s_traffic.json" % (name, short))
 
 
 def kernel_hash():
@@ -130,15 +131,15 @@ def kernel_hash():
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(workload, frames_per_launch):
-    """HBM bytes per step-kernel launch from the committed counter profile,
-    or None when it was taken on a different kernel source or launch
-    length."""
+def measured_traffic(workload, frames_per_launch, kernel):
+    """HBM bytes per launch of the reported kernel (or kernel pair) from the
+    committed counter profile, or None when it was taken on another kernel,
+    kernel source or launch length."""
     try:
-        rec = json.load(open(traffic_file(workload)))
+        rec = json.load(open(traffic_file(workload, kernel)))
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_hash") != kernel_hash():
+    if rec.get("kernel") != kernel or rec.get("kernel_hash") != kernel_hash():
         return None
     if abs(rec.get("frames_per_launch", -1) - frames_per_launch) > 1e-9:
         return None
@@ -701,7 +702,7 @@ def bench_stream(args, dev):
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": measured_traffic(name, fpl),
+            "traffic": measured_traffic(name, fpl, step_kernel),
             "avg_launch_ms": k1_ms,
             "alg_bytes_per_launch": alg_launch,
             "launches_per_step": launches_per_step,

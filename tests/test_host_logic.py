@@ -70,19 +70,24 @@ def _bench():
 
 def test_traffic_record_only_for_same_kernel_and_launch_length(tmp_path):
     bench = _bench()
-    rec = {"kernel_hash": bench.kernel_hash(), "bytes_per_launch": 123.0e6,
-           "frames_per_launch": 124.9}
+    split, fused = "walk_kernel + stamp_kernel", "step_kernel"
+    w = bench.STREAMS["hd"]
+    # each kernel (or pair) has its own record
+    assert bench.traffic_file(w, split).endswith("walk_stamp_kernels_hd1280x720_traffic.json")
+    assert bench.traffic_file(w, fused).endswith("step_kernel_hd1280x720_traffic.json")
+    rec = {"kernel": split, "kernel_hash": bench.kernel_hash(),
+           "bytes_per_launch": 123.0e6, "frames_per_launch": 124.9}
     f = tmp_path / "traffic.json"
     f.write_text(json.dumps(rec))
-    w = bench.STREAMS["hd"]
-    bench.traffic_file = lambda workload: str(f)
-    assert bench.measured_traffic(w, 124.9) == 123.0e6
-    assert bench.measured_traffic(w, 62.5) is None
+    bench.traffic_file = lambda workload, kernel: str(f)
+    assert bench.measured_traffic(w, 124.9, split) == 123.0e6
+    assert bench.measured_traffic(w, 124.9, fused) is None
+    assert bench.measured_traffic(w, 62.5, split) is None
     rec["kernel_hash"] = "0" * 16
     f.write_text(json.dumps(rec))
-    assert bench.measured_traffic(w, 124.9) is None
-    bench.traffic_file = lambda workload: str(tmp_path / "missing.json")
-    assert bench.measured_traffic(w, 124.9) is None
+    assert bench.measured_traffic(w, 124.9, split) is None
+    bench.traffic_file = lambda workload, kernel: str(tmp_path / "missing.json")
+    assert bench.measured_traffic(w, 124.9, split) is None
 
 
 def test_algorithmic_bytes_follow_the_per_unit_figures():
