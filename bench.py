@@ -70,7 +70,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--frames", type=int, default=0,
                     help="use only the first N frames (debug)")
-    ap.add_argument("--cpu-sample-frames", type=int, default=300,
+    ap.add_argument("--cpu-sample-frames", type=int, default=750,
                     help="frame intervals of the CPU oracle sample")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--max-frames-per-launch", type=int, default=0)
@@ -931,22 +931,22 @@ def bench_repr(args, dev):
         touched += int(torch.unique(ent[a:b]).numel())
     alg_upd = 13.0 * n + 32.0 * touched
     ach = alg_upd / t_upd / 1e9
-    # the oracle on one core over the first 100 ms of events
+    # the oracle on one core over the whole workload (well under the CPU
+    # time a sample would be cut to)
     evh = tuple(x.cpu().numpy() for x in ev)
-    m = bounds[min(10, len(bounds) - 1)]
-    sample = oracle.Events(evh[0][:m], evh[1][:m].view(np.uint16),
-                           evh[2][:m].view(np.uint16), evh[3][:m])
+    m = n
+    sample = oracle.Events(evh[0], evh[1].view(np.uint16), evh[2].view(np.uint16), evh[3])
     allowed = os.sched_getaffinity(0)
     os.sched_setaffinity(0, {min(allowed)})
     try:
         c0 = time.perf_counter()
         ots = oracle.TimeSurface(W, H, tau)
-        for i in range(min(10, len(batches))):
+        for i in range(len(batches)):
             a, b = batches[i]
             ots.update(oracle.Events(*(x[a:b] for x in (
                 evh[0], evh[1].view(np.uint16), evh[2].view(np.uint16), evh[3]))))
             ots.read(ends[i])
-        oracle.event_frames(sample, W, H, t0, window, 5)
+        oracle.event_frames(sample, W, H, t0, window, nf)
         c_el = time.perf_counter() - c0
     finally:
         os.sched_setaffinity(0, allowed)
@@ -978,9 +978,9 @@ def bench_repr(args, dev):
         "cpu_baseline": {
             "value": m / c_el / 1e9, "unit": "Gevents/s", "cores": 1,
             "kind": "oracle",
-            "sample": "first 100 ms of the stream's events (%d): 10 time-"
-                      "surface updates and readouts, 5 event frames, one "
-                      "pinned core" % m,
+            "sample": "the whole workload: %d events, %d time-surface "
+                      "updates and readouts, %d event frames, one pinned "
+                      "core" % (m, len(batches), nf),
             "seconds": c_el,
         },
     }
