@@ -990,7 +990,7 @@ def bench_repr(args, dev):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only; this build has no multi-GPU path "
+        print("bench.py runs on one GPU only; the library has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     import torch
