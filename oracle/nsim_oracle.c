@@ -2,7 +2,7 @@
  * nsim_oracle.c -- FP64 CPU oracle of DVS event generation.
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the plain, slow, single-threaded
- * definition against which the GPU path is judged.  Only the test suite, the
+ * definition against which the GPU path is checked.  Only the test suite, the
  * smoke check and the benchmark's CPU-baseline leg may load it; the product
  * path never links, calls or imports it, and it shares no code, header,
  * table or constant with the GPU library.
@@ -11,12 +11,11 @@
  * and the Fig. 3 caption): every pixel keeps a state recording the intensity
  * level of its last triggered event; a new intensity frame triggers events
  * wherever the log intensity has moved by more than a contrast threshold
- * from that level (the "contrast-threshold-based event generation model");
+ * from that level (an event model driven by contrast thresholds);
  * the pixel state is updated and the event stream (t, x, y, p) is output,
  * with t an integer in microseconds and p = +1 / -1 (Sec. 1, event tuple).
  *
- * The paper gives no equation for the model.  The readings taken here (all
- * listed in the design doc) are:
+ * The paper gives no equation for the model.  The readings taken here are:
  *   - L = ln(I + eps) in double precision (or L = I for log-intensity input);
  *   - the reference level lives on the lattice
  *       R = L_init + (n_up * C_pos - n_down * C_neg)

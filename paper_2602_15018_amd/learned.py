@@ -4,7 +4,7 @@ by the HIP U-Net, then through the HIP event generator's log-input entry.
 The paper's event simulation wants 1000+ FPS frames (Sec. 1, contribution on
 efficient high-fidelity event simulation); rendering only every eighth frame
 and predicting the seven in between is our addition.  The full-rate plain
-path is both its fallback and its judge: ``compare_streams`` reports the
+path is both its fallback and its reference: ``compare_streams`` reports the
 per-pixel, per-polarity event-count error of the learned stream against the
 full-rate stream of the same scene, and the timestamp error of the events
 the two streams share (matched per pixel in time order, same polarity,
